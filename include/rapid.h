@@ -1,0 +1,188 @@
+/* rapid.h -- C-ABI of the MI355X (gfx950) RAPID refinement library.
+ *
+ * The library segments an RGB image into superpixels with the coarse-to-fine
+ * topology-preserving refinement of RAPID (Sulimowicz & Ahmad, ICME 2017):
+ * the CTFTPS energy of Eq. (1), block moves of Eq. (3) restricted to
+ * boundary blocks (Eq. (2); Eq. (7) under a prediction gate), the size
+ * regularity of Sec. 3.1 as hard bounds, and the adaptive multi-level
+ * framework of Sec. 3.2 (statistics computed once and reused; Eq. (8) holds
+ * by construction because every sum is kept in fine-pixel units).
+ *
+ * Input: one HWC uint8 RGB image (or a batch) and a target superpixel count.
+ * Output: one int32 label per pixel in [0, gx*gy).
+ *
+ * Conventions
+ *  - Every pointer named *_dev is a device pointer (HIP memory on the
+ *    context's device) owned by the caller; it must stay valid until the
+ *    work queued on the context's stream completes.  The library never frees
+ *    caller memory.  Host pointers (params, report, config) are read or
+ *    written before the call returns.
+ *  - Calls are ordered on the context's stream.  Argument errors are
+ *    returned synchronously and nothing is queued.  rapid_segment,
+ *    rapid_segment_batch and rapid_refine_level synchronise the stream
+ *    before returning when a report is requested; otherwise they return
+ *    after queueing.  A device fault surfaces as RAPID_EDEVICE.
+ *  - On error the contents of output buffers are undefined.
+ *  - Identical inputs give identical outputs (the schedule is deterministic
+ *    and every statistic is an exact integer).
+ */
+#ifndef RAPID_H
+#define RAPID_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RAPID_ABI_VERSION 1
+#define RAPID_MAX_LEVELS 4
+#define RAPID_MAX_STAGES 8
+#define RAPID_MAX_DIM 8192
+
+typedef enum {
+    RAPID_OK = 0,
+    RAPID_EINVAL = -1,   /* bad argument: sizes, schedule, weights, NULL pointer */
+    RAPID_ENOMEM = -2,   /* device or host allocation failed                     */
+    RAPID_EDEVICE = -3,  /* a HIP call or kernel failed                           */
+    RAPID_ESTATE = -4,   /* state used out of order (level already refined ...)  */
+    RAPID_EGATE = -5     /* gate model unusable (non-finite weights)             */
+} rapid_status;
+
+typedef struct rapid_ctx rapid_ctx;       /* opaque, library-owned */
+typedef struct rapid_state rapid_state;   /* opaque, library-owned */
+
+#define RAPID_CFG_TIMING 1   /* record HIP events around every kernel launch */
+
+typedef struct {
+    int32_t abi_version;   /* RAPID_ABI_VERSION */
+    int32_t device;        /* HIP device ordinal */
+    void *hip_stream;      /* hipStream_t to queue on; NULL = the null stream */
+    int32_t flags;         /* RAPID_CFG_* bits */
+    int32_t reserved;
+} rapid_config;
+
+/* Kernel durations of the last segmentation call (context created with
+ * RAPID_CFG_TIMING), measured with HIP events on the context's stream. */
+typedef struct {
+    float block_sums_ms;   /* block-sum pyramid kernels            */
+    float refine_ms;       /* the refinement kernel (all stages)   */
+} rapid_timings;
+
+/* Method parameters, all integers (the paper gives no values for the
+ * weights lambda_pos, lambda_b, the size bounds or the schedule).
+ *  K          target superpixel count; the grid is gy = nearest integer to
+ *             sqrt(K H / W), gx = nearest integer to K / gy (ties to the
+ *             smaller).  K == 0: use gx, gy as given.
+ *  levels     coarse to fine; a level pixel is factor x factor fine pixels
+ *             and its stages are block sizes in level pixels.  The effective
+ *             block size b * factor must not increase and must divide the
+ *             previous one; at most 64.  The first effective size B0 is the
+ *             grid block: gx * B0 <= W and gy * B0 <= H.
+ *  gate_level first level refined under a gate (Algorithm RAPID applies
+ *             the prediction at the second level); -1: never.
+ *  frac_bits  F, fixed-point fraction bits of the means (0..4).
+ *  max_sweeps sweep cap per stage (>= 1).
+ *  min_size, max_size  hard size bounds in pixels (Sec. 3.1, Eq. (5)).
+ *  w_col, w_pos, w_bnd integer weights of colour, position and boundary
+ *             terms (Eq. (1)); rejected when the worst-case block energy
+ *             could leave the int64 range. */
+typedef struct {
+    int32_t K, gx, gy;
+    int32_t n_levels;
+    int32_t factor[RAPID_MAX_LEVELS];
+    int32_t n_stages[RAPID_MAX_LEVELS];
+    int32_t stages[RAPID_MAX_LEVELS][RAPID_MAX_STAGES];
+    int32_t gate_level;
+    int32_t frac_bits;
+    int32_t max_sweeps;
+    int32_t reserved;
+    int64_t min_size, max_size;
+    int64_t w_col, w_pos, w_bnd;
+} rapid_params;
+
+/* One image.  rgb_dev: HWC uint8, row_stride_bytes >= 3 W.  labels_dev:
+ * int32, label_stride (elements) >= W; receives one label per pixel. */
+typedef struct {
+    const uint8_t *rgb_dev;
+    int32_t W, H;
+    int64_t row_stride_bytes;
+    int32_t *labels_dev;
+    int64_t label_stride;
+} rapid_image;
+
+/* Per-stage counters (the complexity terms of Sec. 3.4: blocks visited from
+ * the boundary queue, moves). */
+typedef struct {
+    int32_t level, block, sweeps, converged;
+    int64_t active;      /* block visits summed over sweeps          */
+    int64_t proposals;   /* best move differs from the current label */
+    int64_t commits;     /* proposals admitted by the size filter     */
+    int64_t skip_min;    /* visits skipped: source would fall below min */
+    int64_t skip_topo;   /* visits skipped: not a simple point        */
+} rapid_stage_report;
+
+typedef struct {
+    int32_t n_stages;    /* entries filled in stage[] */
+    int32_t K;           /* superpixels gx * gy       */
+    rapid_stage_report stage[RAPID_MAX_LEVELS * RAPID_MAX_STAGES];
+} rapid_report;
+
+/* Create a context on cfg->device: builds the 256-entry simple-point table
+ * of the topology term (Eq. (1), E_topo) and uploads it.  *out receives the
+ * context; rapid_destroy releases it. */
+rapid_status rapid_init(const rapid_config *cfg, rapid_ctx **out);
+void rapid_destroy(rapid_ctx *ctx);   /* NULL-safe; waits for queued work */
+
+/* Segment one image (Algorithm RAPID, all levels).  gate_dev: NULL for the
+ * plain method, else gx*gy bytes (non-zero = superpixel marked by the
+ * prediction of Eq. (6)) applied from params->gate_level on (Eq. (7)).
+ * report may be NULL. */
+rapid_status rapid_segment(rapid_ctx *ctx, const rapid_image *img, const rapid_params *params,
+                           const uint8_t *gate_dev, rapid_report *report);
+
+/* Segment n images in one launch, every image with the same params (the
+ * grid is derived per image from K).  reports: NULL or n entries. */
+rapid_status rapid_segment_batch(rapid_ctx *ctx, const rapid_image *imgs, int32_t n,
+                                 const rapid_params *params, rapid_report *reports);
+
+/* Level-by-level use (the outer loop of Algorithm RAPID).  state_create
+ * computes the grid labels and the statistics once (first level, Sec. 3.2);
+ * each rapid_refine_level call runs every stage of one level, in order
+ * 0, 1, ..., reusing the statistics; gate_dev as in rapid_segment but for
+ * this level only.  rapid_state_export writes the current labels expanded to
+ * pixels (labels_dev, W*H int32, row-major) and the statistics (stats_dev,
+ * gx*gy*6 int64: n, colour sums R G B, coordinate sums x y); either may be
+ * NULL. */
+rapid_status rapid_state_create(rapid_ctx *ctx, const rapid_image *img, const rapid_params *params,
+                                rapid_state **out);
+rapid_status rapid_refine_level(rapid_ctx *ctx, rapid_state *st, int32_t level,
+                                const uint8_t *gate_dev, rapid_report *report);
+rapid_status rapid_state_export(rapid_ctx *ctx, rapid_state *st, int32_t *labels_dev,
+                                int64_t *stats_dev);
+void rapid_state_destroy(rapid_state *st);   /* NULL-safe */
+
+/* Waits for the last segmentation call and returns its kernel durations;
+ * RAPID_ESTATE when the context does not time or nothing ran yet. */
+rapid_status rapid_last_timings(rapid_ctx *ctx, rapid_timings *out);
+
+/* Grid of a target count (see rapid_params.K).  Host only, no device. */
+rapid_status rapid_grid(int32_t W, int32_t H, int32_t K, int32_t *gx, int32_t *gy);
+
+/* The 256-entry simple-point table of the topology term (E_topo of
+ * Eq. (1)) that the kernels use, as 8 words: bit m of word m/32 is set when
+ * a block whose 3x3 ring has same-label mask m (bit r = neighbour r in
+ * row-major order, centre skipped; out-of-image is "other") may leave its
+ * label: its same-label ring blocks 4-connected to an edge neighbour form one
+ * component and the other ring blocks one 8-connected component.  Host only. */
+rapid_status rapid_simple_lut(uint32_t out[8]);
+
+/* Validate params for a W x H image exactly as rapid_segment would;
+ * *K_out (nullable) receives gx * gy.  Host only, no device. */
+rapid_status rapid_check_params(int32_t W, int32_t H, const rapid_params *params, int32_t *K_out);
+
+const char *rapid_status_str(rapid_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,623 @@
+// rapid_host.cpp -- host side of the C-ABI: validation, schedule, scratch
+// planning, launches.  Every step of the segmentation runs in the kernels of
+// rapid_kernels.hip; this file only marshals.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "rapid_internal.h"
+
+using namespace rapid;
+
+struct rapid_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint32_t *lut_dev = nullptr;
+    size_t lds_limit = 0;
+    int threads = 512;
+    // scratch pool for rapid_segment / rapid_segment_batch
+    char *pool = nullptr;
+    size_t pool_size = 0;
+    Job *jobs_dev = nullptr;
+    size_t jobs_cap = 0;
+    Job *jobs_pinned = nullptr;
+    hipEvent_t jobs_copied = nullptr;
+    bool timing = false;
+    bool timed = false;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    std::mutex mu;
+};
+
+struct rapid_state {
+    rapid_ctx *ctx = nullptr;
+    Job job{};
+    Job *job_dev = nullptr;
+    char *mem = nullptr;
+    Sched sc{};
+    int32_t level_first[RAPID_MAX_LEVELS + 1] = {};
+    int32_t next_level = 0;
+    int32_t map_stage = 0;   // stage whose block size the current label map uses
+    int32_t W = 0, H = 0;
+};
+
+namespace {
+
+// ------------------------------------------------------------ topology LUT
+
+// (4,8) simple-point table of the topology term: bit m is set when a block
+// whose 3x3 ring has same-label mask m may leave its label.  Ring bit r is the
+// neighbour (dx, dy) in row-major order with the centre skipped.  Built with
+// union-find over the ring cells.
+struct UF {
+    int p[8];
+    UF() { for (int i = 0; i < 8; i++) p[i] = i; }
+    int f(int x) { while (p[x] != x) x = p[x] = p[p[x]]; return x; }
+    void u(int a, int b) { p[f(a)] = f(b); }
+};
+
+void build_simple_lut(uint32_t lut[8])
+{
+    static const int DX[8] = {-1, 0, 1, -1, 1, -1, 0, 1};
+    static const int DY[8] = {-1, -1, -1, 0, 0, 1, 1, 1};
+    std::memset(lut, 0, 8 * sizeof(uint32_t));
+    for (int m = 0; m < 256; m++) {
+        UF fg, bg;
+        for (int a = 0; a < 8; a++)
+            for (int b = a + 1; b < 8; b++) {
+                int ddx = std::abs(DX[a] - DX[b]), ddy = std::abs(DY[a] - DY[b]);
+                bool in_a = (m >> a) & 1, in_b = (m >> b) & 1;
+                if (in_a && in_b && ddx + ddy == 1) fg.u(a, b);           // 4-adjacent
+                if (!in_a && !in_b && ddx <= 1 && ddy <= 1) bg.u(a, b);   // 8-adjacent
+            }
+        // foreground components 4-adjacent to the centre
+        int roots_fg[8], nfg = 0, nbg = 0, roots_bg[8];
+        for (int a = 0; a < 8; a++) {
+            bool in_a = (m >> a) & 1;
+            if (in_a && (DX[a] == 0 || DY[a] == 0)) {
+                int r = fg.f(a);
+                bool seen = false;
+                for (int q = 0; q < nfg; q++) seen |= roots_fg[q] == r;
+                if (!seen) roots_fg[nfg++] = r;
+            }
+            if (!in_a) {
+                int r = bg.f(a);
+                bool seen = false;
+                for (int q = 0; q < nbg; q++) seen |= roots_bg[q] == r;
+                if (!seen) roots_bg[nbg++] = r;
+            }
+        }
+        if (nfg == 1 && nbg == 1) lut[m >> 5] |= 1u << (m & 31);
+    }
+}
+
+// ------------------------------------------------------------------ grid
+
+rapid_status grid_of(int32_t W, int32_t H, int32_t K, int32_t *gx, int32_t *gy)
+{
+    if (W < 1 || H < 1 || K < 1) return RAPID_EINVAL;
+    // gy: nearest integer to sqrt(K H / W), ties down
+    int64_t lo = 0, hi = (int64_t)K * H + 1;
+    while (lo + 1 < hi) {   // largest g with g^2 W <= K H
+        int64_t mid = (lo + hi) / 2;
+        if ((__int128)mid * mid * W <= (__int128)K * H) lo = mid; else hi = mid;
+    }
+    int64_t g = lo;
+    if ((__int128)4 * K * H > (__int128)(2 * g + 1) * (2 * g + 1) * W) g++;
+    if (g < 1) g = 1;
+    int64_t q = K / g;
+    if (2 * (K % g) > g) q++;
+    if (q < 1) q = 1;
+    *gy = (int32_t)g;
+    *gx = (int32_t)q;
+    return RAPID_OK;
+}
+
+// --------------------------------------------------------------- validate
+
+rapid_status make_sched(const rapid_params *p, Sched *sc, int32_t level_first[RAPID_MAX_LEVELS + 1])
+{
+    if (!p) return RAPID_EINVAL;
+    if (p->n_levels < 1 || p->n_levels > RAPID_MAX_LEVELS) return RAPID_EINVAL;
+    std::memset(sc, 0, sizeof *sc);
+    int n = 0, prev = 0;
+    for (int l = 0; l < p->n_levels; l++) {
+        if (p->factor[l] < 1 || p->n_stages[l] < 1 || p->n_stages[l] > RAPID_MAX_STAGES)
+            return RAPID_EINVAL;
+        if (level_first) level_first[l] = n;
+        for (int s = 0; s < p->n_stages[l]; s++) {
+            int64_t B = (int64_t)p->stages[l][s] * p->factor[l];
+            if (B < 1 || B > 64) return RAPID_EINVAL;
+            if (prev && (B > prev || prev % B)) return RAPID_EINVAL;
+            prev = (int)B;
+            sc->B[n] = (int32_t)B;
+            sc->level[n] = l;
+            n++;
+        }
+    }
+    if (level_first) level_first[p->n_levels] = n;
+    sc->n_stages = n;
+    sc->gate_stage = n;
+    if (p->gate_level >= 0 && p->gate_level < p->n_levels) {
+        int first = 0;
+        for (int l = 0; l < p->gate_level; l++) first += p->n_stages[l];
+        sc->gate_stage = first;
+    }
+    if (p->frac_bits < 0 || p->frac_bits > 4 || p->max_sweeps < 1) return RAPID_EINVAL;
+    if (p->w_col < 0 || p->w_pos < 0 || p->w_bnd < 0 || p->min_size < 0 || p->max_size < 1)
+        return RAPID_EINVAL;
+    sc->F = p->frac_bits;
+    sc->max_sweeps = p->max_sweeps;
+    sc->min_size = p->min_size;
+    sc->max_size = p->max_size;
+    sc->w_col = p->w_col;
+    sc->w_pos = p->w_pos;
+    sc->w_bnd = p->w_bnd;
+    return RAPID_OK;
+}
+
+// Worst-case |E'| of a block must stay below 2^62 so that the int64 block
+// energy of the kernels is exact.
+bool energy_fits(const Sched &sc, int32_t W, int32_t H)
+{
+    typedef __int128 i128;
+    const i128 lim = (i128)1 << 62;
+    i128 Bm = sc.B[0];
+    i128 m = Bm * Bm;
+    i128 cmax = (i128)255 << sc.F;
+    i128 dim = std::max(W, H);
+    i128 mumax = (dim - 1) << sc.F;
+    i128 e_col = m * 3 * cmax * cmax + ((i128)2 << sc.F) * 3 * cmax * m * 255;
+    i128 e_pos = m * 2 * mumax * mumax + ((i128)2 << sc.F) * 2 * mumax * m * (dim - 1);
+    i128 e_bnd = (4 * Bm) << (2 * sc.F);
+    if (sc.w_col > 0 && e_col > lim / sc.w_col) return false;
+    if (sc.w_pos > 0 && e_pos > lim / sc.w_pos) return false;
+    if (sc.w_bnd > 0 && e_bnd > lim / sc.w_bnd) return false;
+    i128 tot = sc.w_col * e_col + sc.w_pos * e_pos + sc.w_bnd * e_bnd;
+    return tot < lim;
+}
+
+rapid_status check_image(const rapid_image *img, bool need_labels)
+{
+    if (!img || !img->rgb_dev) return RAPID_EINVAL;
+    if (img->W < 1 || img->H < 1 || img->W > RAPID_MAX_DIM || img->H > RAPID_MAX_DIM) return RAPID_EINVAL;
+    if (img->row_stride_bytes < 3 * (int64_t)img->W) return RAPID_EINVAL;
+    if (need_labels && (!img->labels_dev || img->label_stride < img->W)) return RAPID_EINVAL;
+    return RAPID_OK;
+}
+
+rapid_status image_grid(const rapid_image *img, const rapid_params *p, const Sched &sc,
+                        int32_t *gx, int32_t *gy)
+{
+    rapid_status r;
+    if (p->K > 0) {
+        if ((r = grid_of(img->W, img->H, p->K, gx, gy))) return r;
+    } else {
+        *gx = p->gx;
+        *gy = p->gy;
+    }
+    if (*gx < 1 || *gy < 1) return RAPID_EINVAL;
+    if ((int64_t)*gx * sc.B[0] > img->W || (int64_t)*gy * sc.B[0] > img->H) return RAPID_EINVAL;
+    if (!energy_fits(sc, img->W, img->H)) return RAPID_EINVAL;
+    return RAPID_OK;
+}
+
+// ------------------------------------------------------- scratch planning
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t bytes = 0;
+    size_t off_lab[2], off_sums[MAXST], off_lists, off_props, off_changed, off_stamp;
+    size_t off_stats, off_means, off_flow, off_touched, off_rep;
+    int64_t capc = 0;
+};
+
+Layout plan(int32_t W, int32_t H, int32_t K, const Sched &sc)
+{
+    Layout L;
+    size_t o = 0;
+    auto take = [&](size_t n) { size_t r = o; o = align256(o + n); return r; };
+    int Bmin = sc.B[sc.n_stages - 1];
+    int64_t nbxF = (W + Bmin - 1) / Bmin, nbyF = (H + Bmin - 1) / Bmin;
+    int64_t nbF = nbxF * nbyF;
+    L.capc = ((nbxF + 2) / 3) * ((nbyF + 2) / 3);
+    L.off_lab[0] = take(4 * nbF);
+    L.off_lab[1] = take(4 * nbF);
+    for (int s = 0; s < MAXST; s++) {
+        L.off_sums[s] = (size_t)-1;
+        if (s < sc.n_stages && sc.B[s] >= 2) {
+            int64_t nb = (int64_t)((W + sc.B[s] - 1) / sc.B[s]) * ((H + sc.B[s] - 1) / sc.B[s]);
+            L.off_sums[s] = take(8 * nb);
+        }
+    }
+    L.off_lists = take(4 * 9 * L.capc);
+    L.off_props = take(4 * 3 * L.capc);
+    L.off_changed = take(4 * nbF);
+    L.off_stamp = take(4 * nbF);
+    L.off_stats = take(8 * 6 * (size_t)K);
+    L.off_means = take(4 * MN_STRIDE * (size_t)K);
+    L.off_flow = take(4 * 2 * (size_t)K);
+    L.off_touched = take(4 * 2 * (size_t)K);
+    L.off_rep = take(sizeof(rapid_stage_report) * MAXST);
+    L.bytes = o;
+    return L;
+}
+
+void fill_job(Job &J, char *base, const Layout &L, const rapid_image *img, int32_t gx, int32_t gy,
+              const uint8_t *gate)
+{
+    std::memset(&J, 0, sizeof J);
+    J.rgb = img->rgb_dev;
+    J.rgb_stride = img->row_stride_bytes;
+    J.W = img->W;
+    J.H = img->H;
+    J.gx = gx;
+    J.gy = gy;
+    J.K = gx * gy;
+    J.out = img->labels_dev;
+    J.out_stride = img->label_stride;
+    J.lab[0] = reinterpret_cast<int32_t *>(base + L.off_lab[0]);
+    J.lab[1] = reinterpret_cast<int32_t *>(base + L.off_lab[1]);
+    for (int s = 0; s < MAXST; s++)
+        J.sums[s] = L.off_sums[s] == (size_t)-1 ? nullptr : reinterpret_cast<uint64_t *>(base + L.off_sums[s]);
+    J.lists = reinterpret_cast<int32_t *>(base + L.off_lists);
+    J.capc = L.capc;
+    J.props = reinterpret_cast<int32_t *>(base + L.off_props);
+    J.changed = reinterpret_cast<int32_t *>(base + L.off_changed);
+    J.stamp = reinterpret_cast<int32_t *>(base + L.off_stamp);
+    J.stats = reinterpret_cast<int64_t *>(base + L.off_stats);
+    J.means = reinterpret_cast<int32_t *>(base + L.off_means);
+    J.flow = reinterpret_cast<int32_t *>(base + L.off_flow);
+    J.touched = reinterpret_cast<int32_t *>(base + L.off_touched);
+    J.rep = reinterpret_cast<rapid_stage_report *>(base + L.off_rep);
+    J.gate = gate;
+}
+
+rapid_status dev_err(hipError_t e) { return e == hipSuccess ? RAPID_OK : RAPID_EDEVICE; }
+
+#define HIPCHK(x)                                   \
+    do {                                            \
+        hipError_t e_ = (x);                        \
+        if (e_ != hipSuccess) return RAPID_EDEVICE; \
+    } while (0)
+
+bool use_lds(const rapid_ctx *ctx, int32_t Kmax, size_t *bytes)
+{
+    size_t b = (size_t)Kmax * LDS_PER_SP;
+    *bytes = b;
+    return b <= ctx->lds_limit;
+}
+
+rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched &sc, int s_begin,
+                      int s_end, int flags, int32_t Kmax, int64_t max_nb[MAXST])
+{
+    size_t n = jobs.size();
+    if (n > ctx->jobs_cap) {
+        if (ctx->jobs_dev) {
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            HIPCHK(hipFree(ctx->jobs_dev));
+            HIPCHK(hipHostFree(ctx->jobs_pinned));
+            ctx->jobs_dev = nullptr;
+            ctx->jobs_pinned = nullptr;
+            ctx->jobs_cap = 0;
+        }
+        size_t cap = std::max<size_t>(n, 64);
+        if (hipMalloc(&ctx->jobs_dev, cap * sizeof(Job)) != hipSuccess) return RAPID_ENOMEM;
+        if (hipHostMalloc(&ctx->jobs_pinned, cap * sizeof(Job)) != hipSuccess) return RAPID_ENOMEM;
+        ctx->jobs_cap = cap;
+    }
+    // the previous upload from the staging buffer must have completed
+    HIPCHK(hipEventSynchronize(ctx->jobs_copied));
+    std::memcpy(ctx->jobs_pinned, jobs.data(), n * sizeof(Job));
+    HIPCHK(hipMemcpyAsync(ctx->jobs_dev, ctx->jobs_pinned, n * sizeof(Job), hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIPCHK(hipEventRecord(ctx->jobs_copied, ctx->stream));
+    if (ctx->timing) HIPCHK(hipEventRecord(ctx->ev[0], ctx->stream));
+    if (flags & FLAG_INIT) {
+        for (int s = 0; s < sc.n_stages; s++)
+            if (sc.B[s] >= 2)
+                HIPCHK(launch_block_sums(ctx->jobs_dev, (int)n, s, sc.B[s], max_nb[s], ctx->stream));
+    }
+    size_t lds_bytes = 0;
+    bool lds = use_lds(ctx, Kmax, &lds_bytes);
+    if (ctx->timing) HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
+    HIPCHK(launch_refine(ctx->jobs_dev, (int)n, sc, s_begin, s_end, flags, ctx->lut_dev, lds,
+                         lds ? lds_bytes : 0, ctx->threads, ctx->stream));
+    if (ctx->timing) {
+        HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
+        ctx->timed = true;
+    }
+    return RAPID_OK;
+}
+
+rapid_status fetch_reports(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched &sc, int s_begin,
+                           int s_end, rapid_report *reports)
+{
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (size_t j = 0; j < jobs.size(); j++) {
+        rapid_report &R = reports[j];
+        std::memset(&R, 0, sizeof R);
+        R.K = jobs[j].K;
+        R.n_stages = s_end - s_begin;
+        if (s_end > s_begin)
+            HIPCHK(hipMemcpy(R.stage, jobs[j].rep + s_begin, sizeof(rapid_stage_report) * (s_end - s_begin),
+                             hipMemcpyDeviceToHost));
+    }
+    (void)sc;
+    return RAPID_OK;
+}
+
+}  // namespace
+
+// ================================================================= C-ABI
+
+extern "C" {
+
+const char *rapid_status_str(rapid_status s)
+{
+    switch (s) {
+    case RAPID_OK: return "ok";
+    case RAPID_EINVAL: return "invalid argument";
+    case RAPID_ENOMEM: return "out of memory";
+    case RAPID_EDEVICE: return "device error";
+    case RAPID_ESTATE: return "state used out of order";
+    case RAPID_EGATE: return "gate model unusable";
+    }
+    return "unknown status";
+}
+
+rapid_status rapid_grid(int32_t W, int32_t H, int32_t K, int32_t *gx, int32_t *gy)
+{
+    if (!gx || !gy) return RAPID_EINVAL;
+    return grid_of(W, H, K, gx, gy);
+}
+
+// Host-only helpers (no device needed): the topology table and the
+// parameter check, exposed for tests of the host logic.
+rapid_status rapid_simple_lut(uint32_t out[8])
+{
+    if (!out) return RAPID_EINVAL;
+    build_simple_lut(out);
+    return RAPID_OK;
+}
+
+rapid_status rapid_check_params(int32_t W, int32_t H, const rapid_params *params, int32_t *K_out)
+{
+    Sched sc;
+    rapid_status r = make_sched(params, &sc, nullptr);
+    if (r) return r;
+    rapid_image img{};
+    img.rgb_dev = reinterpret_cast<const uint8_t *>(1);
+    img.W = W;
+    img.H = H;
+    img.row_stride_bytes = 3 * (int64_t)W;
+    if ((r = check_image(&img, false))) return r;
+    int32_t gx, gy;
+    if ((r = image_grid(&img, params, sc, &gx, &gy))) return r;
+    if (K_out) *K_out = gx * gy;
+    return RAPID_OK;
+}
+
+rapid_status rapid_init(const rapid_config *cfg, rapid_ctx **out)
+{
+    if (!cfg || !out || cfg->abi_version != RAPID_ABI_VERSION) return RAPID_EINVAL;
+    rapid_ctx *ctx = new (std::nothrow) rapid_ctx();
+    if (!ctx) return RAPID_ENOMEM;
+    ctx->device = cfg->device;
+    ctx->stream = reinterpret_cast<hipStream_t>(cfg->hip_stream);
+    if (hipSetDevice(ctx->device) != hipSuccess) { delete ctx; return RAPID_EDEVICE; }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, ctx->device) != hipSuccess) { delete ctx; return RAPID_EDEVICE; }
+    // leave room for the kernel's static LDS
+    size_t lim = prop.sharedMemPerBlock;
+    ctx->lds_limit = lim > 1024 ? lim - 1024 : 0;
+    if (const char *t = std::getenv("RAPID_THREADS")) {
+        int v = std::atoi(t);
+        if (v >= 64 && v <= 1024 && v % 64 == 0) ctx->threads = v;
+    }
+    ctx->timing = (cfg->flags & RAPID_CFG_TIMING) != 0;
+    if (ctx->timing)
+        for (int i = 0; i < 3; i++)
+            if (hipEventCreate(&ctx->ev[i]) != hipSuccess) { delete ctx; return RAPID_EDEVICE; }
+    uint32_t lut[8];
+    build_simple_lut(lut);
+    if (hipMalloc(&ctx->lut_dev, sizeof lut) != hipSuccess) { delete ctx; return RAPID_ENOMEM; }
+    if (hipMemcpy(ctx->lut_dev, lut, sizeof lut, hipMemcpyHostToDevice) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->jobs_copied, hipEventDisableTiming) != hipSuccess) {
+        (void)hipFree(ctx->lut_dev);
+        delete ctx;
+        return RAPID_EDEVICE;
+    }
+    *out = ctx;
+    return RAPID_OK;
+}
+
+void rapid_destroy(rapid_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(ctx->lut_dev);
+    (void)hipFree(ctx->pool);
+    (void)hipFree(ctx->jobs_dev);
+    if (ctx->jobs_pinned) (void)hipHostFree(ctx->jobs_pinned);
+    if (ctx->jobs_copied) (void)hipEventDestroy(ctx->jobs_copied);
+    for (int i = 0; i < 3; i++)
+        if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+    delete ctx;
+}
+
+rapid_status rapid_last_timings(rapid_ctx *ctx, rapid_timings *out)
+{
+    if (!ctx || !out) return RAPID_EINVAL;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (!ctx->timing || !ctx->timed) return RAPID_ESTATE;
+    HIPCHK(hipEventSynchronize(ctx->ev[2]));
+    HIPCHK(hipEventElapsedTime(&out->block_sums_ms, ctx->ev[0], ctx->ev[1]));
+    HIPCHK(hipEventElapsedTime(&out->refine_ms, ctx->ev[1], ctx->ev[2]));
+    return RAPID_OK;
+}
+
+rapid_status rapid_segment_batch(rapid_ctx *ctx, const rapid_image *imgs, int32_t n,
+                                 const rapid_params *params, rapid_report *reports);
+
+static rapid_status segment_impl(rapid_ctx *ctx, const rapid_image *imgs, int32_t n,
+                                 const rapid_params *params, const uint8_t *gate_dev,
+                                 rapid_report *reports)
+{
+    if (!ctx || !imgs || n < 1 || !params) return RAPID_EINVAL;
+    Sched sc;
+    rapid_status r = make_sched(params, &sc, nullptr);
+    if (r) return r;
+    if (!gate_dev) sc.gate_stage = sc.n_stages;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return RAPID_EDEVICE;
+    std::vector<Layout> lay(n);
+    std::vector<int32_t> gxs(n), gys(n);
+    size_t total = 0;
+    int32_t Kmax = 0;
+    int64_t max_nb[MAXST] = {};
+    for (int i = 0; i < n; i++) {
+        if ((r = check_image(&imgs[i], true))) return r;
+        if ((r = image_grid(&imgs[i], params, sc, &gxs[i], &gys[i]))) return r;
+        lay[i] = plan(imgs[i].W, imgs[i].H, gxs[i] * gys[i], sc);
+        total += lay[i].bytes;
+        Kmax = std::max(Kmax, gxs[i] * gys[i]);
+        for (int s = 0; s < sc.n_stages; s++) {
+            int64_t nb = (int64_t)((imgs[i].W + sc.B[s] - 1) / sc.B[s]) * ((imgs[i].H + sc.B[s] - 1) / sc.B[s]);
+            max_nb[s] = std::max(max_nb[s], nb);
+        }
+    }
+    if (total > ctx->pool_size) {
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        if (ctx->pool) HIPCHK(hipFree(ctx->pool));
+        ctx->pool = nullptr;
+        ctx->pool_size = 0;
+        if (hipMalloc(&ctx->pool, total) != hipSuccess) return RAPID_ENOMEM;
+        ctx->pool_size = total;
+    }
+    std::vector<Job> jobs(n);
+    size_t off = 0;
+    for (int i = 0; i < n; i++) {
+        fill_job(jobs[i], ctx->pool + off, lay[i], &imgs[i], gxs[i], gys[i], gate_dev);
+        off += lay[i].bytes;
+    }
+    if ((r = run_jobs(ctx, jobs, sc, 0, sc.n_stages, FLAG_INIT | FLAG_OUT, Kmax, max_nb))) return r;
+    if (reports) return fetch_reports(ctx, jobs, sc, 0, sc.n_stages, reports);
+    return RAPID_OK;
+}
+
+rapid_status rapid_segment(rapid_ctx *ctx, const rapid_image *img, const rapid_params *params,
+                           const uint8_t *gate_dev, rapid_report *report)
+{
+    return segment_impl(ctx, img, 1, params, gate_dev, report);
+}
+
+rapid_status rapid_segment_batch(rapid_ctx *ctx, const rapid_image *imgs, int32_t n,
+                                 const rapid_params *params, rapid_report *reports)
+{
+    return segment_impl(ctx, imgs, n, params, nullptr, reports);
+}
+
+rapid_status rapid_state_create(rapid_ctx *ctx, const rapid_image *img, const rapid_params *params,
+                                rapid_state **out)
+{
+    if (!ctx || !out) return RAPID_EINVAL;
+    rapid_status r;
+    if ((r = check_image(img, false))) return r;
+    rapid_state *st = new (std::nothrow) rapid_state();
+    if (!st) return RAPID_ENOMEM;
+    if ((r = make_sched(params, &st->sc, st->level_first))) { delete st; return r; }
+    int32_t gx, gy;
+    if ((r = image_grid(img, params, st->sc, &gx, &gy))) { delete st; return r; }
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) { delete st; return RAPID_EDEVICE; }
+    st->ctx = ctx;
+    st->W = img->W;
+    st->H = img->H;
+    Layout L = plan(img->W, img->H, gx * gy, st->sc);
+    if (hipMalloc(&st->mem, L.bytes) != hipSuccess) { delete st; return RAPID_ENOMEM; }
+    if (hipMalloc(&st->job_dev, sizeof(Job)) != hipSuccess) {
+        (void)hipFree(st->mem);
+        delete st;
+        return RAPID_ENOMEM;
+    }
+    rapid_image im = *img;
+    im.labels_dev = nullptr;
+    im.label_stride = img->W;
+    fill_job(st->job, st->mem, L, &im, gx, gy, nullptr);
+    std::vector<Job> jobs(1, st->job);
+    int64_t max_nb[MAXST] = {};
+    for (int s = 0; s < st->sc.n_stages; s++)
+        max_nb[s] = (int64_t)((img->W + st->sc.B[s] - 1) / st->sc.B[s]) * ((img->H + st->sc.B[s] - 1) / st->sc.B[s]);
+    // grid labels and statistics, no stage yet
+    Sched sc = st->sc;
+    sc.gate_stage = sc.n_stages;
+    r = run_jobs(ctx, jobs, sc, 0, 0, FLAG_INIT, gx * gy, max_nb);
+    if (r == RAPID_OK) r = dev_err(hipStreamSynchronize(ctx->stream));
+    if (r) {
+        (void)hipFree(st->mem);
+        (void)hipFree(st->job_dev);
+        delete st;
+        return r;
+    }
+    st->next_level = 0;
+    st->map_stage = 0;
+    *out = st;
+    return RAPID_OK;
+}
+
+rapid_status rapid_refine_level(rapid_ctx *ctx, rapid_state *st, int32_t level, const uint8_t *gate_dev,
+                                rapid_report *report)
+{
+    if (!ctx || !st || st->ctx != ctx) return RAPID_EINVAL;
+    if (level != st->next_level || level >= RAPID_MAX_LEVELS) return RAPID_ESTATE;
+    int s0 = st->level_first[level], s1 = st->level_first[level + 1];
+    if (s1 <= s0) return RAPID_ESTATE;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return RAPID_EDEVICE;
+    Sched sc = st->sc;
+    sc.gate_stage = gate_dev ? s0 : sc.n_stages;
+    st->job.gate = gate_dev;
+    std::vector<Job> jobs(1, st->job);
+    int64_t max_nb[MAXST] = {};
+    rapid_status r = run_jobs(ctx, jobs, sc, s0, s1, 0, st->job.K, max_nb);
+    if (r) return r;
+    st->next_level = level + 1;
+    st->map_stage = s1 - 1;
+    if (report) return fetch_reports(ctx, jobs, sc, s0, s1, report);
+    return RAPID_OK;
+}
+
+rapid_status rapid_state_export(rapid_ctx *ctx, rapid_state *st, int32_t *labels_dev, int64_t *stats_dev)
+{
+    if (!ctx || !st || st->ctx != ctx) return RAPID_EINVAL;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return RAPID_EDEVICE;
+    if (labels_dev) {
+        int s = st->map_stage;
+        HIPCHK(launch_expand(st->job.lab[s & 1], st->W, st->H, st->sc.B[s], labels_dev, st->W, ctx->stream));
+    }
+    if (stats_dev)
+        HIPCHK(hipMemcpyAsync(stats_dev, st->job.stats, sizeof(int64_t) * 6 * st->job.K,
+                              hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RAPID_OK;
+}
+
+void rapid_state_destroy(rapid_state *st)
+{
+    if (!st) return;
+    if (st->ctx) {
+        (void)hipSetDevice(st->ctx->device);
+        (void)hipStreamSynchronize(st->ctx->stream);
+    }
+    (void)hipFree(st->mem);
+    (void)hipFree(st->job_dev);
+    delete st;
+}
+
+}  // extern "C"

@@ -1,0 +1,275 @@
+"""Python binding of the C-ABI in ``include/rapid.h`` (``librapid.so``).
+
+Argument marshalling only: every step of the segmentation runs in the HIP
+kernels of the library.  PyTorch supplies device memory and the stream.
+Importing this module fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librapid.so")
+
+ABI_VERSION = 1
+MAX_LEVELS = 4
+MAX_STAGES = 8
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("librapid.so is not built (run __graft_entry__.build()): " + LIB_PATH)
+_lib = C.CDLL(LIB_PATH)
+
+STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "device error",
+          -4: "state used out of order", -5: "gate model unusable"}
+
+
+class RapidError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__("%s: %s (%d)" % (where, STATUS.get(code, "?"), code))
+        self.code = code
+
+
+CFG_TIMING = 1
+
+
+class Config(C.Structure):
+    _fields_ = [("abi_version", C.c_int32), ("device", C.c_int32), ("hip_stream", C.c_void_p),
+                ("flags", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Timings(C.Structure):
+    _fields_ = [("block_sums_ms", C.c_float), ("refine_ms", C.c_float)]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("K", C.c_int32), ("gx", C.c_int32), ("gy", C.c_int32), ("n_levels", C.c_int32),
+        ("factor", C.c_int32 * MAX_LEVELS), ("n_stages", C.c_int32 * MAX_LEVELS),
+        ("stages", (C.c_int32 * MAX_STAGES) * MAX_LEVELS),
+        ("gate_level", C.c_int32), ("frac_bits", C.c_int32), ("max_sweeps", C.c_int32),
+        ("reserved", C.c_int32),
+        ("min_size", C.c_int64), ("max_size", C.c_int64),
+        ("w_col", C.c_int64), ("w_pos", C.c_int64), ("w_bnd", C.c_int64),
+    ]
+
+
+class Image(C.Structure):
+    _fields_ = [("rgb_dev", C.c_void_p), ("W", C.c_int32), ("H", C.c_int32),
+                ("row_stride_bytes", C.c_int64), ("labels_dev", C.c_void_p),
+                ("label_stride", C.c_int64)]
+
+
+class StageReport(C.Structure):
+    _fields_ = [("level", C.c_int32), ("block", C.c_int32), ("sweeps", C.c_int32),
+                ("converged", C.c_int32), ("active", C.c_int64), ("proposals", C.c_int64),
+                ("commits", C.c_int64), ("skip_min", C.c_int64), ("skip_topo", C.c_int64)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class Report(C.Structure):
+    _fields_ = [("n_stages", C.c_int32), ("K", C.c_int32),
+                ("stage", StageReport * (MAX_LEVELS * MAX_STAGES))]
+
+    def stages(self):
+        return [self.stage[i].as_dict() for i in range(self.n_stages)]
+
+
+_P = C.c_void_p
+_lib.rapid_init.argtypes = [C.POINTER(Config), C.POINTER(_P)]
+_lib.rapid_destroy.argtypes = [_P]
+_lib.rapid_destroy.restype = None
+_lib.rapid_segment.argtypes = [_P, C.POINTER(Image), C.POINTER(Params), _P, C.POINTER(Report)]
+_lib.rapid_segment_batch.argtypes = [_P, C.POINTER(Image), C.c_int32, C.POINTER(Params),
+                                     C.POINTER(Report)]
+_lib.rapid_state_create.argtypes = [_P, C.POINTER(Image), C.POINTER(Params), C.POINTER(_P)]
+_lib.rapid_refine_level.argtypes = [_P, _P, C.c_int32, _P, C.POINTER(Report)]
+_lib.rapid_state_export.argtypes = [_P, _P, _P, _P]
+_lib.rapid_state_destroy.argtypes = [_P]
+_lib.rapid_state_destroy.restype = None
+_lib.rapid_grid.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                            C.POINTER(C.c_int32)]
+_lib.rapid_status_str.argtypes = [C.c_int]
+_lib.rapid_status_str.restype = C.c_char_p
+_lib.rapid_simple_lut.argtypes = [C.POINTER(C.c_uint32)]
+_lib.rapid_check_params.argtypes = [C.c_int32, C.c_int32, C.POINTER(Params), C.POINTER(C.c_int32)]
+_lib.rapid_last_timings.argtypes = [_P, C.POINTER(Timings)]
+
+EXPORTED = ["rapid_init", "rapid_destroy", "rapid_segment", "rapid_segment_batch",
+            "rapid_state_create", "rapid_refine_level", "rapid_state_export",
+            "rapid_state_destroy", "rapid_grid", "rapid_status_str", "rapid_simple_lut",
+            "rapid_check_params", "rapid_last_timings"]
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise RapidError(rc, where)
+
+
+def make_params(d: dict) -> Params:
+    p = Params()
+    p.K = int(d.get("K", 0))
+    p.gx = int(d.get("gx", 0))
+    p.gy = int(d.get("gy", 0))
+    levels = d["levels"]
+    p.n_levels = len(levels)
+    for l, (f, st) in enumerate(levels):
+        p.factor[l] = int(f)
+        p.n_stages[l] = len(st)
+        for s, b in enumerate(st):
+            p.stages[l][s] = int(b)
+    p.gate_level = int(d.get("gate_level", -1))
+    p.frac_bits = int(d.get("frac_bits", 4))
+    p.max_sweeps = int(d.get("max_sweeps", 64))
+    p.min_size = int(d["min_size"])
+    p.max_size = int(d["max_size"])
+    p.w_col = int(d["w_col"])
+    p.w_pos = int(d["w_pos"])
+    p.w_bnd = int(d["w_bnd"])
+    return p
+
+
+# ----------------------------------------------------------- host helpers
+
+def grid(W: int, H: int, K: int):
+    gx, gy = C.c_int32(), C.c_int32()
+    _check(_lib.rapid_grid(W, H, K, C.byref(gx), C.byref(gy)), "rapid_grid")
+    return gx.value, gy.value
+
+
+def simple_lut() -> list:
+    out = (C.c_uint32 * 8)()
+    _check(_lib.rapid_simple_lut(out), "rapid_simple_lut")
+    return [int(v) for v in out]
+
+
+def check_params(W: int, H: int, d: dict) -> int:
+    """Validate params for a W x H image; returns the superpixel count."""
+    k = C.c_int32()
+    p = make_params(d)
+    _check(_lib.rapid_check_params(W, H, C.byref(p), C.byref(k)), "rapid_check_params")
+    return k.value
+
+
+# -------------------------------------------------------------- device API
+
+def _image(rgb, labels) -> Image:
+    import torch
+    assert rgb.is_cuda and rgb.dtype == torch.uint8 and rgb.dim() == 3 and rgb.shape[2] == 3
+    assert rgb.stride(2) == 1 and rgb.stride(1) == 3, "rgb must be HWC with packed pixels"
+    im = Image()
+    im.rgb_dev = rgb.data_ptr()
+    im.H, im.W = int(rgb.shape[0]), int(rgb.shape[1])
+    im.row_stride_bytes = int(rgb.stride(0))
+    if labels is not None:
+        assert labels.is_cuda and labels.dtype == torch.int32 and labels.stride(1) == 1
+        im.labels_dev = labels.data_ptr()
+        im.label_stride = int(labels.stride(0))
+    return im
+
+
+class Context:
+    """rapid_init / rapid_destroy around one device and stream."""
+
+    def __init__(self, device: int = 0, stream=None, timing: bool = False):
+        import torch
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        cfg = Config(ABI_VERSION, device, C.c_void_p(stream.cuda_stream),
+                     CFG_TIMING if timing else 0, 0)
+        h = _P()
+        _check(_lib.rapid_init(C.byref(cfg), C.byref(h)), "rapid_init")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.rapid_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # rapid_segment
+    def segment(self, rgb, params: dict, gate=None, labels=None, report: bool = True):
+        import torch
+        H, W = int(rgb.shape[0]), int(rgb.shape[1])
+        if labels is None:
+            labels = torch.empty((H, W), dtype=torch.int32, device=rgb.device)
+        im = _image(rgb, labels)
+        p = make_params(params)
+        rep = Report() if report else None
+        g = None if gate is None else C.c_void_p(gate.data_ptr())
+        _check(_lib.rapid_segment(self._h, C.byref(im), C.byref(p), g,
+                                  C.byref(rep) if rep is not None else None), "rapid_segment")
+        return labels, (rep.stages() if rep is not None else None)
+
+    # rapid_segment_batch
+    def segment_batch(self, rgbs, params: dict, labels=None, report: bool = True):
+        import torch
+        n = len(rgbs)
+        if labels is None:
+            labels = [torch.empty((int(r.shape[0]), int(r.shape[1])), dtype=torch.int32,
+                                  device=r.device) for r in rgbs]
+        ims = (Image * n)(*[_image(r, l) for r, l in zip(rgbs, labels)])
+        p = make_params(params)
+        reps = (Report * n)() if report else None
+        _check(_lib.rapid_segment_batch(self._h, ims, n, C.byref(p), reps), "rapid_segment_batch")
+        return labels, ([r.stages() for r in reps] if reps is not None else None)
+
+    def last_timings(self) -> dict:
+        t = Timings()
+        _check(_lib.rapid_last_timings(self._h, C.byref(t)), "rapid_last_timings")
+        return {"block_sums_ms": float(t.block_sums_ms), "refine_ms": float(t.refine_ms)}
+
+    def state(self, rgb, params: dict) -> "State":
+        return State(self, rgb, params)
+
+
+class State:
+    """rapid_state_create / rapid_refine_level / rapid_state_export."""
+
+    def __init__(self, ctx: Context, rgb, params: dict):
+        self.ctx = ctx
+        self.rgb = rgb
+        im = _image(rgb, None)
+        p = make_params(params)
+        h = _P()
+        _check(_lib.rapid_state_create(ctx._h, C.byref(im), C.byref(p), C.byref(h)),
+               "rapid_state_create")
+        self._h = h
+        self.K = check_params(im.W, im.H, params)
+
+    def refine_level(self, level: int, gate=None, report: bool = True):
+        rep = Report() if report else None
+        g = None if gate is None else C.c_void_p(gate.data_ptr())
+        _check(_lib.rapid_refine_level(self.ctx._h, self._h, level, g,
+                                       C.byref(rep) if rep is not None else None),
+               "rapid_refine_level")
+        return rep.stages() if rep is not None else None
+
+    def export(self):
+        import torch
+        H, W = int(self.rgb.shape[0]), int(self.rgb.shape[1])
+        labels = torch.empty((H, W), dtype=torch.int32, device=self.rgb.device)
+        stats = torch.empty((self.K, 6), dtype=torch.int64, device=self.rgb.device)
+        _check(_lib.rapid_state_export(self.ctx._h, self._h, C.c_void_p(labels.data_ptr()),
+                                       C.c_void_p(stats.data_ptr())), "rapid_state_export")
+        return labels, stats
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.rapid_state_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -19,16 +19,11 @@ import numpy as np
 
 
 def _voronoi_assign(W: int, H: int, sites: np.ndarray) -> np.ndarray:
-    """Index of the nearest site (squared Euclidean, lowest index on ties)."""
+    """Index of the nearest site (Euclidean) for every pixel."""
+    from scipy.spatial import cKDTree
     ys, xs = np.mgrid[0:H, 0:W]
-    best = np.full((H, W), np.inf)
-    idx = np.zeros((H, W), np.int32)
-    for s, (sx, sy) in enumerate(sites):
-        d = (xs - sx) ** 2 + (ys - sy) ** 2
-        m = d < best
-        best[m] = d[m]
-        idx[m] = s
-    return idx
+    _, idx = cKDTree(sites).query(np.stack([xs.ravel(), ys.ravel()], 1).astype(np.float64), workers=-1)
+    return idx.reshape(H, W).astype(np.int32)
 
 
 def _box3(img: np.ndarray) -> np.ndarray:

@@ -1,0 +1,74 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every symbol its header declares, and its host logic (topology table, grid,
+parameter validation) agrees with the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1704_02083_amd import params, rapid
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "rapid.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rapid_[a-z_]+)\s*\(", src)))
+
+
+def test_header_symbols_exported():
+    syms = _declared_symbols()
+    assert len(syms) >= 12
+    for s in syms:
+        assert hasattr(rapid._lib, s), s
+    assert set(syms) == set(rapid.EXPORTED)
+
+
+def test_simple_lut_matches_oracle():
+    lut = rapid.simple_lut()
+    bits = [(lut[m >> 5] >> (m & 31)) & 1 for m in range(256)]
+    assert sum(bits) == 116
+    for m in range(256):
+        assert bool(bits[m]) == oracle.simple(m), m
+
+
+def test_grid_matches_oracle():
+    rng = np.random.default_rng(3)
+    for _ in range(400):
+        W, H = int(rng.integers(1, 9000)), int(rng.integers(1, 9000))
+        K = int(rng.integers(1, 200000))
+        assert rapid.grid(W, H, K) == oracle.grid(W, H, K), (W, H, K)
+
+
+def test_check_params_accepts_workloads():
+    assert rapid.check_params(256, 256, params.config1()) == 64
+    assert rapid.check_params(481, 321, params.config2(481, 321)) == 400
+    assert rapid.check_params(321, 481, params.config2(321, 481)) == 408
+    assert rapid.check_params(4096, 4096, params.config3()) == 16384
+
+
+@pytest.mark.parametrize("mutate", [
+    lambda p: p.update(levels=[(1, [8, 16])]),          # increasing block size
+    lambda p: p.update(levels=[(1, [16, 6])]),          # 6 does not divide 16
+    lambda p: p.update(levels=[(1, [128, 64])]),        # block > 64
+    lambda p: p.update(frac_bits=5),
+    lambda p: p.update(max_sweeps=0),
+    lambda p: p.update(w_col=-1),
+    lambda p: p.update(w_pos=1 << 40),                  # energy would overflow int64
+    lambda p: p.update(K=100000),                       # grid does not fit 16-px blocks
+    lambda p: p.update(K=0, gx=0, gy=3),
+])
+def test_check_params_rejects(mutate):
+    p = params.config1()
+    mutate(p)
+    with pytest.raises(rapid.RapidError) as e:
+        rapid.check_params(256, 256, p)
+    assert e.value.code == -1
+
+
+def test_check_params_rejects_big_image():
+    with pytest.raises(rapid.RapidError):
+        rapid.check_params(8193, 16, params.default_params(8193, 16, 1))
