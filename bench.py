@@ -120,6 +120,9 @@ def main():
     ap.add_argument("--workload", default="batch", choices=["batch", "single256"])
     ap.add_argument("--cpu-sample", type=int, default=80)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy three times (scales the HBM "
+                         "byte counters of rocprofv3 --pmc)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -129,6 +132,16 @@ def main():
 
     import torch
     from paper_1704_02083_amd import rapid
+
+    if args.copy_calibration:
+        n = 1 << 30
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n, "launches": 3}), flush=True)
+        return
 
     imgs, p, desc = workload(args.workload)
     print("bench: workload %s, %d images generated" % (args.workload, len(imgs)), file=sys.stderr,
