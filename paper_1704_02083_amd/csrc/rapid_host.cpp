@@ -2,6 +2,8 @@
 // planning, launches.  Every step of the segmentation runs in the kernels of
 // rapid_kernels.hip; this file only marshals.
 #include <algorithm>
+#include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -17,7 +19,8 @@ struct rapid_ctx {
     hipStream_t stream = nullptr;
     uint32_t *lut_dev = nullptr;
     size_t lds_limit = 0;
-    int threads = 512;
+    int threads = 1024;
+    bool verbose = false;
     // scratch pool for rapid_segment / rapid_segment_batch
     char *pool = nullptr;
     size_t pool_size = 0;
@@ -158,6 +161,33 @@ rapid_status make_sched(const rapid_params *p, Sched *sc, int32_t level_first[RA
     return RAPID_OK;
 }
 
+// Largest intermediate magnitude of E' for blocks of size B (see
+// block_energy / block_energy_f64): every product and partial sum is bounded
+// by the sum of the three weighted terms' worst cases.
+__int128 energy_bound(const Sched &sc, int B, int32_t W, int32_t H)
+{
+    typedef __int128 i128;
+    i128 m = (i128)B * B;
+    i128 cmax = (i128)255 << sc.F;
+    i128 dim = std::max(W, H);
+    i128 mumax = (dim - 1) << sc.F;
+    i128 e_col = m * 3 * cmax * cmax + ((i128)2 << sc.F) * 3 * cmax * m * 255;
+    i128 e_pos = m * 2 * mumax * mumax + ((i128)2 << sc.F) * 2 * mumax * m * (dim - 1);
+    i128 e_bnd = (4 * (i128)B) << (2 * sc.F);
+    return sc.w_col * e_col + sc.w_pos * e_pos + sc.w_bnd * e_bnd;
+}
+
+// Per stage: can fp64 evaluate E' exactly (all intermediates < 2^53)?
+void set_exactness(Sched &sc, int32_t W, int32_t H)
+{
+    const __int128 lim53 = (__int128)1 << 53;
+    for (int s = 0; s < sc.n_stages; s++) sc.f64[s] = energy_bound(sc, sc.B[s], W, H) < lim53;
+    sc.d_wc = (double)sc.w_col;
+    sc.d_wp = (double)sc.w_pos;
+    sc.d_wb = std::ldexp((double)sc.w_bnd, 2 * sc.F);
+    sc.d_fs = std::ldexp(1.0, sc.F + 1);
+}
+
 // Worst-case |E'| of a block must stay below 2^62 so that the int64 block
 // energy of the kernels is exact.
 bool energy_fits(const Sched &sc, int32_t W, int32_t H)
@@ -234,7 +264,7 @@ Layout plan(int32_t W, int32_t H, int32_t K, const Sched &sc)
         }
     }
     L.off_lists = take(4 * 9 * L.capc);
-    L.off_props = take(4 * 3 * L.capc);
+    L.off_props = take(sizeof(Prop) * L.capc);
     L.off_changed = take(4 * nbF);
     L.off_stamp = take(4 * nbF);
     L.off_stats = take(8 * 6 * (size_t)K);
@@ -265,7 +295,7 @@ void fill_job(Job &J, char *base, const Layout &L, const rapid_image *img, int32
         J.sums[s] = L.off_sums[s] == (size_t)-1 ? nullptr : reinterpret_cast<uint64_t *>(base + L.off_sums[s]);
     J.lists = reinterpret_cast<int32_t *>(base + L.off_lists);
     J.capc = L.capc;
-    J.props = reinterpret_cast<int32_t *>(base + L.off_props);
+    J.props = reinterpret_cast<Prop *>(base + L.off_props);
     J.changed = reinterpret_cast<int32_t *>(base + L.off_changed);
     J.stamp = reinterpret_cast<int32_t *>(base + L.off_stamp);
     J.stats = reinterpret_cast<int64_t *>(base + L.off_stats);
@@ -284,15 +314,40 @@ rapid_status dev_err(hipError_t e) { return e == hipSuccess ? RAPID_OK : RAPID_E
         if (e_ != hipSuccess) return RAPID_EDEVICE; \
     } while (0)
 
-bool use_lds(const rapid_ctx *ctx, int32_t Kmax, size_t *bytes)
+// Carve the LDS of the refinement kernel: statistics first (when they fit
+// with room to spare), then the class lists, proposals, the frontier visit
+// bitmap and the changed list, each within a share of what remains.
+LdsPlan plan_lds(size_t limit, int32_t Kmax, int64_t nbF)
 {
-    size_t b = (size_t)Kmax * LDS_PER_SP;
-    *bytes = b;
-    return b <= ctx->lds_limit;
+    LdsPlan p;
+    std::memset(&p, 0, sizeof p);
+    auto a16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
+    size_t off = 0;
+    size_t stats = (size_t)Kmax * LDS_PER_SP;
+    if (stats + 48 * 1024 <= limit) {
+        p.stats_lds = 1;
+        off = a16(stats);
+    }
+    size_t rem = limit > off ? limit - off : 0;
+    p.capl = (int)std::min<size_t>(1024, rem * 35 / 100 / (9 * 4));
+    p.capp = (int)std::min<size_t>(1024, rem * 25 / 100 / sizeof(Prop));
+    p.bm_words = (int)std::min<size_t>((size_t)((nbF + 31) / 32), rem * 25 / 100 / 4);
+    p.off_lists = (uint32_t)off;
+    off = a16(off + (size_t)9 * 4 * p.capl);
+    p.off_props = (uint32_t)off;
+    off = a16(off + sizeof(Prop) * p.capp);
+    p.off_bm = (uint32_t)off;
+    off = a16(off + 4 * (size_t)p.bm_words);
+    p.off_chg = (uint32_t)off;
+    size_t left = limit > off ? limit - off : 0;
+    p.capx = (int)std::min<size_t>(4096, left / 4);
+    off = a16(off + 4 * (size_t)p.capx);
+    p.total = (uint32_t)off;
+    return p;
 }
 
 rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched &sc, int s_begin,
-                      int s_end, int flags, int32_t Kmax, int64_t max_nb[MAXST])
+                      int s_end, int flags, int32_t Kmax, int64_t nbF_max, int64_t max_nb[MAXST])
 {
     size_t n = jobs.size();
     if (n > ctx->jobs_cap) {
@@ -321,11 +376,14 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
             if (sc.B[s] >= 2)
                 HIPCHK(launch_block_sums(ctx->jobs_dev, (int)n, s, sc.B[s], max_nb[s], ctx->stream));
     }
-    size_t lds_bytes = 0;
-    bool lds = use_lds(ctx, Kmax, &lds_bytes);
+    LdsPlan lp = plan_lds(ctx->lds_limit, Kmax, nbF_max);
+    if (ctx->verbose)
+        std::fprintf(stderr,
+                     "rapid: lds limit %zu, stats_lds %d, capl %d capp %d capx %d bm_words %d total %u\n",
+                     ctx->lds_limit, lp.stats_lds, lp.capl, lp.capp, lp.capx, lp.bm_words, lp.total);
     if (ctx->timing) HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
-    HIPCHK(launch_refine(ctx->jobs_dev, (int)n, sc, s_begin, s_end, flags, ctx->lut_dev, lds,
-                         lds ? lds_bytes : 0, ctx->threads, ctx->stream));
+    HIPCHK(launch_refine(ctx->jobs_dev, (int)n, sc, lp, s_begin, s_end, flags, ctx->lut_dev,
+                         ctx->threads, ctx->stream));
     if (ctx->timing) {
         HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
         ctx->timed = true;
@@ -414,6 +472,7 @@ rapid_status rapid_init(const rapid_config *cfg, rapid_ctx **out)
     // leave room for the kernel's static LDS
     size_t lim = prop.sharedMemPerBlock;
     ctx->lds_limit = lim > 1024 ? lim - 1024 : 0;
+    ctx->verbose = std::getenv("RAPID_VERBOSE") != nullptr;
     if (const char *t = std::getenv("RAPID_THREADS")) {
         int v = std::atoi(t);
         if (v >= 64 && v <= 1024 && v % 64 == 0) ctx->threads = v;
@@ -480,6 +539,7 @@ static rapid_status segment_impl(rapid_ctx *ctx, const rapid_image *imgs, int32_
     size_t total = 0;
     int32_t Kmax = 0;
     int64_t max_nb[MAXST] = {};
+    int64_t nbF_max = 0;
     for (int i = 0; i < n; i++) {
         if ((r = check_image(&imgs[i], true))) return r;
         if ((r = image_grid(&imgs[i], params, sc, &gxs[i], &gys[i]))) return r;
@@ -490,6 +550,7 @@ static rapid_status segment_impl(rapid_ctx *ctx, const rapid_image *imgs, int32_
             int64_t nb = (int64_t)((imgs[i].W + sc.B[s] - 1) / sc.B[s]) * ((imgs[i].H + sc.B[s] - 1) / sc.B[s]);
             max_nb[s] = std::max(max_nb[s], nb);
         }
+        nbF_max = std::max(nbF_max, max_nb[sc.n_stages - 1]);
     }
     if (total > ctx->pool_size) {
         HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -504,8 +565,19 @@ static rapid_status segment_impl(rapid_ctx *ctx, const rapid_image *imgs, int32_
     for (int i = 0; i < n; i++) {
         fill_job(jobs[i], ctx->pool + off, lay[i], &imgs[i], gxs[i], gys[i], gate_dev);
         off += lay[i].bytes;
+        // a final stage of single pixels writes its label map straight into
+        // the caller's contiguous label buffer
+        if (sc.B[sc.n_stages - 1] == 1 && imgs[i].label_stride == imgs[i].W)
+            jobs[i].lab[(sc.n_stages - 1) & 1] = imgs[i].labels_dev;
     }
-    if ((r = run_jobs(ctx, jobs, sc, 0, sc.n_stages, FLAG_INIT | FLAG_OUT, Kmax, max_nb))) return r;
+    int32_t Wmax = 0, Hmax = 0;
+    for (int i = 0; i < n; i++) {
+        Wmax = std::max(Wmax, imgs[i].W);
+        Hmax = std::max(Hmax, imgs[i].H);
+    }
+    set_exactness(sc, Wmax, Hmax);
+    if ((r = run_jobs(ctx, jobs, sc, 0, sc.n_stages, FLAG_INIT | FLAG_OUT, Kmax, nbF_max, max_nb)))
+        return r;
     if (reports) return fetch_reports(ctx, jobs, sc, 0, sc.n_stages, reports);
     return RAPID_OK;
 }
@@ -538,6 +610,7 @@ rapid_status rapid_state_create(rapid_ctx *ctx, const rapid_image *img, const ra
     st->ctx = ctx;
     st->W = img->W;
     st->H = img->H;
+    set_exactness(st->sc, img->W, img->H);
     Layout L = plan(img->W, img->H, gx * gy, st->sc);
     if (hipMalloc(&st->mem, L.bytes) != hipSuccess) { delete st; return RAPID_ENOMEM; }
     if (hipMalloc(&st->job_dev, sizeof(Job)) != hipSuccess) {
@@ -556,7 +629,7 @@ rapid_status rapid_state_create(rapid_ctx *ctx, const rapid_image *img, const ra
     // grid labels and statistics, no stage yet
     Sched sc = st->sc;
     sc.gate_stage = sc.n_stages;
-    r = run_jobs(ctx, jobs, sc, 0, 0, FLAG_INIT, gx * gy, max_nb);
+    r = run_jobs(ctx, jobs, sc, 0, 0, FLAG_INIT, gx * gy, max_nb[st->sc.n_stages - 1], max_nb);
     if (r == RAPID_OK) r = dev_err(hipStreamSynchronize(ctx->stream));
     if (r) {
         (void)hipFree(st->mem);
@@ -584,7 +657,9 @@ rapid_status rapid_refine_level(rapid_ctx *ctx, rapid_state *st, int32_t level, 
     st->job.gate = gate_dev;
     std::vector<Job> jobs(1, st->job);
     int64_t max_nb[MAXST] = {};
-    rapid_status r = run_jobs(ctx, jobs, sc, s0, s1, 0, st->job.K, max_nb);
+    int Bf = sc.B[sc.n_stages - 1];
+    int64_t nbF = (int64_t)((st->W + Bf - 1) / Bf) * ((st->H + Bf - 1) / Bf);
+    rapid_status r = run_jobs(ctx, jobs, sc, s0, s1, 0, st->job.K, nbF, max_nb);
     if (r) return r;
     st->next_level = level + 1;
     st->map_stage = s1 - 1;

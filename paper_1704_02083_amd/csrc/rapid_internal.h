@@ -15,9 +15,30 @@ struct Sched {
     int32_t n_stages;
     int32_t B[MAXST];
     int32_t level[MAXST];
+    int32_t f64[MAXST];      // 1: every intermediate of E' at this stage is an
+                             // integer below 2^53, so fp64 evaluates it exactly
     int32_t gate_stage;      // first stage refined under the gate
     int32_t F, max_sweeps;
     int64_t min_size, max_size, w_col, w_pos, w_bnd;
+    double d_wc, d_wp, d_wb, d_fs;   // w_col, w_pos, w_bnd 2^(2F), 2^(F+1) as doubles
+};
+
+// A proposal: block, source and destination labels, packed colour sum of
+// the block (21 bits per channel).
+struct Prop {
+    int32_t bi, a, k, pad;
+    uint64_t I;
+};
+
+// LDS carve-up of the refinement kernel (byte offsets into dynamic LDS).
+// Statistics at offset 0 when stats_lds; work lists hold their first
+// cap* entries in LDS and spill to global scratch; the visit bitmap of the
+// frontier rebuild is used when it covers the stage's blocks.
+struct LdsPlan {
+    int32_t stats_lds;
+    int32_t capl, capp, capx, bm_words;
+    uint32_t off_lists, off_props, off_chg, off_bm;
+    uint32_t total;
 };
 
 // One image (or tile) and its scratch, all device pointers.
@@ -31,9 +52,9 @@ struct Job {
     uint64_t *sums[MAXST];   // packed block sums per stage (B >= 2)
     int32_t *lists;          // 9 class lists of capc entries
     int64_t capc;
-    int32_t *props;          // 3 ints per proposal
+    Prop *props;             // proposals beyond the LDS capacity
     int32_t *changed;        // changed blocks of a sweep
-    int32_t *stamp;          // per block visit stamp
+    int32_t *stamp;          // per block visit stamp (when the LDS bitmap is too small)
     int64_t *stats;          // K x 6 int64: n, S_r, S_g, S_b, T_x, T_y
     int32_t *means;          // K x MN_STRIDE (global working set)
     int32_t *flow;           // K x 2 out/in (global working set)
@@ -46,8 +67,8 @@ hipError_t launch_block_sums(const Job *jobs_dev, int n_jobs, int s, int B, int6
                              hipStream_t stream);
 hipError_t launch_expand(const int32_t *L, int W, int H, int B, int32_t *out, int64_t stride,
                          hipStream_t stream);
-hipError_t launch_refine(const Job *jobs_dev, int n_jobs, const Sched &sc, int s_begin, int s_end,
-                         int flags, const uint32_t *lut_dev, bool lds, size_t lds_bytes, int threads,
+hipError_t launch_refine(const Job *jobs_dev, int n_jobs, const Sched &sc, const LdsPlan &lp,
+                         int s_begin, int s_end, int flags, const uint32_t *lut_dev, int threads,
                          hipStream_t stream);
 
 // per-superpixel means record: c_r c_g c_b mu_x mu_y n (int32)

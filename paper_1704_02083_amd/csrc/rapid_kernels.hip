@@ -107,6 +107,38 @@ __device__ __forceinline__ int64_t block_energy(const int32_t *mn, int k, const 
 // Means in fixed point, rounded half up, plus the size n: the class-start
 // snapshot that every proposal and every size-filter decision of the next
 // class reads while the integer atomics of that class update the sums.
+// The same E' in fp64.  Used only where the host has proven that every
+// product and sum below is an integer of magnitude < 2^53, so each fp64
+// operation is exact and the result equals the int64 one bit for bit.
+__device__ __forceinline__ double block_energy_f64(const int32_t *mn, int k, double m, double I0,
+                                                   double I1, double I2, double px, double py,
+                                                   int bnd, const Sched &sc)
+{
+    const int32_t *c = mn + MN_STRIDE * k;
+    double c0 = c[0], c1 = c[1], c2 = c[2], mx = c[3], my = c[4];
+    double col = fma(c0, c0, fma(c1, c1, c2 * c2));
+    double dot = fma(c0, I0, fma(c1, I1, c2 * I2));
+    double e_col = fma(m, col, -(sc.d_fs * dot));
+    double pos = fma(mx, mx, my * my);
+    double pdot = fma(mx, px, my * py);
+    double e_pos = fma(m, pos, -(sc.d_fs * pdot));
+    return fma(sc.d_wc, e_col, fma(sc.d_wp, e_pos, sc.d_wb * (double)bnd));
+}
+
+// floor(num / den) for 0 <= num, 0 < den < 2^53: fp64 quotient, then one
+// exact correction step each way (products stay below 2^53).
+__device__ __forceinline__ int64_t floor_div_f64(int64_t num, int64_t den)
+{
+    double dn = (double)num, dd = (double)den;
+    double q = floor(dn / dd);
+    if (q * dd > dn) q -= 1.0;
+    else if ((q + 1.0) * dd <= dn) q += 1.0;
+    return (int64_t)q;
+}
+
+// Means in fixed point, rounded half up, plus the size n: the class-start
+// snapshot that every proposal and every size-filter decision of the next
+// class reads while the integer atomics of that class update the sums.
 __device__ __forceinline__ void refresh_means(const int64_t *st, int32_t *mn, int k, int F)
 {
     const int64_t *r = st + 6 * (int64_t)k;
@@ -114,13 +146,13 @@ __device__ __forceinline__ void refresh_means(const int64_t *st, int32_t *mn, in
     int64_t d = 2 * n;
     int32_t *o = mn + MN_STRIDE * (int64_t)k;
 #pragma unroll
-    for (int q = 0; q < 5; q++) o[q] = (int32_t)(((r[1 + q] << (F + 1)) + n) / d);
+    for (int q = 0; q < 5; q++) o[q] = (int32_t)floor_div_f64((r[1 + q] << (F + 1)) + n, d);
     o[5] = (int32_t)n;
 }
 
 __device__ __forceinline__ int32_t lab_at(const int32_t *L, int bx, int by, int nbx, int nby)
 {
-    return (bx >= 0 && by >= 0 && bx < nbx && by < nby) ? L[(int64_t)by * nbx + bx] : -1;
+    return (bx >= 0 && by >= 0 && bx < nbx && by < nby) ? L[by * nbx + bx] : -1;
 }
 
 __device__ __forceinline__ bool pair_on(const uint8_t *gate, int a, int k)
@@ -131,7 +163,7 @@ __device__ __forceinline__ bool pair_on(const uint8_t *gate, int a, int k)
 __device__ __forceinline__ bool eligible(const int32_t *L, int bx, int by, int nbx, int nby,
                                          const uint8_t *gate)
 {
-    int32_t a = L[(int64_t)by * nbx + bx];
+    int32_t a = L[by * nbx + bx];
     int32_t k;
     if ((k = lab_at(L, bx - 1, by, nbx, nby)) >= 0 && k != a && pair_on(gate, a, k)) return true;
     if ((k = lab_at(L, bx + 1, by, nbx, nby)) >= 0 && k != a && pair_on(gate, a, k)) return true;
@@ -186,8 +218,39 @@ __global__ void k_expand(const int32_t *__restrict__ L, int W, int H, int B,
 }
 
 // ------------------------------------------------------------- k_refine
+
+// Work lists live in LDS up to a capacity and spill to the image's global
+// scratch beyond it (same index space).
+__device__ __forceinline__ int32_t list_get(const int32_t *lds, int cap, const int32_t *glob,
+                                            int64_t gbase, int e)
+{
+    return e < cap ? lds[e] : glob[gbase + e];
+}
+
+__device__ __forceinline__ void list_put(int32_t *lds, int cap, int32_t *glob, int64_t gbase, int e,
+                                         int32_t v)
+{
+    if (e < cap) lds[e] = v;
+    else glob[gbase + e] = v;
+}
+
+__device__ __forceinline__ uint64_t pack_rgb(int64_t r, int64_t g, int64_t b)
+{
+    return (uint64_t)r | ((uint64_t)g << 21) | ((uint64_t)b << 42);
+}
+
+// Append v to the list of class cls (LDS atomic on the class counter; the
+// hardware serialises lanes hitting the same counter, which is cheaper than
+// nine rounds of wave-level aggregation).
+__device__ __forceinline__ void class_push(int32_t *cnt, int32_t *lds, int capl, int32_t *glob,
+                                           int64_t capg, int cls, int32_t v)
+{
+    int slot = atomicAdd(&cnt[cls], 1);
+    list_put(lds + cls * capl, capl, glob, cls * capg, slot, v);
+}
+
 template <bool LDS>
-__global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, Sched sc,
+__global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, Sched sc, LdsPlan lp,
                                                   int s_begin, int s_end, int flags,
                                                   const uint32_t *__restrict__ lut_g)
 {
@@ -205,13 +268,23 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
     if (LDS) {
         st = reinterpret_cast<int64_t *>(smem);
         mn = reinterpret_cast<int32_t *>(st + 6 * (int64_t)K);  // K x MN_STRIDE
+        fl = mn + MN_STRIDE * (int64_t)K;
+        tch = fl + 2 * (int64_t)K;
+        tl = tch + K;
     } else {
         st = J.stats;
         mn = J.means;
+        fl = J.flow;
+        tch = J.touched;
+        tl = J.touched + K;
     }
-    fl = LDS ? mn + MN_STRIDE * (int64_t)K : J.flow;
-    tch = LDS ? fl + 2 * (int64_t)K : J.touched;
-    tl = LDS ? tch + K : J.touched + K;
+    int32_t *l_lists = reinterpret_cast<int32_t *>(smem + lp.off_lists);
+    Prop *l_props = reinterpret_cast<Prop *>(smem + lp.off_props);
+    int32_t *l_chg = reinterpret_cast<int32_t *>(smem + lp.off_chg);
+    uint32_t *l_bm = reinterpret_cast<uint32_t *>(smem + lp.off_bm);
+    Prop *g_props = J.props;
+    const int capl = lp.capl, capp = lp.capp, capx = lp.capx;
+    const int64_t capg = J.capc;
 
     if (tid < 8) s_lut[tid] = lut_g[tid];
     if (tid == 0) {
@@ -222,6 +295,7 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
     }
     for (int64_t i = tid; i < 2 * (int64_t)K; i += nt) fl[i] = 0;
     for (int64_t i = tid; i < K; i += nt) tch[i] = 0;
+    for (int i = tid; i < lp.bm_words; i += nt) l_bm[i] = 0;
 
     if (flags & FLAG_INIT) {
         // grid initialisation (Algorithm RAPID, first step) and the
@@ -255,44 +329,73 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
     for (int64_t k = tid; k < K; k += nt) refresh_means(st, mn, (int)k, sc.F);
     wg_sync();
 
-    const int64_t capc = J.capc;
     for (int s = s_begin; s < s_end; s++) {
         const int B = sc.B[s];
         const int nbx = (W + B - 1) / B, nby = (H + B - 1) / B;
         const int64_t nb = (int64_t)nbx * nby;
         int32_t *L = J.lab[s & 1];
         const uint8_t *gate = (J.gate && s >= sc.gate_stage) ? J.gate : nullptr;
-        if (s > 0) {
-            // split: each block inherits the label of the block that holds it
-            const int Bp = sc.B[s - 1];
-            const int nbxp = (W + Bp - 1) / Bp;
-            const int32_t *Lp = J.lab[(s - 1) & 1];
-            const int r = Bp / B;
-            for (int64_t i = tid; i < nb; i += nt) {
-                int bx = (int)(i % nbx), by = (int)(i / nbx);
-                L[i] = Lp[(int64_t)(by / r) * nbxp + bx / r];
-            }
-        }
+        const bool use_bm = (int64_t)lp.bm_words * 32 >= nb;
+        const bool use_f64 = sc.f64[s] != 0;
         if (tid < 9) s_cnt[tid] = 0;
         if (tid < 5) s_ctr[tid] = 0;
         wg_sync();
-        // boundary blocks of the stage (Eq. (2); Eq. (7) under the gate)
-        for (int64_t i0 = 0; i0 < nb; i0 += nt) {
-            int64_t i = i0 + tid;
-            bool e = false;
-            int cls = 0;
-            if (i < nb) {
-                int bx = (int)(i % nbx), by = (int)(i / nbx);
-                J.stamp[i] = 0;
-                e = eligible(L, bx, by, nbx, nby, gate);
-                cls = 3 * (by % 3) + (bx % 3);
+        if (s > 0) {
+            // split: each block inherits the label of the block that holds it.
+            // A child is a boundary block only on a side where its parent
+            // borders a parent of another (active) label, so the boundary
+            // scan runs over the parents.
+            const int Bp = sc.B[s - 1];
+            const int nbxp = (W + Bp - 1) / Bp, nbyp = (H + Bp - 1) / Bp;
+            const int64_t nbp = (int64_t)nbxp * nbyp;
+            const int32_t *Lp = J.lab[(s - 1) & 1];
+            const int r = Bp / B;
+            for (int64_t p0 = 0; p0 < nbp; p0 += nt) {
+                int64_t p = p0 + tid;
+                int32_t a = 0;
+                bool sw = false, se = false, sn = false, ss = false;
+                int pxb = 0, pyb = 0;
+                if (p < nbp) {
+                    pxb = (int)(p % nbxp);
+                    pyb = (int)(p / nbxp);
+                    a = Lp[p];
+                    int32_t k;
+                    k = lab_at(Lp, pxb - 1, pyb, nbxp, nbyp);
+                    sw = k >= 0 && k != a && pair_on(gate, a, k);
+                    k = lab_at(Lp, pxb + 1, pyb, nbxp, nbyp);
+                    se = k >= 0 && k != a && pair_on(gate, a, k);
+                    k = lab_at(Lp, pxb, pyb - 1, nbxp, nbyp);
+                    sn = k >= 0 && k != a && pair_on(gate, a, k);
+                    k = lab_at(Lp, pxb, pyb + 1, nbxp, nbyp);
+                    ss = k >= 0 && k != a && pair_on(gate, a, k);
+                }
+#pragma unroll 1
+                for (int ch = 0; ch < r * r; ch++) {
+                    int cx = pxb * r + ch % r, cy = pyb * r + ch / r;
+                    bool valid = p < nbp && cx < nbx && cy < nby;
+                    if (valid) L[(int64_t)cy * nbx + cx] = a;
+                    bool e = valid && ((sw && ch % r == 0) || (se && ch % r == r - 1) ||
+                                       (sn && ch / r == 0) || (ss && ch / r == r - 1));
+                    if (e) class_push(s_cnt, l_lists, capl, J.lists, capg, 3 * (cy % 3) + (cx % 3),
+                                      cy * nbx + cx);
+                }
             }
-            // one append per class: loop over the classes present in the wave
-            for (int c = 0; c < 9; c++) {
-                int slot = wave_append(&s_cnt[c], e && cls == c);
-                if (slot >= 0) J.lists[c * capc + slot] = (int32_t)i;
+        } else {
+            // boundary blocks of the grid (Eq. (2); Eq. (7) under the gate)
+            for (int64_t i0 = 0; i0 < nb; i0 += nt) {
+                int64_t i = i0 + tid;
+                bool e = false;
+                int cls = 0;
+                if (i < nb) {
+                    int bx = (int)(i % nbx), by = (int)(i / nbx);
+                    e = eligible(L, bx, by, nbx, nby, gate);
+                    cls = 3 * (by % 3) + (bx % 3);
+                }
+                if (e) class_push(s_cnt, l_lists, capl, J.lists, capg, cls, (int32_t)i);
             }
         }
+        if (!use_bm)
+            for (int64_t i = tid; i < nb; i += nt) J.stamp[i] = 0;
         wg_sync();
 
         int sweeps = 0, converged = 0;
@@ -307,31 +410,39 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
             for (int c = 0; c < 9; c++) {
                 const int ncls = s_cnt[c];
                 if (ncls == 0) continue;
-                const int32_t *lst = J.lists + c * capc;
-                // ---- P1: propose
+                const int32_t *llst = l_lists + c * capl;
+                // ---- P1: propose from the class-start state
                 for (int e0 = 0; e0 < ncls; e0 += nt) {
                     int e = e0 + tid;
                     bool prop = false, smin = false, stopo = false;
                     int32_t bi = 0, a = 0, best = 0;
                     int64_t m = 0;
+                    uint64_t Ipk = 0;
                     if (e < ncls) {
-                        bi = lst[e];
-                        int bx = bi % nbx, by = bi / nbx;
-                        a = L[bi];
+                        bi = list_get(llst, capl, J.lists, c * capg, e);
+                        const int bx = bi % nbx, by = bi / nbx;
+                        const bool hw = bx > 0, he = bx + 1 < nbx, hn = by > 0, hs = by + 1 < nby;
+                        // every global load of the block at once: its label,
+                        // its 3x3 ring and its colour sum
+                        const int32_t *Lc = L + bi;
+                        a = Lc[0];
+                        int32_t rl[8];
+                        rl[0] = (hn && hw) ? Lc[-nbx - 1] : -1;
+                        rl[1] = hn ? Lc[-nbx] : -1;
+                        rl[2] = (hn && he) ? Lc[-nbx + 1] : -1;
+                        rl[3] = hw ? Lc[-1] : -1;
+                        rl[4] = he ? Lc[1] : -1;
+                        rl[5] = (hs && hw) ? Lc[nbx - 1] : -1;
+                        rl[6] = hs ? Lc[nbx] : -1;
+                        rl[7] = (hs && he) ? Lc[nbx + 1] : -1;
+                        int64_t I[3];
+                        block_rgb(J, s, B, bi, bx, by, I);
+                        Ipk = pack_rgb(I[0], I[1], I[2]);
                         Geo g = block_geo(bx, by, B, W, H);
                         m = g.m;
-                        if ((int64_t)mn[MN_STRIDE * (int64_t)a + 5] - g.m < sc.min_size) {
+                        if ((int64_t)mn[MN_STRIDE * a + 5] - g.m < sc.min_size) {
                             smin = true;
                         } else {
-                            int32_t rl[8];
-                            rl[0] = lab_at(L, bx - 1, by - 1, nbx, nby);
-                            rl[1] = lab_at(L, bx, by - 1, nbx, nby);
-                            rl[2] = lab_at(L, bx + 1, by - 1, nbx, nby);
-                            rl[3] = lab_at(L, bx - 1, by, nbx, nby);
-                            rl[4] = lab_at(L, bx + 1, by, nbx, nby);
-                            rl[5] = lab_at(L, bx - 1, by + 1, nbx, nby);
-                            rl[6] = lab_at(L, bx, by + 1, nbx, nby);
-                            rl[7] = lab_at(L, bx + 1, by + 1, nbx, nby);
                             uint32_t mask = 0;
 #pragma unroll
                             for (int q = 0; q < 8; q++) mask |= (rl[q] == a ? 1u : 0u) << q;
@@ -339,41 +450,55 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                                 stopo = true;
                             } else {
                                 // 4-neighbours W, E, N, S and their shared edge lengths
-                                int32_t nl[4] = {rl[3], rl[4], rl[1], rl[6]};
-                                int el[4] = {g.h, g.h, g.w, g.w};
-                                int32_t cand[4];
-                                int nc = 0;
-#pragma unroll
-                                for (int d = 0; d < 4; d++) {
-                                    int32_t k = nl[d];
-                                    bool ok = k >= 0 && k != a;
-                                    for (int q = 0; q < d; q++) ok = ok && nl[q] != k;
-                                    if (ok) cand[nc++] = k;
-                                }
-                                // ascending order
-                                for (int u = 1; u < nc; u++)
-                                    for (int v = u; v > 0 && cand[v - 1] > cand[v]; v--) {
-                                        int32_t tmp = cand[v];
-                                        cand[v] = cand[v - 1];
-                                        cand[v - 1] = tmp;
-                                    }
-                                int64_t I[3];
-                                block_rgb(J, s, B, bi, bx, by, I);
+                                const int32_t nl[4] = {rl[3], rl[4], rl[1], rl[6]};
+                                const int el[4] = {g.h, g.h, g.w, g.w};
+                                // candidate labels: distinct, != a, ascending
+                                // (sorting network; excluded values sink as INT_MAX)
+                                int32_t q0 = (nl[0] < 0 || nl[0] == a) ? INT32_MAX : nl[0];
+                                int32_t q1 = (nl[1] < 0 || nl[1] == a) ? INT32_MAX : nl[1];
+                                int32_t q2 = (nl[2] < 0 || nl[2] == a) ? INT32_MAX : nl[2];
+                                int32_t q3 = (nl[3] < 0 || nl[3] == a) ? INT32_MAX : nl[3];
+                                int32_t t0 = min(q0, q1), t1 = max(q0, q1), t2 = min(q2, q3), t3 = max(q2, q3);
+                                int32_t s0 = min(t0, t2), s2 = max(t0, t2), s1 = min(t1, t3), s3 = max(t1, t3);
+                                int32_t u1 = min(s1, s2), u2 = max(s1, s2);
+                                const int32_t cs[4] = {s0, u1, u2, s3};
                                 int bnd_a = 0;
 #pragma unroll
                                 for (int d = 0; d < 4; d++) bnd_a += (nl[d] >= 0 && nl[d] != a) ? el[d] : 0;
-                                int64_t estar = block_energy(mn, a, g, I, bnd_a, sc);
                                 best = a;
-                                for (int u = 0; u < nc; u++) {
-                                    int32_t k = cand[u];
-                                    if ((int64_t)mn[MN_STRIDE * (int64_t)k + 5] + g.m > sc.max_size) continue;
-                                    int bnd = 0;
+                                if (use_f64) {
+                                    const double dm = (double)g.m, dI0 = (double)I[0], dI1 = (double)I[1],
+                                                 dI2 = (double)I[2], dpx = (double)g.px, dpy = (double)g.py;
+                                    double estar = block_energy_f64(mn, a, dm, dI0, dI1, dI2, dpx, dpy, bnd_a, sc);
 #pragma unroll
-                                    for (int d = 0; d < 4; d++) bnd += (nl[d] >= 0 && nl[d] != k) ? el[d] : 0;
-                                    int64_t ek = block_energy(mn, k, g, I, bnd, sc);
-                                    if (ek < estar) {
-                                        estar = ek;
-                                        best = k;
+                                    for (int u = 0; u < 4; u++) {
+                                        const int32_t k = cs[u];
+                                        if (k == INT32_MAX || (u > 0 && k == cs[u - 1])) continue;
+                                        if ((int64_t)mn[MN_STRIDE * k + 5] + g.m > sc.max_size) continue;
+                                        int bnd = 0;
+#pragma unroll
+                                        for (int d = 0; d < 4; d++) bnd += (nl[d] >= 0 && nl[d] != k) ? el[d] : 0;
+                                        double ek = block_energy_f64(mn, k, dm, dI0, dI1, dI2, dpx, dpy, bnd, sc);
+                                        if (ek < estar) {
+                                            estar = ek;
+                                            best = k;
+                                        }
+                                    }
+                                } else {
+                                    int64_t estar = block_energy(mn, a, g, I, bnd_a, sc);
+#pragma unroll
+                                    for (int u = 0; u < 4; u++) {
+                                        const int32_t k = cs[u];
+                                        if (k == INT32_MAX || (u > 0 && k == cs[u - 1])) continue;
+                                        if ((int64_t)mn[MN_STRIDE * k + 5] + g.m > sc.max_size) continue;
+                                        int bnd = 0;
+#pragma unroll
+                                        for (int d = 0; d < 4; d++) bnd += (nl[d] >= 0 && nl[d] != k) ? el[d] : 0;
+                                        int64_t ek = block_energy(mn, k, g, I, bnd, sc);
+                                        if (ek < estar) {
+                                            estar = ek;
+                                            best = k;
+                                        }
                                     }
                                 }
                                 prop = best != a && pair_on(gate, a, best);
@@ -384,9 +509,14 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                     wave_count(&s_ctr[4], stopo);
                     int slot = wave_append(&s_nprop, prop);
                     if (slot >= 0) {
-                        J.props[3 * (int64_t)slot] = bi;
-                        J.props[3 * (int64_t)slot + 1] = a;
-                        J.props[3 * (int64_t)slot + 2] = best;
+                        Prop rec;
+                        rec.bi = bi;
+                        rec.a = a;
+                        rec.k = best;
+                        rec.pad = 0;
+                        rec.I = Ipk;
+                        if (slot < capp) l_props[slot] = rec;
+                        else g_props[slot] = rec;
                         atomicAdd(&fl[2 * (int64_t)a], (int32_t)m);
                         atomicAdd(&fl[2 * (int64_t)best + 1], (int32_t)m);
                     }
@@ -400,9 +530,9 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                     bool com = false;
                     int32_t bi = 0;
                     if (e < np) {
-                        bi = J.props[3 * (int64_t)e];
-                        int32_t a = J.props[3 * (int64_t)e + 1];
-                        int32_t k = J.props[3 * (int64_t)e + 2];
+                        Prop rec = e < capp ? l_props[e] : g_props[e];
+                        bi = rec.bi;
+                        const int32_t a = rec.a, k = rec.k;
                         // sizes from the class-start snapshot: the atomics of
                         // this phase are already moving the live counts
                         com = (int64_t)mn[MN_STRIDE * (int64_t)a + 5] - fl[2 * (int64_t)a] >= sc.min_size &&
@@ -410,18 +540,19 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                         if (com) {
                             int bx = bi % nbx, by = bi / nbx;
                             Geo g = block_geo(bx, by, B, W, H);
-                            int64_t I[3];
-                            block_rgb(J, s, B, bi, bx, by, I);
+                            const int64_t I0 = (int64_t)(rec.I & 0x1FFFFFull);
+                            const int64_t I1 = (int64_t)((rec.I >> 21) & 0x1FFFFFull);
+                            const int64_t I2 = (int64_t)(rec.I >> 42);
                             L[bi] = k;
                             int64_t *ra = st + 6 * (int64_t)a, *rk = st + 6 * (int64_t)k;
                             add64(ra + 0, -g.m);
                             add64(rk + 0, g.m);
-                            add64(ra + 1, -I[0]);
-                            add64(rk + 1, I[0]);
-                            add64(ra + 2, -I[1]);
-                            add64(rk + 2, I[1]);
-                            add64(ra + 3, -I[2]);
-                            add64(rk + 3, I[2]);
+                            add64(ra + 1, -I0);
+                            add64(rk + 1, I0);
+                            add64(ra + 2, -I1);
+                            add64(rk + 2, I1);
+                            add64(ra + 3, -I2);
+                            add64(rk + 3, I2);
                             add64(ra + 4, -g.px);
                             add64(rk + 4, g.px);
                             add64(ra + 5, -g.py);
@@ -431,7 +562,7 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                         }
                     }
                     int slot = wave_append(&s_nchg, com);
-                    if (slot >= 0) J.changed[slot] = bi;
+                    if (slot >= 0) list_put(l_chg, capx, J.changed, 0, slot, bi);
                     wave_count(&s_ctr[2], com);
                     {
                         uint64_t mk = __ballot(com);
@@ -448,8 +579,9 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                     refresh_means(st, mn, k, sc.F);
                 }
                 for (int e = tid; e < np; e += nt) {
-                    fl[2 * (int64_t)J.props[3 * (int64_t)e + 1]] = 0;
-                    fl[2 * (int64_t)J.props[3 * (int64_t)e + 2] + 1] = 0;
+                    Prop rec = e < capp ? l_props[e] : g_props[e];
+                    fl[2 * (int64_t)rec.a] = 0;
+                    fl[2 * (int64_t)rec.k + 1] = 0;
                 }
                 // every thread read np before the P2 barrier: safe to reset
                 if (tid == 0) {
@@ -473,30 +605,28 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
             wg_sync();
             if (tid < 9) s_cnt[tid] = 0;
             wg_sync();
+            // nine lanes per changed block, one per block of its 3x3
+            // neighbourhood; the first visitor of a block checks eligibility
             const int32_t stamp = t + 1;
-            for (int64_t q0 = 0; q0 < 9 * (int64_t)nchg; q0 += nt) {
-                int64_t q = q0 + tid;
-                bool e = false;
-                int cls = 0;
-                int32_t ni = 0;
-                if (q < 9 * (int64_t)nchg) {
-                    int32_t bi = J.changed[q / 9];
-                    int d = (int)(q % 9);
-                    int bx = bi % nbx + (d % 3) - 1, by = bi / nbx + (d / 3) - 1;
-                    if (bx >= 0 && by >= 0 && bx < nbx && by < nby) {
-                        ni = by * nbx + bx;
-                        if (atomicExch(&J.stamp[ni], stamp) != stamp) {
-                            e = eligible(L, bx, by, nbx, nby, gate);
-                            cls = 3 * (by % 3) + (bx % 3);
-                        }
-                    }
+            for (int q = tid; q < 9 * nchg; q += nt) {
+                int32_t bi = list_get(l_chg, capx, J.changed, 0, q / 9);
+                int d = q % 9;
+                int bx = bi % nbx + (d % 3) - 1, by = bi / nbx + (d / 3) - 1;
+                if (bx < 0 || by < 0 || bx >= nbx || by >= nby) continue;
+                int32_t ni = by * nbx + bx;
+                bool first;
+                if (use_bm) {
+                    uint32_t bit = 1u << (ni & 31);
+                    first = (atomicOr(&l_bm[ni >> 5], bit) & bit) == 0;
+                } else {
+                    first = atomicExch(&J.stamp[ni], stamp) != stamp;
                 }
-                for (int c = 0; c < 9; c++) {
-                    int slot = wave_append(&s_cnt[c], e && cls == c);
-                    if (slot >= 0) J.lists[c * capc + slot] = ni;
-                }
+                if (first && eligible(L, bx, by, nbx, nby, gate))
+                    class_push(s_cnt, l_lists, capl, J.lists, capg, 3 * (by % 3) + (bx % 3), ni);
             }
             wg_sync();
+            if (use_bm)
+                for (int i = tid; i < (int)((nb + 31) >> 5); i += nt) l_bm[i] = 0;
             if (tid == 0) s_nchg = 0;
             wg_sync();
         }
@@ -554,20 +684,19 @@ hipError_t launch_expand(const int32_t *L, int W, int H, int B, int32_t *out, in
     return hipGetLastError();
 }
 
-hipError_t launch_refine(const Job *jobs_dev, int n_jobs, const Sched &sc, int s_begin, int s_end,
-                         int flags, const uint32_t *lut_dev, bool lds, size_t lds_bytes, int threads,
+hipError_t launch_refine(const Job *jobs_dev, int n_jobs, const Sched &sc, const LdsPlan &lp,
+                         int s_begin, int s_end, int flags, const uint32_t *lut_dev, int threads,
                          hipStream_t stream)
 {
-    if (lds) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_refine<true>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_refine<true>, dim3((unsigned)n_jobs), dim3(threads), lds_bytes, stream,
-                           jobs_dev, sc, s_begin, s_end, flags, lut_dev);
-    } else {
-        hipLaunchKernelGGL(k_refine<false>, dim3((unsigned)n_jobs), dim3(threads), 0, stream,
-                           jobs_dev, sc, s_begin, s_end, flags, lut_dev);
-    }
+    const void *fn = lp.stats_lds ? (const void *)k_refine<true> : (const void *)k_refine<false>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp.total);
+    if (e != hipSuccess) return e;
+    if (lp.stats_lds)
+        hipLaunchKernelGGL(k_refine<true>, dim3((unsigned)n_jobs), dim3(threads), lp.total, stream,
+                           jobs_dev, sc, lp, s_begin, s_end, flags, lut_dev);
+    else
+        hipLaunchKernelGGL(k_refine<false>, dim3((unsigned)n_jobs), dim3(threads), lp.total, stream,
+                           jobs_dev, sc, lp, s_begin, s_end, flags, lut_dev);
     return hipGetLastError();
 }
 

@@ -10,7 +10,8 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librapid.so")
+# RAPID_LIB selects another build of the same C-ABI (e.g. an instrumented one)
+LIB_PATH = os.environ.get("RAPID_LIB") or os.path.join(_HERE, "librapid.so")
 
 ABI_VERSION = 1
 MAX_LEVELS = 4

@@ -187,3 +187,16 @@ def test_determinism_and_thread_counts(gpu_lib):
             os.environ["RAPID_THREADS"] = old
     for lab, rep in outs[1:]:
         assert (lab == outs[0][0]).all() and rep == outs[0][1]
+
+
+def test_int64_and_fp64_energy_paths(ctx):
+    """2000x64 image, blocks 64..1 and w_pos = 100: the worst-case block
+    energy exceeds 2^53 at B >= 8 (exact int64 evaluation) and stays below it
+    at B <= 4 (exact fp64 evaluation); both must match the oracle."""
+    img = synth.voronoi_gradient(2000, 64, seed=77, regions=(20, 40))
+    p = params.default_params(2000, 64, 20, levels=[(1, [64, 32, 16, 8, 4, 2, 1])], min_size=100)
+    p.update(w_col=50, w_pos=100, w_bnd=4096)
+    _say("case: 2000x64 int64 and fp64 energy paths")
+    got, rep = _gpu_segment(ctx, img, p)
+    ref, _, ref_rep = oracle.segment(img, p)
+    _assert_same(got, rep, ref, ref_rep, "int64/fp64 paths")
