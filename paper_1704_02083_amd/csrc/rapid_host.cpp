@@ -162,7 +162,7 @@ rapid_status make_sched(const rapid_params *p, Sched *sc, int32_t level_first[RA
 }
 
 // Largest intermediate magnitude of E' for blocks of size B (see
-// block_energy / block_energy_f64): every product and partial sum is bounded
+// block_energy / energy_md): every product and partial sum is bounded
 // by the sum of the three weighted terms' worst cases.
 __int128 energy_bound(const Sched &sc, int B, int32_t W, int32_t H)
 {
@@ -186,6 +186,8 @@ void set_exactness(Sched &sc, int32_t W, int32_t H)
     sc.d_wp = (double)sc.w_pos;
     sc.d_wb = std::ldexp((double)sc.w_bnd, 2 * sc.F);
     sc.d_fs = std::ldexp(1.0, sc.F + 1);
+    sc.d_wcfs = sc.d_wc * sc.d_fs;
+    sc.d_wpfs = sc.d_wp * sc.d_fs;
 }
 
 // Worst-case |E'| of a block must stay below 2^62 so that the int64 block
@@ -241,7 +243,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
     size_t bytes = 0;
     size_t off_lab[2], off_sums[MAXST], off_lists, off_props, off_changed, off_stamp;
-    size_t off_stats, off_means, off_flow, off_touched, off_rep;
+    size_t off_stats, off_means, off_flow, off_mdbl, off_rep;
     int64_t capc = 0;
 };
 
@@ -270,7 +272,7 @@ Layout plan(int32_t W, int32_t H, int32_t K, const Sched &sc)
     L.off_stats = take(8 * 6 * (size_t)K);
     L.off_means = take(4 * MN_STRIDE * (size_t)K);
     L.off_flow = take(4 * 2 * (size_t)K);
-    L.off_touched = take(4 * 2 * (size_t)K);
+    L.off_mdbl = take(8 * MD_STRIDE * (size_t)K);
     L.off_rep = take(sizeof(rapid_stage_report) * MAXST);
     L.bytes = o;
     return L;
@@ -301,7 +303,7 @@ void fill_job(Job &J, char *base, const Layout &L, const rapid_image *img, int32
     J.stats = reinterpret_cast<int64_t *>(base + L.off_stats);
     J.means = reinterpret_cast<int32_t *>(base + L.off_means);
     J.flow = reinterpret_cast<int32_t *>(base + L.off_flow);
-    J.touched = reinterpret_cast<int32_t *>(base + L.off_touched);
+    J.mdbl = reinterpret_cast<double *>(base + L.off_mdbl);
     J.rep = reinterpret_cast<rapid_stage_report *>(base + L.off_rep);
     J.gate = gate;
 }

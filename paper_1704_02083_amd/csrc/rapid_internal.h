@@ -21,6 +21,7 @@ struct Sched {
     int32_t F, max_sweeps;
     int64_t min_size, max_size, w_col, w_pos, w_bnd;
     double d_wc, d_wp, d_wb, d_fs;   // w_col, w_pos, w_bnd 2^(2F), 2^(F+1) as doubles
+    double d_wcfs, d_wpfs;           // w_col 2^(F+1), w_pos 2^(F+1)
 };
 
 // A proposal: block, source and destination labels, packed colour sum of
@@ -58,7 +59,7 @@ struct Job {
     int64_t *stats;          // K x 6 int64: n, S_r, S_g, S_b, T_x, T_y
     int32_t *means;          // K x MN_STRIDE (global working set)
     int32_t *flow;           // K x 2 out/in (global working set)
-    int32_t *touched;        // K flags + K list (global working set)
+    double *mdbl;            // K x MD_STRIDE (global working set)
     rapid_stage_report *rep; // per stage
     const uint8_t *gate;     // K bytes or null
 };
@@ -73,8 +74,11 @@ hipError_t launch_refine(const Job *jobs_dev, int n_jobs, const Sched &sc, const
 
 // per-superpixel means record: c_r c_g c_b mu_x mu_y n (int32)
 constexpr int MN_STRIDE = 6;
+// per-superpixel fp64 energy record: A c'_r c'_g c'_b mu'_x mu'_y
+constexpr int MD_STRIDE = 6;
 
-// bytes of LDS per superpixel when the statistics live in LDS
-constexpr size_t LDS_PER_SP = 6 * 8 + MN_STRIDE * 4 + 2 * 4 + 4 + 4;
+// bytes of LDS per superpixel when the statistics live in LDS: sums,
+// fp64 energy record, means record, flow counters
+constexpr size_t LDS_PER_SP = 6 * 8 + MD_STRIDE * 8 + MN_STRIDE * 4 + 2 * 4;
 
 }  // namespace rapid

@@ -13,7 +13,7 @@
 //     for each sweep: for each of the 9 classes (bx mod 3, by mod 3):
 //       P1 propose from the class-start state (size, topology, argmin E')
 //       P2 class-wide size filter, commit, integer stat moves
-//       P3 refresh means of touched superpixels, clear the flow counters
+//       P3 refresh means of the moved superpixels, clear the flow counters
 //     rebuild the boundary set around changed blocks
 #include "rapid_internal.h"
 
@@ -107,47 +107,52 @@ __device__ __forceinline__ int64_t block_energy(const int32_t *mn, int k, const 
 // Means in fixed point, rounded half up, plus the size n: the class-start
 // snapshot that every proposal and every size-filter decision of the next
 // class reads while the integer atomics of that class update the sums.
-// The same E' in fp64.  Used only where the host has proven that every
-// product and sum below is an integer of magnitude < 2^53, so each fp64
-// operation is exact and the result equals the int64 one bit for bit.
-__device__ __forceinline__ double block_energy_f64(const int32_t *mn, int k, double m, double I0,
-                                                   double I1, double I2, double px, double py,
-                                                   int bnd, const Sched &sc)
-{
-    const int32_t *c = mn + MN_STRIDE * k;
-    double c0 = c[0], c1 = c[1], c2 = c[2], mx = c[3], my = c[4];
-    double col = fma(c0, c0, fma(c1, c1, c2 * c2));
-    double dot = fma(c0, I0, fma(c1, I1, c2 * I2));
-    double e_col = fma(m, col, -(sc.d_fs * dot));
-    double pos = fma(mx, mx, my * my);
-    double pdot = fma(mx, px, my * py);
-    double e_pos = fma(m, pos, -(sc.d_fs * pdot));
-    return fma(sc.d_wc, e_col, fma(sc.d_wp, e_pos, sc.d_wb * (double)bnd));
-}
-
-// floor(num / den) for 0 <= num, 0 < den < 2^53: fp64 quotient, then one
-// exact correction step each way (products stay below 2^53).
-__device__ __forceinline__ int64_t floor_div_f64(int64_t num, int64_t den)
-{
-    double dn = (double)num, dd = (double)den;
-    double q = floor(dn / dd);
-    if (q * dd > dn) q -= 1.0;
-    else if ((q + 1.0) * dd <= dn) q += 1.0;
-    return (int64_t)q;
-}
-
-// Means in fixed point, rounded half up, plus the size n: the class-start
-// snapshot that every proposal and every size-filter decision of the next
-// class reads while the integer atomics of that class update the sums.
-__device__ __forceinline__ void refresh_means(const int64_t *st, int32_t *mn, int k, int F)
+// Refresh superpixel k from its exact integer sums (st[k]):
+//  mn[k]: means in fixed point, floor((2^(F+1) S + n) / (2 n)) (rounded half
+//         up), and the size n -- the class-start snapshot every proposal and
+//         every size-filter decision of the next class reads;
+//  md[k]: the same means folded into the fp64 form of E',
+//         A = w_col |c|^2 + w_pos |mu|^2, c' = w_col 2^(F+1) c,
+//         mu' = w_pos 2^(F+1) mu, so that E' = m A - <c', I> - <mu', P>
+//         + w_bnd 2^(2F) bnd.  Used only where every term is an integer
+//         below 2^53 (then exact).
+// The quotients use one reciprocal and an exact correction step (all
+// products stay below 2^53).
+__device__ __forceinline__ void refresh_sp(const int64_t *st, int32_t *mn, double *md, int k,
+                                           const Sched &sc)
 {
     const int64_t *r = st + 6 * (int64_t)k;
-    int64_t n = r[0];
-    int64_t d = 2 * n;
-    int32_t *o = mn + MN_STRIDE * (int64_t)k;
+    const int64_t n = r[0];
+    const double dd = (double)(2 * n), dn0 = (double)n;
+    const double rcp = 1.0 / dd;
+    int32_t *o = mn + MN_STRIDE * k;
+    double q[5];
 #pragma unroll
-    for (int q = 0; q < 5; q++) o[q] = (int32_t)floor_div_f64((r[1 + q] << (F + 1)) + n, d);
+    for (int j = 0; j < 5; j++) {
+        const double dn = fma((double)r[1 + j], sc.d_fs, dn0);   // 2^(F+1) S + n, exact
+        double v = floor(dn * rcp);
+        if (v * dd > dn) v -= 1.0;
+        else if ((v + 1.0) * dd <= dn) v += 1.0;
+        q[j] = v;
+        o[j] = (int32_t)v;
+    }
     o[5] = (int32_t)n;
+    double *d = md + MD_STRIDE * k;
+    d[0] = fma(sc.d_wc, fma(q[0], q[0], fma(q[1], q[1], q[2] * q[2])), sc.d_wp * fma(q[3], q[3], q[4] * q[4]));
+    d[1] = sc.d_wcfs * q[0];
+    d[2] = sc.d_wcfs * q[1];
+    d[3] = sc.d_wcfs * q[2];
+    d[4] = sc.d_wpfs * q[3];
+    d[5] = sc.d_wpfs * q[4];
+}
+
+// fp64 E' from the folded superpixel record (see refresh_sp).
+__device__ __forceinline__ double energy_md(const double *md, int k, double m, double I0, double I1,
+                                            double I2, double px, double py, double wbnd)
+{
+    const double *d = md + MD_STRIDE * k;
+    const double lin = fma(d[1], I0, fma(d[2], I1, fma(d[3], I2, fma(d[4], px, d[5] * py))));
+    return fma(m, d[0], -lin) + wbnd;
 }
 
 __device__ __forceinline__ int32_t lab_at(const int32_t *L, int bx, int by, int nbx, int nby)
@@ -257,26 +262,25 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
     extern __shared__ __align__(16) char smem[];
     __shared__ uint32_t s_lut[8];
     __shared__ int32_t s_cnt[9];
-    __shared__ int32_t s_nprop, s_nchg, s_ntch, s_commits;
+    __shared__ int32_t s_nprop, s_nchg;
     __shared__ unsigned long long s_ctr[5];   // active proposals commits skip_min skip_topo
 
     const Job &J = jobs[blockIdx.x];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int W = J.W, H = J.H, K = J.K;
     int64_t *st;
-    int32_t *mn, *fl, *tch, *tl;
+    double *md;
+    int32_t *mn, *fl;
     if (LDS) {
         st = reinterpret_cast<int64_t *>(smem);
-        mn = reinterpret_cast<int32_t *>(st + 6 * (int64_t)K);  // K x MN_STRIDE
+        md = reinterpret_cast<double *>(st + 6 * (int64_t)K);   // K x MD_STRIDE
+        mn = reinterpret_cast<int32_t *>(md + MD_STRIDE * (int64_t)K);  // K x MN_STRIDE
         fl = mn + MN_STRIDE * (int64_t)K;
-        tch = fl + 2 * (int64_t)K;
-        tl = tch + K;
     } else {
         st = J.stats;
+        md = J.mdbl;
         mn = J.means;
         fl = J.flow;
-        tch = J.touched;
-        tl = J.touched + K;
     }
     int32_t *l_lists = reinterpret_cast<int32_t *>(smem + lp.off_lists);
     Prop *l_props = reinterpret_cast<Prop *>(smem + lp.off_props);
@@ -290,11 +294,8 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
     if (tid == 0) {
         s_nprop = 0;
         s_nchg = 0;
-        s_ntch = 0;
-        s_commits = 0;
     }
     for (int64_t i = tid; i < 2 * (int64_t)K; i += nt) fl[i] = 0;
-    for (int64_t i = tid; i < K; i += nt) tch[i] = 0;
     for (int i = tid; i < lp.bm_words; i += nt) l_bm[i] = 0;
 
     if (flags & FLAG_INIT) {
@@ -326,7 +327,7 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
         for (int64_t i = tid; i < 6 * (int64_t)K; i += nt) st[i] = J.stats[i];
     }
     wg_sync();
-    for (int64_t k = tid; k < K; k += nt) refresh_means(st, mn, (int)k, sc.F);
+    for (int k = tid; k < K; k += nt) refresh_sp(st, mn, md, k, sc);
     wg_sync();
 
     for (int s = s_begin; s < s_end; s++) {
@@ -399,12 +400,12 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
         wg_sync();
 
         int sweeps = 0, converged = 0;
+        int n_smin = 0, n_stopo = 0;   // this thread's skip counts of the stage
         for (int t = 0; t < sc.max_sweeps; t++) {
             if (tid == 0) {
                 int64_t tot = 0;
                 for (int c = 0; c < 9; c++) tot += s_cnt[c];
                 s_ctr[0] += (unsigned long long)tot;
-                s_commits = 0;
             }
             wg_sync();
             for (int c = 0; c < 9; c++) {
@@ -469,7 +470,7 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                                 if (use_f64) {
                                     const double dm = (double)g.m, dI0 = (double)I[0], dI1 = (double)I[1],
                                                  dI2 = (double)I[2], dpx = (double)g.px, dpy = (double)g.py;
-                                    double estar = block_energy_f64(mn, a, dm, dI0, dI1, dI2, dpx, dpy, bnd_a, sc);
+                                    double estar = energy_md(md, a, dm, dI0, dI1, dI2, dpx, dpy, sc.d_wb * (double)bnd_a);
 #pragma unroll
                                     for (int u = 0; u < 4; u++) {
                                         const int32_t k = cs[u];
@@ -478,7 +479,7 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                                         int bnd = 0;
 #pragma unroll
                                         for (int d = 0; d < 4; d++) bnd += (nl[d] >= 0 && nl[d] != k) ? el[d] : 0;
-                                        double ek = block_energy_f64(mn, k, dm, dI0, dI1, dI2, dpx, dpy, bnd, sc);
+                                        double ek = energy_md(md, k, dm, dI0, dI1, dI2, dpx, dpy, sc.d_wb * (double)bnd);
                                         if (ek < estar) {
                                             estar = ek;
                                             best = k;
@@ -505,8 +506,8 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                             }
                         }
                     }
-                    wave_count(&s_ctr[3], smin);
-                    wave_count(&s_ctr[4], stopo);
+                    n_smin += smin;
+                    n_stopo += stopo;
                     int slot = wave_append(&s_nprop, prop);
                     if (slot >= 0) {
                         Prop rec;
@@ -524,64 +525,55 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                 wg_sync();
                 const int np = s_nprop;
                 if (np == 0) continue;   // uniform: nothing proposed in this class
-                // ---- P2: class-wide size filter, commit, stat moves
-                for (int e0 = 0; e0 < np; e0 += nt) {
-                    int e = e0 + tid;
+                // ---- P2: class-wide size filter, commit, stat moves.  Two
+                // lanes per proposal: lane 0 moves the block's sums out of the
+                // source a (and writes the label), lane 1 into the target k.
+                for (int e0 = 0; e0 < 2 * np; e0 += nt) {
+                    const int e = (e0 + tid) >> 1, side = (e0 + tid) & 1;
                     bool com = false;
                     int32_t bi = 0;
                     if (e < np) {
-                        Prop rec = e < capp ? l_props[e] : g_props[e];
+                        const Prop rec = e < capp ? l_props[e] : g_props[e];
                         bi = rec.bi;
                         const int32_t a = rec.a, k = rec.k;
                         // sizes from the class-start snapshot: the atomics of
                         // this phase are already moving the live counts
-                        com = (int64_t)mn[MN_STRIDE * (int64_t)a + 5] - fl[2 * (int64_t)a] >= sc.min_size &&
-                              (int64_t)mn[MN_STRIDE * (int64_t)k + 5] + fl[2 * (int64_t)k + 1] <= sc.max_size;
+                        com = (int64_t)mn[MN_STRIDE * a + 5] - fl[2 * a] >= sc.min_size &&
+                              (int64_t)mn[MN_STRIDE * k + 5] + fl[2 * k + 1] <= sc.max_size;
                         if (com) {
-                            int bx = bi % nbx, by = bi / nbx;
-                            Geo g = block_geo(bx, by, B, W, H);
-                            const int64_t I0 = (int64_t)(rec.I & 0x1FFFFFull);
-                            const int64_t I1 = (int64_t)((rec.I >> 21) & 0x1FFFFFull);
-                            const int64_t I2 = (int64_t)(rec.I >> 42);
-                            L[bi] = k;
-                            int64_t *ra = st + 6 * (int64_t)a, *rk = st + 6 * (int64_t)k;
-                            add64(ra + 0, -g.m);
-                            add64(rk + 0, g.m);
-                            add64(ra + 1, -I0);
-                            add64(rk + 1, I0);
-                            add64(ra + 2, -I1);
-                            add64(rk + 2, I1);
-                            add64(ra + 3, -I2);
-                            add64(rk + 3, I2);
-                            add64(ra + 4, -g.px);
-                            add64(rk + 4, g.px);
-                            add64(ra + 5, -g.py);
-                            add64(rk + 5, g.py);
-                            if (atomicExch(&tch[a], 1) == 0) tl[atomicAdd(&s_ntch, 1)] = a;
-                            if (atomicExch(&tch[k], 1) == 0) tl[atomicAdd(&s_ntch, 1)] = k;
+                            const int bx = bi % nbx, by = bi / nbx;
+                            const Geo g = block_geo(bx, by, B, W, H);
+                            const int64_t sg = side ? 1 : -1;
+                            int64_t *rr = st + 6 * (int64_t)(side ? k : a);
+                            add64(rr + 0, sg * g.m);
+                            add64(rr + 1, sg * (int64_t)(rec.I & 0x1FFFFFull));
+                            add64(rr + 2, sg * (int64_t)((rec.I >> 21) & 0x1FFFFFull));
+                            add64(rr + 3, sg * (int64_t)(rec.I >> 42));
+                            add64(rr + 4, sg * g.px);
+                            add64(rr + 5, sg * g.py);
+                            if (side == 0) {
+                                L[bi] = k;
+                                // P3 refreshes the superpixels of committed moves
+                                if (e < capp) l_props[e].pad = 1;
+                                else g_props[e].pad = 1;
+                            }
                         }
                     }
-                    int slot = wave_append(&s_nchg, com);
+                    // the changed list doubles as the sweep's commit count
+                    int slot = wave_append(&s_nchg, com && side == 0);
                     if (slot >= 0) list_put(l_chg, capx, J.changed, 0, slot, bi);
-                    wave_count(&s_ctr[2], com);
-                    {
-                        uint64_t mk = __ballot(com);
-                        if (mk && lane_id() == __ffsll((unsigned long long)mk) - 1)
-                            atomicAdd(&s_commits, __popcll(mk));
-                    }
                 }
                 wg_sync();
-                // ---- P3: refresh means of touched superpixels, clear flows
-                const int ntouch = s_ntch;
-                for (int e = tid; e < ntouch; e += nt) {
-                    int32_t k = tl[e];
-                    tch[k] = 0;
-                    refresh_means(st, mn, k, sc.F);
-                }
-                for (int e = tid; e < np; e += nt) {
-                    Prop rec = e < capp ? l_props[e] : g_props[e];
-                    fl[2 * (int64_t)rec.a] = 0;
-                    fl[2 * (int64_t)rec.k + 1] = 0;
+                // ---- P3: refresh the superpixels of committed moves (lane 0 of
+                // a proposal its source, lane 1 its target; a superpixel in
+                // several moves is refreshed several times with identical
+                // values) and clear the flow counters
+                for (int q = tid; q < 2 * np; q += nt) {
+                    const int e = q >> 1, side = q & 1;
+                    const Prop rec = e < capp ? l_props[e] : g_props[e];
+                    const int32_t sp = side ? rec.k : rec.a;
+                    fl[2 * sp + side] = 0;
+                    if (rec.pad) refresh_sp(st, mn, md, sp, sc);
                 }
                 // every thread read np before the P2 barrier: safe to reset
                 if (tid == 0) {
@@ -589,13 +581,11 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                     s_nprop = 0;
                 }
                 wg_sync();
-                // ntouch was read after the P2 barrier; the next writer of
-                // s_ntch (P2 of the next class) runs after the next barrier
-                if (tid == 0) s_ntch = 0;
             }
             wg_sync();
             sweeps = t + 1;
-            const int commits = s_commits;
+            const int commits = s_nchg;
+            if (tid == 0) s_ctr[2] += (unsigned long long)commits;
             if (commits == 0) {
                 converged = 1;
                 break;
@@ -630,6 +620,9 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
             if (tid == 0) s_nchg = 0;
             wg_sync();
         }
+        if (n_smin) atomicAdd(&s_ctr[3], (unsigned long long)n_smin);
+        if (n_stopo) atomicAdd(&s_ctr[4], (unsigned long long)n_stopo);
+        wg_sync();
         if (tid == 0) {
             rapid_stage_report r;
             r.level = sc.level[s];
