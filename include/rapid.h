@@ -165,6 +165,75 @@ void rapid_state_destroy(rapid_state *st);   /* NULL-safe */
  * RAPID_ESTATE when the context does not time or nothing ran yet. */
 rapid_status rapid_last_timings(rapid_ctx *ctx, rapid_timings *out);
 
+/* ---------------------------------------------------------------- gate
+ * The prediction step of Algorithm RAPID: at the start of the gate level
+ * every superpixel gets a feature vector x and a classifier decides
+ * y = [h(x) >= thresh] (Eq. (6)); from then on a move between superpixels a
+ * and k is allowed only when y_a or y_k is set (Eq. (7), read per
+ * superpixel).  h is a multilayer perceptron 16 -> 64 -> 64 -> 1 (ReLU,
+ * logit output) with 5313 bf16 parameters: W1 (64x16, row = output), b1
+ * (64), W2 (64x64), b2 (64), w3 (64), b3 (1).
+ *
+ * Features (16 float32 per superpixel, computed from exact integer sums at
+ * the last stage before the gate): mean colour / 255 (3), colour standard
+ * deviation / 64 (3), size / A, boundary length / (4 sqrt A), boundary
+ * length^2 / (16 size), centroid drift from the initial cell centre /
+ * sqrt A, max / edge-weighted rms / min colour contrast to neighbours /
+ * (255 2^F) (3), pixels moved so far / size, max colour deviation / 64, 1;
+ * A = floor(W H / (gx gy)). */
+typedef struct {
+    const uint16_t *w_bf16_dev;   /* 5313 bf16 parameters (device)            */
+    float thresh;                 /* decision threshold on the logit (0: p >= 1/2) */
+} rapid_gate_model;
+
+/* Like rapid_segment_batch, with the gate: levels before params->gate_level
+ * run plain, then features and the network decide the gate bits, then the
+ * remaining levels run gated.  features_dev (nullable) receives the
+ * features of all images' superpixels, image after image (sum of gx*gy rows
+ * of 16 floats); gate_dev (nullable) the gate bits in the same order.
+ * gate_level must be in [1, n_levels).  A model with non-finite weights is
+ * refused: the images are segmented plain and RAPID_EGATE is returned. */
+rapid_status rapid_segment_gated(rapid_ctx *ctx, const rapid_image *imgs, int32_t n,
+                                 const rapid_params *params, const rapid_gate_model *model,
+                                 float *features_dev, uint8_t *gate_dev, rapid_report *reports);
+
+/* State tracking for training data: involved_dev (nullable, gx*gy bytes)
+ * has bytes set to 1 for superpixels that are the source or target of any
+ * proposal in later rapid_refine_level calls; moved_dev (nullable, gx*gy
+ * int64) accumulates the pixels moved into or out of each superpixel.  Both
+ * are caller-owned and must be zeroed by the caller. */
+rapid_status rapid_state_track(rapid_state *st, uint8_t *involved_dev, int64_t *moved_dev);
+
+/* The 16 gate features of the state's superpixels at its current stage
+ * (X_dev: gx*gy rows of 16 float32).  Feature 13 uses the moved counts
+ * tracked so far (zero when not tracked). */
+rapid_status rapid_state_features(rapid_ctx *ctx, rapid_state *st, float *X_dev);
+
+/* Network forward pass on n feature rows: logits_dev (nullable) receives
+ * h(x); gate_dev (nullable) receives [h(x) >= thresh]. */
+rapid_status rapid_mlp_forward(rapid_ctx *ctx, const float *X_dev, int64_t n, const uint16_t *w_bf16_dev,
+                               float thresh, float *logits_dev, uint8_t *gate_dev);
+
+/* Gradient of the mean binary cross-entropy with logits over the nb
+ * samples idx_dev[0..nb) of (X_dev, t_dev): grads_dev receives 5313
+ * floats; logits_dev (nullable) the nb logits.  Deterministic. */
+rapid_status rapid_mlp_grad(rapid_ctx *ctx, const float *X_dev, const uint8_t *t_dev, const int32_t *idx_dev,
+                            int32_t nb, const uint16_t *w_bf16_dev, float *grads_dev, float *logits_dev);
+
+typedef struct {
+    int32_t epochs;       /* passes of floor(n / batch) batches               */
+    int32_t batch;        /* even; half positive, half negative samples       */
+    float lr, beta1, beta2, eps;   /* Adam (Kingma & Ba, 2015)                 */
+    uint64_t seed;        /* sample order                                     */
+} rapid_train_cfg;
+
+/* Train the gate network on n samples (features X_dev, targets t_dev in
+ * {0,1}) with balanced batches and Adam.  master_dev: 5313 float32 master
+ * weights, initial values in, trained values out; w_bf16_dev receives their
+ * bf16 copy. */
+rapid_status rapid_gate_train(rapid_ctx *ctx, const float *X_dev, const uint8_t *t_dev, int64_t n,
+                              const rapid_train_cfg *cfg, float *master_dev, uint16_t *w_bf16_dev);
+
 /* Grid of a target count (see rapid_params.K).  Host only, no device. */
 rapid_status rapid_grid(int32_t W, int32_t H, int32_t K, int32_t *gx, int32_t *gy);
 

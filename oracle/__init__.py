@@ -38,7 +38,8 @@ def build(force: bool = False) -> str:
     ):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(
-            ["gcc", "-O2", "-std=gnu11", "-Wall", "-shared", "-fPIC", "-o", tmp, _SRC]
+            ["gcc", "-O2", "-std=gnu11", "-Wall", "-ffp-contract=off", "-shared", "-fPIC", "-o", tmp,
+             _SRC, "-lm"]
         )
         os.replace(tmp, _LIB)
     return _LIB
@@ -88,6 +89,10 @@ def lib():
         L.orc_block_energy.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, C.POINTER(OrcParams), P,
                                        C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
         L.orc_block_energy.restype = C.c_int64
+        L.orc_segment_ex.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, C.POINTER(OrcParams), P,
+                                     P, P, P, C.c_int32, C.c_int32, P, P]
+        L.orc_features.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, P, C.c_int32, P, P,
+                                   C.c_int32, C.c_int32, C.c_int32, P]
     return _lib
 
 
@@ -148,9 +153,11 @@ def n_superpixels(W: int, H: int, d: dict) -> int:
 
 
 def segment(rgb: np.ndarray, d: dict, gate: np.ndarray | None = None,
-            debug: bool = False, shuffle_seed: int = 0):
+            debug: bool = False, shuffle_seed: int = 0, track: bool = False):
     """Run the full schedule.  rgb: (H, W, 3) uint8.  Returns (labels (H, W)
-    int32, stats (K', 6) int64, list of per-stage report dicts)."""
+    int32, stats (K', 6) int64, list of per-stage report dicts); with track,
+    also involved (K',) uint8 (source or target of a proposal at a level >=
+    gate_level) and moved (K',) int64 (pixels moved in or out)."""
     rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
     H, W, _ = rgb.shape
     K = n_superpixels(W, H, d)
@@ -163,11 +170,31 @@ def segment(rgb: np.ndarray, d: dict, gate: np.ndarray | None = None,
     if gate is not None:
         g = np.ascontiguousarray(gate, dtype=np.uint8)
         assert g.shape == (K,)
-    rc = lib().orc_segment(_ptr(rgb), W, H, 3 * W, C.byref(p), _ptr(g), _ptr(labels), _ptr(stats),
-                           reps, nst, int(debug))
+    inv = np.zeros(K, np.uint8) if track else None
+    mov = np.zeros(K, np.int64) if track else None
+    rc = lib().orc_segment_ex(_ptr(rgb), W, H, 3 * W, C.byref(p), _ptr(g), _ptr(labels),
+                              _ptr(stats), reps, nst, int(debug), _ptr(inv), _ptr(mov))
     if rc < 0:
         raise RuntimeError("orc_segment failed rc=%d" % rc)
-    return labels, stats, [reps[i].as_dict() for i in range(rc)]
+    out = (labels, stats, [reps[i].as_dict() for i in range(rc)])
+    return out + (inv, mov) if track else out
+
+
+def features(rgb: np.ndarray, labels: np.ndarray, B: int, stats: np.ndarray,
+             moved: np.ndarray | None, gx: int, gy: int, F: int = 4) -> np.ndarray:
+    """Sixteen gate features per superpixel (see orc_features)."""
+    rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    stats = np.ascontiguousarray(stats, dtype=np.int64)
+    H, W, _ = rgb.shape
+    K = gx * gy
+    out = np.empty((K, 16), np.float32)
+    mv = None if moved is None else np.ascontiguousarray(moved, dtype=np.int64)
+    rc = lib().orc_features(_ptr(rgb), W, H, 3 * W, _ptr(labels), B, _ptr(stats), _ptr(mv),
+                            gx, gy, F, _ptr(out))
+    if rc < 0:
+        raise RuntimeError("orc_features failed rc=%d" % rc)
+    return out
 
 
 def propose_class(rgb: np.ndarray, d: dict, labels: np.ndarray, K: int, B: int, cls: int,

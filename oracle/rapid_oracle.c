@@ -42,6 +42,7 @@
  *     orc_init_labels).
  */
 #include "rapid_oracle.h"
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -178,6 +179,8 @@ typedef struct {
     int32_t *bl;               /* block labels (label matrix L at this stage) */
     int64_t *bs;               /* block colour sums, 3 per block */
     const uint8_t *gate;       /* NULL: every pair active */
+    uint8_t *involved;         /* optional: superpixels in a proposal        */
+    int64_t *moved;            /* optional: pixels moved in or out, per label */
 } state;
 
 static inline int64_t div_round(int64_t num, int64_t n, int F)
@@ -464,6 +467,7 @@ static int64_t propose(state *s, int32_t cls, const uint8_t *active,
             if (ek < estar) { estar = ek; best = k; }
         }
         if (best != a && pair_active(s, a, best)) {
+            if (s->involved) { s->involved[a] = 1; s->involved[best] = 1; }
             out[np].b = (int32_t)bi; out[np].a = a; out[np].k = best;
             i128 de = estar - e0;   /* < 0; saturated for reporting only */
             out[np].de = de < -(i128)INT64_MAX ? -INT64_MAX : (int64_t)de;
@@ -542,6 +546,7 @@ static int run_stage(state *s, int32_t level, int32_t B, int32_t *lab,
                 s->T[2 * (int64_t)a] -= b.px_; s->T[2 * (int64_t)k] += b.px_;
                 s->T[2 * (int64_t)a + 1] -= b.py_; s->T[2 * (int64_t)k + 1] += b.py_;
                 changed[bi] = 1; touched[a] = 1; touched[k] = 1;
+                if (s->moved) { s->moved[a] += b.m; s->moved[k] += b.m; }
                 de_sum += block_energy(s, bx, by, k) - block_energy(s, bx, by, a);
                 sweep_commits++;
                 rep->commits++;
@@ -621,10 +626,30 @@ static int check_params(const orc_params *p, int32_t W, int32_t H)
  * level only gated pairs move.  labels: W*H int32 out.  stats_out: K'*6 int64
  * (n, S0, S1, S2, Tx, Ty), may be NULL.  rep: one entry per stage, may be
  * NULL.  Returns the number of stages run, or an error code. */
+int orc_segment_ex(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
+                   const orc_params *p, const uint8_t *gate,
+                   int32_t *labels, int64_t *stats_out,
+                   orc_stage_report *rep, int32_t max_rep, int32_t debug,
+                   uint8_t *involved, int64_t *moved);
+
 int orc_segment(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
                 const orc_params *p, const uint8_t *gate,
                 int32_t *labels, int64_t *stats_out,
                 orc_stage_report *rep, int32_t max_rep, int32_t debug)
+{
+    return orc_segment_ex(rgb, W, H, stride, p, gate, labels, stats_out, rep, max_rep, debug,
+                          NULL, NULL);
+}
+
+/* As orc_segment, plus two optional per-superpixel outputs:
+ *   involved[k] = 1 when k is the source or target of any proposal at a
+ *                 level >= gate_level (the gate's training target), else 0;
+ *   moved[k]    = pixels moved into or out of k by committed moves. */
+int orc_segment_ex(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
+                   const orc_params *p, const uint8_t *gate,
+                   int32_t *labels, int64_t *stats_out,
+                   orc_stage_report *rep, int32_t max_rep, int32_t debug,
+                   uint8_t *involved, int64_t *moved)
 {
     int rc = check_params(p, W, H);
     if (rc) return rc;
@@ -651,8 +676,12 @@ int orc_segment(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
         refresh_means(&s, k);
     }
     int nrep = 0;
+    if (involved) memset(involved, 0, K);
+    if (moved) memset(moved, 0, sizeof(int64_t) * K);
+    s.moved = moved;
     for (int l = 0; l < p->n_levels; l++) {
         s.gate = (gate && p->gate_level >= 0 && l >= p->gate_level) ? gate : NULL;
+        s.involved = (involved && p->gate_level >= 0 && l >= p->gate_level) ? involved : NULL;
         for (int st = 0; st < p->n_stages[l]; st++) {
             orc_stage_report r;
             rc = run_stage(&s, l, p->stages[l][st] * p->factor[l], labels, &r, debug);
@@ -737,4 +766,105 @@ int64_t orc_block_energy(const uint8_t *rgb, int32_t W, int32_t H, int64_t strid
     }
     free(s.n); free(s.S); free(s.T); free(s.c); free(s.mu); free(s.bl); free(s.bs);
     return r;
+}
+
+
+/* ------------------------------------------------------- gate features */
+
+/* Sixteen features of every superpixel at the gate point (Eq. (6) needs a
+ * feature vector x per superpixel; the paper's classifier uses absolute and
+ * comparative colour and region dissimilarity -- these are this project's
+ * own choice along those lines, all from exact integer accumulators):
+ *   0-2  mean colour / 255
+ *   3-5  colour standard deviation / 64 (pixel second moments)
+ *   6    size / nominal area A
+ *   7    boundary length / (4 sqrt A)
+ *   8    compactness: boundary length^2 / (16 size)
+ *   9    centroid drift from the initial grid cell centre / sqrt A
+ *   10-12 max, edge-weighted rms and min colour contrast to neighbours
+ *        (distance of fixed-point means) / (255 2^F)
+ *   13   pixels moved in or out so far / size
+ *   14   max of features 3-5
+ *   15   1
+ * labels: pixel labels constant on blocks of size B (the last stage before
+ * the gate); stats: K x 6 (n, S, T); moved: K (may be NULL: zeros). */
+int orc_features(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
+                 const int32_t *labels, int32_t B, const int64_t *stats, const int64_t *moved,
+                 int32_t gx, int32_t gy, int32_t F, float *out)
+{
+    int32_t K = gx * gy;
+    int64_t *Q = calloc(3 * (int64_t)K, sizeof(int64_t));
+    int64_t *bl = calloc(K, sizeof(int64_t)), *ced = calloc(K, sizeof(int64_t));
+    int64_t *cmax = calloc(K, sizeof(int64_t)), *cmin = malloc(sizeof(int64_t) * K);
+    int64_t *cm = malloc(sizeof(int64_t) * 3 * K);
+    if (!Q || !bl || !ced || !cmax || !cmin || !cm) {
+        free(Q); free(bl); free(ced); free(cmax); free(cmin); free(cm);
+        return ORC_ENOMEM;
+    }
+    for (int32_t k = 0; k < K; k++) {
+        cmin[k] = -1;
+        for (int ch = 0; ch < 3; ch++)
+            cm[3 * k + ch] = div_round(stats[6 * (int64_t)k + 1 + ch], stats[6 * (int64_t)k], F);
+    }
+    for (int32_t y = 0; y < H; y++)
+        for (int32_t x = 0; x < W; x++) {
+            int32_t k = labels[(int64_t)y * W + x];
+            const uint8_t *q = rgb + (int64_t)y * stride + 3 * (int64_t)x;
+            for (int ch = 0; ch < 3; ch++) Q[3 * k + ch] += (int64_t)q[ch] * q[ch];
+            /* boundary pixel pairs to the right and below */
+            for (int d = 0; d < 2; d++) {
+                int32_t xx = x + (d == 0), yy = y + (d == 1);
+                if (xx >= W || yy >= H) continue;
+                int32_t j = labels[(int64_t)yy * W + xx];
+                if (j == k) continue;
+                int64_t d2 = 0;
+                for (int ch = 0; ch < 3; ch++) {
+                    int64_t df = cm[3 * k + ch] - cm[3 * j + ch];
+                    d2 += df * df;
+                }
+                int32_t both[2] = {k, j};
+                for (int u = 0; u < 2; u++) {
+                    int32_t t = both[u];
+                    bl[t] += 1;
+                    ced[t] += d2;
+                    if (d2 > cmax[t]) cmax[t] = d2;
+                    if (cmin[t] < 0 || d2 < cmin[t]) cmin[t] = d2;
+                }
+            }
+        }
+    (void)B;
+    double A = (double)(((int64_t)W * H) / K);
+    double sA = sqrt(A);
+    double cs = 255.0 * (double)(1 << F);
+    for (int32_t k = 0; k < K; k++) {
+        const int64_t *r = stats + 6 * (int64_t)k;
+        double n = (double)r[0];
+        float *f = out + 16 * (int64_t)k;
+        double sd[3];
+        for (int ch = 0; ch < 3; ch++) {
+            double mu = (double)r[1 + ch] / n;
+            double v = (double)Q[3 * k + ch] / n - mu * mu;
+            sd[ch] = sqrt(v > 0.0 ? v : 0.0);
+            f[ch] = (float)(mu / 255.0);
+            f[3 + ch] = (float)(sd[ch] / 64.0);
+        }
+        f[6] = (float)(n / A);
+        f[7] = (float)((double)bl[k] / (4.0 * sA));
+        f[8] = (float)((double)bl[k] * (double)bl[k] / (16.0 * n));
+        int32_t col = k % gx, row = k / gx;
+        double cx0 = (double)(2 * col + 1) * (double)W / (2.0 * gx) - 0.5;
+        double cy0 = (double)(2 * row + 1) * (double)H / (2.0 * gy) - 0.5;
+        double dx = (double)r[4] / n - cx0, dy = (double)r[5] / n - cy0;
+        f[9] = (float)(sqrt(dx * dx + dy * dy) / sA);
+        f[10] = (float)(sqrt((double)cmax[k]) / cs);
+        f[11] = (float)(bl[k] ? sqrt((double)ced[k] / (double)bl[k]) / cs : 0.0);
+        f[12] = (float)(cmin[k] >= 0 ? sqrt((double)cmin[k]) / cs : 0.0);
+        f[13] = (float)((moved ? (double)moved[k] : 0.0) / n);
+        double m3 = sd[0] > sd[1] ? sd[0] : sd[1];
+        m3 = m3 > sd[2] ? m3 : sd[2];
+        f[14] = (float)(m3 / 64.0);
+        f[15] = 1.0f;
+    }
+    free(Q); free(bl); free(ced); free(cmax); free(cmin); free(cm);
+    return ORC_OK;
 }

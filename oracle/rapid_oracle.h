@@ -56,6 +56,14 @@ int orc_segment(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
                 const orc_params *p, const uint8_t *gate,
                 int32_t *labels, int64_t *stats_out,
                 orc_stage_report *rep, int32_t max_rep, int32_t debug);
+int orc_segment_ex(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
+                   const orc_params *p, const uint8_t *gate,
+                   int32_t *labels, int64_t *stats_out,
+                   orc_stage_report *rep, int32_t max_rep, int32_t debug,
+                   uint8_t *involved, int64_t *moved);
+int orc_features(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
+                 const int32_t *labels, int32_t B, const int64_t *stats, const int64_t *moved,
+                 int32_t gx, int32_t gy, int32_t F, float *out);
 int orc_propose_class(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
                       const orc_params *p, const int32_t *labels, int32_t K,
                       int32_t B, int32_t cls, const uint8_t *gate,

@@ -31,6 +31,7 @@ struct rapid_ctx {
     bool timing = false;
     bool timed = false;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    float *part = nullptr;   // per-wave partial gradients of the gate network
     std::mutex mu;
 };
 
@@ -38,6 +39,7 @@ struct rapid_state {
     rapid_ctx *ctx = nullptr;
     Job job{};
     Job *job_dev = nullptr;
+    int64_t *zero_dev = nullptr;   // a device 0 (row offset of the state's features)
     char *mem = nullptr;
     Sched sc{};
     int32_t level_first[RAPID_MAX_LEVELS + 1] = {};
@@ -244,6 +246,7 @@ struct Layout {
     size_t bytes = 0;
     size_t off_lab[2], off_sums[MAXST], off_lists, off_props, off_changed, off_stamp;
     size_t off_stats, off_means, off_flow, off_mdbl, off_rep;
+    size_t off_fmean, off_facc, off_moved;
     int64_t capc = 0;
 };
 
@@ -274,6 +277,9 @@ Layout plan(int32_t W, int32_t H, int32_t K, const Sched &sc)
     L.off_flow = take(4 * 2 * (size_t)K);
     L.off_mdbl = take(8 * MD_STRIDE * (size_t)K);
     L.off_rep = take(sizeof(rapid_stage_report) * MAXST);
+    L.off_fmean = take(4 * 3 * (size_t)K);
+    L.off_facc = take(8 * FACC * (size_t)K);
+    L.off_moved = take(8 * (size_t)K);
     L.bytes = o;
     return L;
 }
@@ -306,6 +312,8 @@ void fill_job(Job &J, char *base, const Layout &L, const rapid_image *img, int32
     J.mdbl = reinterpret_cast<double *>(base + L.off_mdbl);
     J.rep = reinterpret_cast<rapid_stage_report *>(base + L.off_rep);
     J.gate = gate;
+    J.fmean = reinterpret_cast<int32_t *>(base + L.off_fmean);
+    J.facc = reinterpret_cast<int64_t *>(base + L.off_facc);
 }
 
 rapid_status dev_err(hipError_t e) { return e == hipSuccess ? RAPID_OK : RAPID_EDEVICE; }
@@ -504,6 +512,7 @@ void rapid_destroy(rapid_ctx *ctx)
     (void)hipFree(ctx->lut_dev);
     (void)hipFree(ctx->pool);
     (void)hipFree(ctx->jobs_dev);
+    (void)hipFree(ctx->part);
     if (ctx->jobs_pinned) (void)hipHostFree(ctx->jobs_pinned);
     if (ctx->jobs_copied) (void)hipEventDestroy(ctx->jobs_copied);
     for (int i = 0; i < 3; i++)
@@ -522,37 +531,63 @@ rapid_status rapid_last_timings(rapid_ctx *ctx, rapid_timings *out)
     return RAPID_OK;
 }
 
-rapid_status rapid_segment_batch(rapid_ctx *ctx, const rapid_image *imgs, int32_t n,
-                                 const rapid_params *params, rapid_report *reports);
+}  // extern "C"
 
-static rapid_status segment_impl(rapid_ctx *ctx, const rapid_image *imgs, int32_t n,
-                                 const rapid_params *params, const uint8_t *gate_dev,
-                                 rapid_report *reports)
-{
-    if (!ctx || !imgs || n < 1 || !params) return RAPID_EINVAL;
+namespace {
+
+// A batch of images laid out in the context's scratch pool: per image its
+// Job scratch, then (for the gate) the feature rows of all superpixels,
+// their gate bits and the per-image row offsets.
+struct Batch {
+    std::vector<Job> jobs;
+    std::vector<int64_t> xoff;
     Sched sc;
-    rapid_status r = make_sched(params, &sc, nullptr);
+    int32_t Kmax = 0;
+    int64_t Ktot = 0, nbF_max = 0;
+    int64_t max_nb[MAXST] = {};
+    float *X = nullptr;
+    uint8_t *gates = nullptr;
+    int64_t *xoff_dev = nullptr;
+};
+
+rapid_status prepare_batch(rapid_ctx *ctx, const rapid_image *imgs, int32_t n, const rapid_params *params,
+                           const uint8_t *gate_dev, bool gated, Batch &b)
+{
+    rapid_status r = make_sched(params, &b.sc, nullptr);
     if (r) return r;
-    if (!gate_dev) sc.gate_stage = sc.n_stages;
-    std::lock_guard<std::mutex> lock(ctx->mu);
-    if (hipSetDevice(ctx->device) != hipSuccess) return RAPID_EDEVICE;
+    Sched &sc = b.sc;
+    if (gated) {
+        if (params->gate_level < 1 || params->gate_level >= params->n_levels) return RAPID_EINVAL;
+    } else if (!gate_dev) {
+        sc.gate_stage = sc.n_stages;
+    }
     std::vector<Layout> lay(n);
     std::vector<int32_t> gxs(n), gys(n);
     size_t total = 0;
-    int32_t Kmax = 0;
-    int64_t max_nb[MAXST] = {};
-    int64_t nbF_max = 0;
+    int32_t Wmax = 0, Hmax = 0;
+    b.xoff.assign(n, 0);
     for (int i = 0; i < n; i++) {
         if ((r = check_image(&imgs[i], true))) return r;
         if ((r = image_grid(&imgs[i], params, sc, &gxs[i], &gys[i]))) return r;
         lay[i] = plan(imgs[i].W, imgs[i].H, gxs[i] * gys[i], sc);
         total += lay[i].bytes;
-        Kmax = std::max(Kmax, gxs[i] * gys[i]);
+        b.Kmax = std::max(b.Kmax, gxs[i] * gys[i]);
+        b.xoff[i] = b.Ktot;
+        b.Ktot += gxs[i] * gys[i];
         for (int s = 0; s < sc.n_stages; s++) {
             int64_t nb = (int64_t)((imgs[i].W + sc.B[s] - 1) / sc.B[s]) * ((imgs[i].H + sc.B[s] - 1) / sc.B[s]);
-            max_nb[s] = std::max(max_nb[s], nb);
+            b.max_nb[s] = std::max(b.max_nb[s], nb);
         }
-        nbF_max = std::max(nbF_max, max_nb[sc.n_stages - 1]);
+        b.nbF_max = std::max(b.nbF_max, b.max_nb[sc.n_stages - 1]);
+        Wmax = std::max(Wmax, imgs[i].W);
+        Hmax = std::max(Hmax, imgs[i].H);
+    }
+    size_t off_x = total, off_g = 0, off_xo = 0;
+    if (gated) {
+        off_x = align256(total);
+        off_g = align256(off_x + 4 * 16 * (size_t)b.Ktot);
+        off_xo = align256(off_g + (size_t)b.Ktot);
+        total = align256(off_xo + 8 * (size_t)n);
     }
     if (total > ctx->pool_size) {
         HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -562,25 +597,58 @@ static rapid_status segment_impl(rapid_ctx *ctx, const rapid_image *imgs, int32_
         if (hipMalloc(&ctx->pool, total) != hipSuccess) return RAPID_ENOMEM;
         ctx->pool_size = total;
     }
-    std::vector<Job> jobs(n);
+    b.jobs.resize(n);
     size_t off = 0;
     for (int i = 0; i < n; i++) {
-        fill_job(jobs[i], ctx->pool + off, lay[i], &imgs[i], gxs[i], gys[i], gate_dev);
+        fill_job(b.jobs[i], ctx->pool + off, lay[i], &imgs[i], gxs[i], gys[i], gate_dev);
+        if (gated) b.jobs[i].moved = reinterpret_cast<int64_t *>(ctx->pool + off + lay[i].off_moved);
         off += lay[i].bytes;
         // a final stage of single pixels writes its label map straight into
         // the caller's contiguous label buffer
         if (sc.B[sc.n_stages - 1] == 1 && imgs[i].label_stride == imgs[i].W)
-            jobs[i].lab[(sc.n_stages - 1) & 1] = imgs[i].labels_dev;
+            b.jobs[i].lab[(sc.n_stages - 1) & 1] = imgs[i].labels_dev;
     }
-    int32_t Wmax = 0, Hmax = 0;
-    for (int i = 0; i < n; i++) {
-        Wmax = std::max(Wmax, imgs[i].W);
-        Hmax = std::max(Hmax, imgs[i].H);
+    if (gated) {
+        b.X = reinterpret_cast<float *>(ctx->pool + off_x);
+        b.gates = reinterpret_cast<uint8_t *>(ctx->pool + off_g);
+        b.xoff_dev = reinterpret_cast<int64_t *>(ctx->pool + off_xo);
+        HIPCHK(hipMemcpyAsync(b.xoff_dev, b.xoff.data(), 8 * (size_t)n, hipMemcpyHostToDevice, ctx->stream));
+        for (int i = 0; i < n; i++) {
+            HIPCHK(hipMemsetAsync(b.jobs[i].moved, 0, 8 * (size_t)b.jobs[i].K, ctx->stream));
+        }
     }
     set_exactness(sc, Wmax, Hmax);
-    if ((r = run_jobs(ctx, jobs, sc, 0, sc.n_stages, FLAG_INIT | FLAG_OUT, Kmax, nbF_max, max_nb)))
+    return RAPID_OK;
+}
+
+// bf16 weights with an all-ones exponent are Inf or NaN
+bool model_finite(const uint16_t *w_dev, hipStream_t stream)
+{
+    std::vector<uint16_t> h(MLP_PARAMS);
+    if (hipMemcpyAsync(h.data(), w_dev, 2 * MLP_PARAMS, hipMemcpyDeviceToHost, stream) != hipSuccess) return false;
+    if (hipStreamSynchronize(stream) != hipSuccess) return false;
+    for (uint16_t v : h)
+        if ((v & 0x7F80) == 0x7F80) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+static rapid_status segment_impl(rapid_ctx *ctx, const rapid_image *imgs, int32_t n,
+                                 const rapid_params *params, const uint8_t *gate_dev,
+                                 rapid_report *reports)
+{
+    if (!ctx || !imgs || n < 1 || !params) return RAPID_EINVAL;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return RAPID_EDEVICE;
+    Batch b;
+    rapid_status r = prepare_batch(ctx, imgs, n, params, gate_dev, false, b);
+    if (r) return r;
+    if ((r = run_jobs(ctx, b.jobs, b.sc, 0, b.sc.n_stages, FLAG_INIT | FLAG_OUT, b.Kmax, b.nbF_max, b.max_nb)))
         return r;
-    if (reports) return fetch_reports(ctx, jobs, sc, 0, sc.n_stages, reports);
+    if (reports) return fetch_reports(ctx, b.jobs, b.sc, 0, b.sc.n_stages, reports);
     return RAPID_OK;
 }
 
@@ -594,6 +662,52 @@ rapid_status rapid_segment_batch(rapid_ctx *ctx, const rapid_image *imgs, int32_
                                  const rapid_params *params, rapid_report *reports)
 {
     return segment_impl(ctx, imgs, n, params, nullptr, reports);
+}
+
+rapid_status rapid_segment_gated(rapid_ctx *ctx, const rapid_image *imgs, int32_t n,
+                                 const rapid_params *params, const rapid_gate_model *model,
+                                 float *features_dev, uint8_t *gate_dev, rapid_report *reports)
+{
+    if (!ctx || !imgs || n < 1 || !params || !model || !model->w_bf16_dev) return RAPID_EINVAL;
+    if (!model_finite(model->w_bf16_dev, ctx->stream)) {
+        rapid_status r = segment_impl(ctx, imgs, n, params, nullptr, reports);
+        return r ? r : RAPID_EGATE;
+    }
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return RAPID_EDEVICE;
+    Batch b;
+    rapid_status r = prepare_batch(ctx, imgs, n, params, nullptr, true, b);
+    if (r) return r;
+    const int gs = b.sc.gate_stage;
+    // levels before the gate
+    if ((r = run_jobs(ctx, b.jobs, b.sc, 0, gs, FLAG_INIT, b.Kmax, b.nbF_max, b.max_nb))) return r;
+    // features of every superpixel and the network's decision (Eq. (6))
+    HIPCHK(launch_features(ctx->jobs_dev, n, b.sc.B[gs - 1], (gs - 1) & 1, b.sc.F, b.Kmax, b.max_nb[gs - 1],
+                           b.xoff_dev, b.X, ctx->stream));
+    HIPCHK(launch_mlp_fwd(b.X, b.Ktot, model->w_bf16_dev, model->thresh, nullptr, b.gates, ctx->stream));
+    if (features_dev)
+        HIPCHK(hipMemcpyAsync(features_dev, b.X, 4 * 16 * (size_t)b.Ktot, hipMemcpyDeviceToDevice, ctx->stream));
+    if (gate_dev)
+        HIPCHK(hipMemcpyAsync(gate_dev, b.gates, (size_t)b.Ktot, hipMemcpyDeviceToDevice, ctx->stream));
+    // the finer levels under the gate (Eq. (7))
+    for (int i = 0; i < n; i++) {
+        b.jobs[i].gate = b.gates + b.xoff[i];
+        b.jobs[i].moved = nullptr;
+    }
+    if ((r = run_jobs(ctx, b.jobs, b.sc, gs, b.sc.n_stages, FLAG_OUT, b.Kmax, b.nbF_max, b.max_nb))) return r;
+    if (reports) {
+        // one report per image over all stages
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        for (int i = 0; i < n; i++) {
+            rapid_report &R = reports[i];
+            std::memset(&R, 0, sizeof R);
+            R.K = b.jobs[i].K;
+            R.n_stages = b.sc.n_stages;
+            HIPCHK(hipMemcpy(R.stage, b.jobs[i].rep, sizeof(rapid_stage_report) * b.sc.n_stages,
+                             hipMemcpyDeviceToHost));
+        }
+    }
+    return RAPID_OK;
 }
 
 rapid_status rapid_state_create(rapid_ctx *ctx, const rapid_image *img, const rapid_params *params,
@@ -694,7 +808,149 @@ void rapid_state_destroy(rapid_state *st)
     }
     (void)hipFree(st->mem);
     (void)hipFree(st->job_dev);
+    (void)hipFree(st->zero_dev);
     delete st;
+}
+
+rapid_status rapid_state_track(rapid_state *st, uint8_t *involved_dev, int64_t *moved_dev)
+{
+    if (!st) return RAPID_EINVAL;
+    st->job.involved = involved_dev;
+    st->job.moved = moved_dev;
+    st->job.involve_stage = 0;
+    return RAPID_OK;
+}
+
+rapid_status rapid_state_features(rapid_ctx *ctx, rapid_state *st, float *X_dev)
+{
+    if (!ctx || !st || st->ctx != ctx || !X_dev) return RAPID_EINVAL;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return RAPID_EDEVICE;
+    if (!st->zero_dev) {
+        if (hipMalloc(&st->zero_dev, 8) != hipSuccess) return RAPID_ENOMEM;
+        HIPCHK(hipMemsetAsync(st->zero_dev, 0, 8, ctx->stream));
+    }
+    HIPCHK(hipMemcpyAsync(st->job_dev, &st->job, sizeof(Job), hipMemcpyHostToDevice, ctx->stream));
+    const int s = st->map_stage, B = st->sc.B[s];
+    const int64_t nb = (int64_t)((st->W + B - 1) / B) * ((st->H + B - 1) / B);
+    HIPCHK(launch_features(st->job_dev, 1, B, s & 1, st->sc.F, st->job.K, nb, st->zero_dev, X_dev, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RAPID_OK;
+}
+
+rapid_status rapid_mlp_forward(rapid_ctx *ctx, const float *X_dev, int64_t n, const uint16_t *w_bf16_dev,
+                               float thresh, float *logits_dev, uint8_t *gate_dev)
+{
+    if (!ctx || !X_dev || n < 0 || !w_bf16_dev || (!logits_dev && !gate_dev)) return RAPID_EINVAL;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return RAPID_EDEVICE;
+    if (n == 0) return RAPID_OK;
+    HIPCHK(launch_mlp_fwd(X_dev, n, w_bf16_dev, thresh, logits_dev, gate_dev, ctx->stream));
+    return RAPID_OK;
+}
+
+}  // extern "C"
+
+namespace {
+constexpr int GRAD_WAVES = 64;
+
+rapid_status ensure_train_scratch(rapid_ctx *ctx)
+{
+    if (ctx->part) return RAPID_OK;
+    if (hipMalloc(&ctx->part, sizeof(float) * (size_t)GRAD_WAVES * MLP_PARAMS) != hipSuccess) return RAPID_ENOMEM;
+    return RAPID_OK;
+}
+}  // namespace
+
+extern "C" {
+
+rapid_status rapid_mlp_grad(rapid_ctx *ctx, const float *X_dev, const uint8_t *t_dev, const int32_t *idx_dev,
+                            int32_t nb, const uint16_t *w_bf16_dev, float *grads_dev, float *logits_dev)
+{
+    if (!ctx || !X_dev || !t_dev || !idx_dev || nb < 1 || !w_bf16_dev || !grads_dev) return RAPID_EINVAL;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return RAPID_EDEVICE;
+    rapid_status r = ensure_train_scratch(ctx);
+    if (r) return r;
+    HIPCHK(launch_mlp_grad(X_dev, t_dev, idx_dev, nb, 1.0f / (float)nb, w_bf16_dev, ctx->part, GRAD_WAVES,
+                           grads_dev, logits_dev, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RAPID_OK;
+}
+
+rapid_status rapid_gate_train(rapid_ctx *ctx, const float *X_dev, const uint8_t *t_dev, int64_t n,
+                              const rapid_train_cfg *cfg, float *master_dev, uint16_t *w_bf16_dev)
+{
+    if (!ctx || !X_dev || !t_dev || n < 1 || n > INT32_MAX || !cfg || !master_dev || !w_bf16_dev)
+        return RAPID_EINVAL;
+    if (cfg->epochs < 0 || cfg->batch < 2 || cfg->batch % 2 || !(cfg->lr > 0.f)) return RAPID_EINVAL;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return RAPID_EDEVICE;
+    rapid_status r = ensure_train_scratch(ctx);
+    if (r) return r;
+    // class index lists (balanced batches: half positive, half negative)
+    std::vector<uint8_t> t(n);
+    HIPCHK(hipMemcpy(t.data(), t_dev, (size_t)n, hipMemcpyDeviceToHost));
+    std::vector<int32_t> pos, neg;
+    for (int64_t i = 0; i < n; i++) (t[i] ? pos : neg).push_back((int32_t)i);
+    const int32_t bs = cfg->batch;
+    const int64_t per_epoch = std::max<int64_t>(1, n / bs);
+    float *m = nullptr, *v = nullptr, *g = nullptr;
+    int32_t *idx = nullptr;
+    size_t idx_n = (size_t)per_epoch * bs;
+    if (hipMalloc(&m, 4 * MLP_PARAMS) != hipSuccess || hipMalloc(&v, 4 * MLP_PARAMS) != hipSuccess ||
+        hipMalloc(&g, 4 * MLP_PARAMS) != hipSuccess || hipMalloc(&idx, 4 * idx_n) != hipSuccess) {
+        (void)hipFree(m); (void)hipFree(v); (void)hipFree(g); (void)hipFree(idx);
+        return RAPID_ENOMEM;
+    }
+    rapid_status rc = RAPID_OK;
+    std::vector<int32_t> hidx(idx_n);
+    uint64_t rs = cfg->seed * 0x9E3779B97F4A7C15ull + 1;
+    auto rnd = [&rs]() {   // SplitMix64
+        uint64_t z = (rs += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    auto shuffle = [&rnd](std::vector<int32_t> &a) {
+        for (size_t i = a.size(); i > 1; i--) std::swap(a[i - 1], a[rnd() % i]);
+    };
+    int step = 0;
+    if (hipMemsetAsync(m, 0, 4 * MLP_PARAMS, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(v, 0, 4 * MLP_PARAMS, ctx->stream) != hipSuccess ||
+        launch_to_bf16(master_dev, w_bf16_dev, MLP_PARAMS, ctx->stream) != hipSuccess)
+        rc = RAPID_EDEVICE;
+    for (int ep = 0; rc == RAPID_OK && ep < cfg->epochs; ep++) {
+        shuffle(pos);
+        shuffle(neg);
+        size_t ip = 0, in = 0;
+        for (int64_t bi = 0; bi < per_epoch; bi++)
+            for (int32_t j = 0; j < bs; j++) {
+                const bool want_pos = (j & 1) ? !neg.empty() && pos.empty() : !pos.empty();
+                std::vector<int32_t> &src = (want_pos || neg.empty()) ? pos : neg;
+                size_t &cur = (&src == &pos) ? ip : in;
+                if (cur == src.size()) { shuffle(src); cur = 0; }
+                hidx[(size_t)bi * bs + j] = src[cur++];
+            }
+        if (hipStreamSynchronize(ctx->stream) != hipSuccess ||
+            hipMemcpy(idx, hidx.data(), 4 * idx_n, hipMemcpyHostToDevice) != hipSuccess) {
+            rc = RAPID_EDEVICE;
+            break;
+        }
+        for (int64_t bi = 0; bi < per_epoch; bi++) {
+            step++;
+            if (launch_mlp_grad(X_dev, t_dev, idx + bi * bs, bs, 1.0f / (float)bs, w_bf16_dev, ctx->part,
+                                GRAD_WAVES, g, nullptr, ctx->stream) != hipSuccess ||
+                launch_adam(master_dev, m, v, g, w_bf16_dev, cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, step,
+                            ctx->stream) != hipSuccess) {
+                rc = RAPID_EDEVICE;
+                break;
+            }
+        }
+    }
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess && rc == RAPID_OK) rc = RAPID_EDEVICE;
+    (void)hipFree(m); (void)hipFree(v); (void)hipFree(g); (void)hipFree(idx);
+    return rc;
 }
 
 }  // extern "C"

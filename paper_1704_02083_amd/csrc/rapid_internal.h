@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 #include "rapid.h"
 
 namespace rapid {
@@ -62,6 +64,13 @@ struct Job {
     double *mdbl;            // K x MD_STRIDE (global working set)
     rapid_stage_report *rep; // per stage
     const uint8_t *gate;     // K bytes or null
+    // optional tracking (null: off)
+    uint8_t *involved;       // K: source or target of a proposal at stage >= involve_stage
+    int64_t *moved;          // K: pixels moved in or out by committed moves
+    int32_t involve_stage, pad2;
+    // gate feature scratch
+    int32_t *fmean;          // K x 3 fixed-point means
+    int64_t *facc;           // K x FACC accumulators
 };
 
 hipError_t launch_block_sums(const Job *jobs_dev, int n_jobs, int s, int B, int64_t max_nb,
@@ -72,10 +81,25 @@ hipError_t launch_refine(const Job *jobs_dev, int n_jobs, const Sched &sc, const
                          int s_begin, int s_end, int flags, const uint32_t *lut_dev, int threads,
                          hipStream_t stream);
 
+// gate network size and feature accumulators
+constexpr int MLP_PARAMS = 5313;
+constexpr int FACC = 8;
+
 // per-superpixel means record: c_r c_g c_b mu_x mu_y n (int32)
 constexpr int MN_STRIDE = 6;
 // per-superpixel fp64 energy record: A c'_r c'_g c'_b mu'_x mu'_y
 constexpr int MD_STRIDE = 6;
+
+hipError_t launch_features(const Job *jobs_dev, int n_jobs, int B, int lab_buf, int F, int32_t Kmax,
+                           int64_t max_nb, const int64_t *xoff_dev, float *X, hipStream_t stream);
+hipError_t launch_mlp_fwd(const float *X, int64_t N, const uint16_t *P, float thresh, float *logits,
+                          uint8_t *gate, hipStream_t stream);
+hipError_t launch_mlp_grad(const float *X, const uint8_t *T, const int32_t *idx, int32_t nb, float scale,
+                           const uint16_t *P, float *part, int n_waves, float *grads, float *logits,
+                           hipStream_t stream);
+hipError_t launch_adam(float *theta, float *m, float *v, const float *g, uint16_t *wbf, float lr, float b1,
+                       float b2, float eps, int step, hipStream_t stream);
+hipError_t launch_to_bf16(const float *src, uint16_t *dst, int64_t n, hipStream_t stream);
 
 // bytes of LDS per superpixel when the statistics live in LDS: sums,
 // fp64 energy record, means record, flow counters

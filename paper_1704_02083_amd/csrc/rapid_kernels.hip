@@ -508,6 +508,10 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                     }
                     n_smin += smin;
                     n_stopo += stopo;
+                    if (prop && J.involved && s >= J.involve_stage) {
+                        J.involved[a] = 1;
+                        J.involved[best] = 1;
+                    }
                     int slot = wave_append(&s_nprop, prop);
                     if (slot >= 0) {
                         Prop rec;
@@ -551,6 +555,9 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                             add64(rr + 3, sg * (int64_t)(rec.I >> 42));
                             add64(rr + 4, sg * g.px);
                             add64(rr + 5, sg * g.py);
+                            if (J.moved)
+                                atomicAdd(reinterpret_cast<unsigned long long *>(J.moved + (side ? k : a)),
+                                          (unsigned long long)g.m);
                             if (side == 0) {
                                 L[bi] = k;
                                 // P3 refreshes the superpixels of committed moves

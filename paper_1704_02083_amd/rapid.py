@@ -78,6 +78,19 @@ class Report(C.Structure):
         return [self.stage[i].as_dict() for i in range(self.n_stages)]
 
 
+class GateModel(C.Structure):
+    _fields_ = [("w_bf16_dev", C.c_void_p), ("thresh", C.c_float)]
+
+
+class TrainCfg(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("seed", C.c_uint64)]
+
+
+MLP_PARAMS = 5313
+N_FEATURES = 16
+
 _P = C.c_void_p
 _lib.rapid_init.argtypes = [C.POINTER(Config), C.POINTER(_P)]
 _lib.rapid_destroy.argtypes = [_P]
@@ -97,11 +110,20 @@ _lib.rapid_status_str.restype = C.c_char_p
 _lib.rapid_simple_lut.argtypes = [C.POINTER(C.c_uint32)]
 _lib.rapid_check_params.argtypes = [C.c_int32, C.c_int32, C.POINTER(Params), C.POINTER(C.c_int32)]
 _lib.rapid_last_timings.argtypes = [_P, C.POINTER(Timings)]
+_lib.rapid_segment_gated.argtypes = [_P, C.POINTER(Image), C.c_int32, C.POINTER(Params),
+                                     C.POINTER(GateModel), _P, _P, C.POINTER(Report)]
+_lib.rapid_state_track.argtypes = [_P, _P, _P]
+_lib.rapid_state_features.argtypes = [_P, _P, _P]
+_lib.rapid_mlp_forward.argtypes = [_P, _P, C.c_int64, _P, C.c_float, _P, _P]
+_lib.rapid_mlp_grad.argtypes = [_P, _P, _P, _P, C.c_int32, _P, _P, _P]
+_lib.rapid_gate_train.argtypes = [_P, _P, _P, C.c_int64, C.POINTER(TrainCfg), _P, _P]
 
 EXPORTED = ["rapid_init", "rapid_destroy", "rapid_segment", "rapid_segment_batch",
             "rapid_state_create", "rapid_refine_level", "rapid_state_export",
             "rapid_state_destroy", "rapid_grid", "rapid_status_str", "rapid_simple_lut",
-            "rapid_check_params", "rapid_last_timings"]
+            "rapid_check_params", "rapid_last_timings", "rapid_segment_gated",
+            "rapid_state_track", "rapid_state_features", "rapid_mlp_forward", "rapid_mlp_grad",
+            "rapid_gate_train"]
 
 
 def _check(rc: int, where: str):
@@ -224,6 +246,60 @@ class Context:
         _check(_lib.rapid_segment_batch(self._h, ims, n, C.byref(p), reps), "rapid_segment_batch")
         return labels, ([r.stages() for r in reps] if reps is not None else None)
 
+    # rapid_segment_gated
+    def segment_gated(self, rgbs, params: dict, w_bf16, thresh: float = 0.0, labels=None,
+                      features: bool = False, report: bool = True):
+        """Returns (labels list, reports, features (sum K, 16) or None, gate bits)."""
+        import torch
+        n = len(rgbs)
+        if labels is None:
+            labels = [torch.empty((int(r.shape[0]), int(r.shape[1])), dtype=torch.int32,
+                                  device=r.device) for r in rgbs]
+        ims = (Image * n)(*[_image(r, l) for r, l in zip(rgbs, labels)])
+        p = make_params(params)
+        Ktot = sum(check_params(int(r.shape[1]), int(r.shape[0]), params) for r in rgbs)
+        X = torch.empty((Ktot, N_FEATURES), dtype=torch.float32, device=rgbs[0].device) if features else None
+        g = torch.empty(Ktot, dtype=torch.uint8, device=rgbs[0].device)
+        model = GateModel(w_bf16.data_ptr(), thresh)
+        reps = (Report * n)() if report else None
+        rc = _lib.rapid_segment_gated(self._h, ims, n, C.byref(p), C.byref(model),
+                                      C.c_void_p(X.data_ptr()) if X is not None else None,
+                                      C.c_void_p(g.data_ptr()), reps)
+        _check(rc, "rapid_segment_gated")
+        return labels, ([r.stages() for r in reps] if reps is not None else None), X, g
+
+    def mlp_forward(self, X, w_bf16, thresh: float = 0.0):
+        import torch
+        n = int(X.shape[0])
+        logits = torch.empty(n, dtype=torch.float32, device=X.device)
+        gate = torch.empty(n, dtype=torch.uint8, device=X.device)
+        _check(_lib.rapid_mlp_forward(self._h, C.c_void_p(X.data_ptr()), n, C.c_void_p(w_bf16.data_ptr()),
+                                      thresh, C.c_void_p(logits.data_ptr()), C.c_void_p(gate.data_ptr())),
+               "rapid_mlp_forward")
+        return logits, gate
+
+    def mlp_grad(self, X, t, idx, w_bf16):
+        import torch
+        grads = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device)
+        logits = torch.empty(int(idx.shape[0]), dtype=torch.float32, device=X.device)
+        _check(_lib.rapid_mlp_grad(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(t.data_ptr()),
+                                   C.c_void_p(idx.data_ptr()), int(idx.shape[0]),
+                                   C.c_void_p(w_bf16.data_ptr()), C.c_void_p(grads.data_ptr()),
+                                   C.c_void_p(logits.data_ptr())), "rapid_mlp_grad")
+        return grads, logits
+
+    def gate_train(self, X, t, master, epochs: int = 20, batch: int = 4096, lr: float = 1e-3,
+                   beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, seed: int = 0):
+        """Trains in place: master (5313 float32, device) in/out; returns the
+        bf16 weights (5313 uint16 as int16 tensor)."""
+        import torch
+        w = torch.empty(MLP_PARAMS, dtype=torch.int16, device=X.device)
+        cfg = TrainCfg(epochs, batch, lr, beta1, beta2, eps, seed)
+        _check(_lib.rapid_gate_train(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(t.data_ptr()),
+                                     int(X.shape[0]), C.byref(cfg), C.c_void_p(master.data_ptr()),
+                                     C.c_void_p(w.data_ptr())), "rapid_gate_train")
+        return w
+
     def last_timings(self) -> dict:
         t = Timings()
         _check(_lib.rapid_last_timings(self._h, C.byref(t)), "rapid_last_timings")
@@ -254,6 +330,19 @@ class State:
                                        C.byref(rep) if rep is not None else None),
                "rapid_refine_level")
         return rep.stages() if rep is not None else None
+
+    def track(self, involved=None, moved=None):
+        _check(_lib.rapid_state_track(self._h,
+                                      C.c_void_p(involved.data_ptr()) if involved is not None else None,
+                                      C.c_void_p(moved.data_ptr()) if moved is not None else None),
+               "rapid_state_track")
+
+    def features(self):
+        import torch
+        X = torch.empty((self.K, N_FEATURES), dtype=torch.float32, device=self.rgb.device)
+        _check(_lib.rapid_state_features(self.ctx._h, self._h, C.c_void_p(X.data_ptr())),
+               "rapid_state_features")
+        return X
 
     def export(self):
         import torch

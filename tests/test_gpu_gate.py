@@ -1,0 +1,201 @@
+"""GPU parity of the gate: features, targets, network forward/backward,
+Adam, and gated segmentation against the CPU references."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+from paper_1704_02083_amd import params, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    c = gpu_lib.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _he_case():
+    img = synth.he_tile(256, 192, seed=12)
+    p = params.default_params(256, 192, 48, levels=params.THREE_LEVEL, gate_level=1)
+    return img, p
+
+
+def test_features_and_targets_match_oracle(ctx):
+    import torch
+    img, p = _he_case()
+    gx, gy = oracle.grid(256, 192, 48)
+    K = gx * gy
+    _say("case: features 256x192 H&E K=%d" % K)
+    st = ctx.state(_dev(img), p)
+    moved = torch.zeros(K, dtype=torch.int64, device="cuda")
+    involved = torch.zeros(K, dtype=torch.uint8, device="cuda")
+    st.track(None, moved)
+    st.refine_level(0)
+    X = st.features().cpu().numpy()
+    moved0 = moved.cpu().numpy().copy()
+    # oracle: level 0 only
+    p0 = dict(p, levels=p["levels"][:1], gate_level=-1)
+    lab0, s0, _, _, mov0 = oracle.segment(img, p0, track=True)
+    Xo = oracle.features(img, lab0, 16, s0, mov0, gx, gy)
+    assert (moved0 == mov0).all()
+    diff = np.abs(X - Xo)
+    assert diff.max() <= 1e-6 * max(1.0, np.abs(Xo).max()), diff.max()
+    # targets: involvement after the gate level
+    st.track(involved, moved)
+    st.refine_level(1)
+    st.refine_level(2)
+    lab, _ = st.export()
+    _, _, _, inv, mov = oracle.segment(img, p, track=True)
+    assert (involved.cpu().numpy() == inv).all()
+    assert (moved.cpu().numpy() == mov).all()
+    st.close()
+
+
+def _rand_model(seed):
+    theta = mlp.he_init(seed).astype(np.float32)
+    return theta, mlp.to_bf16_bits(theta).view(np.int16)
+
+
+def test_mlp_forward_matches_oracle(ctx):
+    import torch
+    rng = np.random.default_rng(5)
+    N = 1000   # not a multiple of 16
+    X = rng.normal(size=(N, 16)).astype(np.float32)
+    theta, wb = _rand_model(7)
+    logits, gate = ctx.mlp_forward(_dev(X), _dev(wb), 0.25)
+    logits = logits.cpu().numpy()
+    ref, _ = mlp.forward(theta.astype(np.float64), X.astype(np.float64), bf16=True)
+    err = np.abs(logits - ref)
+    _say("mlp forward max abs err %.3g" % err.max())
+    assert err.max() <= 1e-2
+    far = np.abs(ref - 0.25) > 1e-2
+    assert (gate.cpu().numpy()[far] == (ref[far] >= 0.25)).all()
+
+
+def test_mlp_grad_matches_oracle(ctx):
+    rng = np.random.default_rng(6)
+    N = 2000
+    X = (rng.normal(size=(N, 16)) * 0.7).astype(np.float32)
+    t = (rng.random(N) < 0.45).astype(np.uint8)
+    idx = rng.choice(N, 777, replace=False).astype(np.int32)
+    theta, wb = _rand_model(9)
+    g, logits = ctx.mlp_grad(_dev(X), _dev(t), _dev(idx), _dev(wb))
+    g = g.cpu().numpy().astype(np.float64)
+    gr, zr = mlp.grad(theta.astype(np.float64), X[idx].astype(np.float64), t[idx].astype(np.float64),
+                      bf16=True)
+    assert np.abs(logits.cpu().numpy() - zr).max() <= 1e-2
+    parts_g, parts_r = mlp.unpack(g), mlp.unpack(gr)
+    for name, _ in mlp.SIZES:
+        a, b = parts_g[name].ravel(), parts_r[name].ravel()
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-12)
+        _say("grad %s rel L2 %.3g" % (name, rel))
+        assert rel <= 2 ** -6, name
+
+
+def test_mlp_grad_deterministic(ctx):
+    rng = np.random.default_rng(11)
+    X = rng.normal(size=(5000, 16)).astype(np.float32)
+    t = (rng.random(5000) < 0.5).astype(np.uint8)
+    idx = np.arange(4096, dtype=np.int32)
+    theta, wb = _rand_model(3)
+    g1, _ = ctx.mlp_grad(_dev(X), _dev(t), _dev(idx), _dev(wb))
+    g2, _ = ctx.mlp_grad(_dev(X), _dev(t), _dev(idx), _dev(wb))
+    assert (g1.cpu().numpy() == g2.cpu().numpy()).all()
+
+
+def test_adam_first_step(ctx):
+    """One epoch of one balanced batch (all 512 samples): the update equals
+    the closed-form first Adam step -lr g / (|g| + eps)."""
+    import torch
+    rng = np.random.default_rng(12)
+    X = rng.normal(size=(512, 16)).astype(np.float32)
+    t = np.zeros(512, np.uint8)
+    t[rng.choice(512, 256, replace=False)] = 1
+    theta, wb = _rand_model(4)
+    g, _ = ctx.mlp_grad(_dev(X), _dev(t), _dev(np.arange(512, dtype=np.int32)), _dev(wb))
+    g = g.cpu().numpy()
+    master = _dev(theta)
+    w = ctx.gate_train(_dev(X), _dev(t), master, epochs=1, batch=512, lr=1e-3, seed=1)
+    step = master.cpu().numpy() - theta
+    big = np.abs(g) > 1e-5
+    assert big.sum() > 1000
+    assert np.allclose(step[big], -1e-3 * np.sign(g[big]), rtol=0, atol=2e-5)
+    assert (w.cpu().numpy().view(np.uint16) == mlp.to_bf16_bits(master.cpu().numpy())).all()
+
+
+def _oracle_gated(img, p, theta):
+    """Oracle's own gate: features at the gate point, its own network, a
+    threshold placed in the widest gap near the median logit."""
+    gx, gy = oracle.grid(img.shape[1], img.shape[0], p["K"])
+    p0 = dict(p, levels=p["levels"][:1], gate_level=-1)
+    lab0, s0, _, _, mov0 = oracle.segment(img, p0, track=True)
+    Xo = oracle.features(img, lab0, p["levels"][0][0] * p["levels"][0][1][-1], s0, mov0, gx, gy)
+    z, _ = mlp.forward(theta.astype(np.float64), Xo.astype(np.float64), bf16=True)
+    zs = np.sort(z)
+    mid = len(zs) // 2
+    lo, hi = max(1, mid - len(zs) // 4), min(len(zs) - 1, mid + len(zs) // 4)
+    gaps = zs[lo:hi + 1] - zs[lo - 1:hi]
+    j = int(np.argmax(gaps)) + lo
+    thresh = float((zs[j - 1] + zs[j]) / 2)
+    assert gaps.max() > 2e-2, "no clear threshold"
+    bits = (z >= thresh).astype(np.uint8)
+    lab, _, rep = oracle.segment(img, p, gate=bits)
+    return thresh, bits, lab, rep, Xo
+
+
+def test_gated_segment_matches_oracle(ctx):
+    img, p = _he_case()
+    theta, wb = _rand_model(21)
+    thresh, bits, ref, ref_rep, Xo = _oracle_gated(img, p, theta)
+    _say("case: gated 256x192, thresh %.4f, marked %d of %d" % (thresh, bits.sum(), len(bits)))
+    labs, reps, X, g = ctx.segment_gated([_dev(img)], p, _dev(wb), thresh, features=True)
+    assert np.abs(X.cpu().numpy() - Xo).max() <= 1e-6
+    assert (g.cpu().numpy() == bits).all()
+    assert (labs[0].cpu().numpy() == ref).all()
+    assert reps[0] == ref_rep
+
+
+def test_gate_with_targets_is_plain_gpu(ctx):
+    import torch
+    img, p = _he_case()
+    gx, gy = oracle.grid(256, 192, 48)
+    K = gx * gy
+    st = ctx.state(_dev(img), p)
+    involved = torch.zeros(K, dtype=torch.uint8, device="cuda")
+    st.refine_level(0)
+    st.track(involved, None)
+    st.refine_level(1)
+    st.refine_level(2)
+    plain, _ = st.export()
+    st.close()
+    lab, _ = ctx.segment(_dev(img), p, gate=involved)
+    assert (lab.cpu().numpy() == plain.cpu().numpy()).all()
+
+
+def test_non_finite_model_falls_back_to_plain(ctx, gpu_lib):
+    import torch
+    img, p = _he_case()
+    theta, wb = _rand_model(2)
+    wb = wb.copy()
+    wb[100] = np.int16(0x7FC0)   # NaN
+    lab = torch.empty((192, 256), dtype=torch.int32, device="cuda")
+    with pytest.raises(gpu_lib.RapidError) as e:
+        ctx.segment_gated([_dev(img)], p, _dev(wb), 0.0, labels=[lab])
+    assert e.value.code == -5
+    plain, _ = ctx.segment(_dev(img), p)
+    assert (lab.cpu().numpy() == plain.cpu().numpy()).all()

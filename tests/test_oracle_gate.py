@@ -1,0 +1,126 @@
+"""Pins of the gate's reference code (features, network, Adam, targets)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+from paper_1704_02083_amd import params, synth
+
+
+def test_bf16_round_to_nearest_even():
+    cases = {1.0: 0x3F80, 1.0 + 2 ** -8: 0x3F80, 1.0 + 3 * 2 ** -8: 0x3F82,
+             1.0 + 2 ** -9: 0x3F80, -2.5: 0xC020, 3.140625: 0x4049, 0.0: 0x0000}
+    for v, bits in cases.items():
+        assert int(mlp.to_bf16_bits(np.float32(v))) == bits, v
+    x = np.random.default_rng(0).normal(size=1000).astype(np.float32)
+    back = mlp.from_bf16_bits(mlp.to_bf16_bits(x))
+    assert np.all(np.abs(back - x) <= np.abs(x) * 2 ** -8)
+
+
+def test_backward_matches_central_differences():
+    """fp64 gradient of the mean BCE equals central differences (rel 1e-6)."""
+    rng = np.random.default_rng(1)
+    theta = mlp.he_init(3)
+    X = rng.normal(size=(37, 16))
+    t = (rng.random(37) < 0.4).astype(np.float64)
+    g, _ = mlp.grad(theta, X, t, bf16=False)
+    h = 1e-6
+    idx = np.concatenate([rng.choice(1024, 40, replace=False), 1024 + rng.choice(64, 10, replace=False),
+                          1088 + rng.choice(4096, 60, replace=False), 5184 + rng.choice(64, 10, replace=False),
+                          5248 + np.arange(64), [5312]])
+    num = []
+    for i in idx:
+        tp = theta.copy(); tp[i] += h
+        tm = theta.copy(); tm[i] -= h
+        num.append((mlp.loss(tp, X, t, bf16=False) - mlp.loss(tm, X, t, bf16=False)) / (2 * h))
+    num = np.array(num)
+    err = np.abs(num - g[idx])
+    assert np.all(err <= 1e-6 * np.maximum(np.abs(num), 1e-3) + 1e-9), err.max()
+
+
+def test_adam_first_step_closed_form():
+    """From zero moments the first Adam step is -lr g / (|g| + eps)."""
+    rng = np.random.default_rng(2)
+    theta = rng.normal(size=100)
+    g = rng.normal(size=100)
+    new, m, v = mlp.adam_step(theta, np.zeros(100), np.zeros(100), g, 1, lr=1e-3)
+    assert np.allclose(new - theta, -1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+
+
+def test_logit_of_linear_network():
+    """With W1 = [I;0] on 16 inputs, W2 = I, w3 = e_0 and zero biases, the
+    network computes relu(x_0): a closed form for the forward pass."""
+    parts = {"W1": np.zeros((64, 16)), "b1": np.zeros(64), "W2": np.eye(64), "b2": np.zeros(64),
+             "w3": np.zeros(64), "b3": np.zeros(1)}
+    parts["W1"][:16, :16] = np.eye(16)
+    parts["w3"][0] = 1.0
+    X = np.linspace(-2, 2, 32).reshape(2, 16)
+    z, _ = mlp.forward(mlp.pack(parts), X, bf16=False)
+    assert np.allclose(z, np.maximum(X[:, 0], 0))
+
+
+def _two_region_features():
+    """64 x 32 image, left half (30, 60, 90), right half (200, 100, 50),
+    K = 2 (a 2 x 1 grid on the halves), one stage at B = 16."""
+    img = np.zeros((32, 64, 3), np.uint8)
+    img[:, :32] = (30, 60, 90)
+    img[:, 32:] = (200, 100, 50)
+    p = {"K": 2, "levels": [(1, [16])], "gate_level": -1, "frac_bits": 4, "max_sweeps": 8,
+         "min_size": 0, "max_size": 1 << 30, "w_col": 1, "w_pos": 1, "w_bnd": 1}
+    lab, st, rep, inv, mov = oracle.segment(img, p, track=True)
+    return img, lab, st, mov, oracle.features(img, lab, 16, st, mov, 2, 1)
+
+
+def test_features_two_regions_by_hand():
+    img, lab, st, mov, f = _two_region_features()
+    xs = np.mgrid[0:32, 0:64][1]
+    assert (lab == (xs >= 32)).all()           # already optimal: nothing moves
+    A = 64 * 32 // 2
+    d = np.sqrt((170 ** 2 + 40 ** 2 + 40 ** 2) * 16 ** 2) / (255 * 16)
+    exp0 = [30 / 255, 60 / 255, 90 / 255, 0, 0, 0, 1.0, 32 / (4 * np.sqrt(A)),
+            32 ** 2 / (16 * A), 0.0, d, d, d, 0.0, 0.0, 1.0]
+    exp1 = [200 / 255, 100 / 255, 50 / 255, 0, 0, 0, 1.0, 32 / (4 * np.sqrt(A)),
+            32 ** 2 / (16 * A), 0.0, d, d, d, 0.0, 0.0, 1.0]
+    assert np.allclose(f[0], exp0, rtol=1e-6, atol=1e-7)
+    assert np.allclose(f[1], exp1, rtol=1e-6, atol=1e-7)
+
+
+def test_features_std_and_drift():
+    """Colour standard deviation from pixel second moments and the centroid
+    drift, against numpy on a noisy image after refinement."""
+    img = synth.voronoi_blur(96, 64, regions=8, seed=3)
+    p = params.default_params(96, 64, 6, levels=[(1, [16, 8])])
+    lab, st, rep, inv, mov = oracle.segment(img, p, track=True)
+    gx, gy = oracle.grid(96, 64, 6)
+    f = oracle.features(img, lab, 8, st, mov, gx, gy)
+    A = 96 * 64 // 6
+    ys, xs = np.mgrid[0:64, 0:96]
+    for k in range(gx * gy):
+        m = lab == k
+        px = img[m].astype(np.float64)
+        assert np.allclose(f[k, 3:6], px.std(0) / 64, rtol=1e-5, atol=1e-6)
+        col, row = k % gx, k // gx
+        cx0 = (2 * col + 1) * 96 / (2 * gx) - 0.5
+        cy0 = (2 * row + 1) * 64 / (2 * gy) - 0.5
+        drift = np.hypot(xs[m].mean() - cx0, ys[m].mean() - cy0) / np.sqrt(A)
+        assert abs(f[k, 9] - drift) < 1e-6
+        assert abs(f[k, 13] - mov[k] / m.sum()) < 1e-7
+
+
+def test_gate_with_targets_is_plain():
+    """Targets t (superpixels in any proposal past the gate level of the
+    plain run) gate exactly the moves the plain run makes: by induction a
+    gated-off superpixel never appears in a plain proposal, so the gated run
+    with g = t reproduces the plain labels bit for bit."""
+    img = synth.voronoi_blur(160, 128, regions=14, seed=8)
+    img[:, :96] = (128, 128, 128)   # a flat region: its inner superpixels never move
+    p = params.default_params(160, 128, 20, levels=params.THREE_LEVEL, gate_level=1)
+    lab, st, rep, inv, mov = oracle.segment(img, p, track=True)
+    assert 0 < inv.sum() < len(inv)
+    gated = oracle.segment(img, p, gate=inv)
+    assert (gated[0] == lab).all()
+    # and every superpixel whose statistics changed after the gate is a target
+    p1 = dict(p, levels=p["levels"][:1])
+    _, st1, _ = oracle.segment(img, p1)
+    changed = np.any(st1 != st, axis=1)
+    assert np.all(inv[changed] == 1)
