@@ -82,27 +82,30 @@ def batch_images(n: int = 200, seed0: int = 1000) -> list[np.ndarray]:
 # ----------------------------------------------------------------- H&E tiles
 
 def _perlin(W: int, H: int, cell: int, rng: np.random.Generator) -> np.ndarray:
-    """Gradient ("improved") Perlin noise on a lattice of the given cell size."""
-    gw, gh = W // cell + 2, H // cell + 2
+    """Gradient ("improved") Perlin noise on a lattice of the given cell size,
+    evaluated cell by cell with broadcasting."""
+    gw, gh = -(-W // cell) + 1, -(-H // cell) + 1
     ang = rng.uniform(0, 2 * np.pi, size=(gh, gw))
     gxv, gyv = np.cos(ang), np.sin(ang)
-    ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
-    fx, fy = xs / cell, ys / cell
-    x0, y0 = np.floor(fx).astype(np.int64), np.floor(fy).astype(np.int64)
-    tx, ty = fx - x0, fy - y0
+    t = np.arange(cell, dtype=np.float64) / cell
+    tx = t[None, None, None, :]
+    ty = t[None, :, None, None]
 
-    def fade(t):
-        return t * t * t * (t * (t * 6 - 15) + 10)
+    def corner(dy, dx):
+        return (gxv[dy:dy + gh - 1, dx:dx + gw - 1][:, None, :, None],
+                gyv[dy:dy + gh - 1, dx:dx + gw - 1][:, None, :, None])
 
-    def dot(ix, iy, dx, dy):
-        return gxv[iy, ix] * dx + gyv[iy, ix] * dy
+    def fade(v):
+        return v * v * v * (v * (v * 6 - 15) + 10)
 
-    n00 = dot(x0, y0, tx, ty)
-    n10 = dot(x0 + 1, y0, tx - 1, ty)
-    n01 = dot(x0, y0 + 1, tx, ty - 1)
-    n11 = dot(x0 + 1, y0 + 1, tx - 1, ty - 1)
+    g00, g10, g01, g11 = corner(0, 0), corner(0, 1), corner(1, 0), corner(1, 1)
+    n00 = g00[0] * tx + g00[1] * ty
+    n10 = g10[0] * (tx - 1) + g10[1] * ty
+    n01 = g01[0] * tx + g01[1] * (ty - 1)
+    n11 = g11[0] * (tx - 1) + g11[1] * (ty - 1)
     u, v = fade(tx), fade(ty)
-    return (n00 * (1 - u) + n10 * u) * (1 - v) + (n01 * (1 - u) + n11 * u) * v
+    out = (n00 * (1 - u) + n10 * u) * (1 - v) + (n01 * (1 - u) + n11 * u) * v
+    return out.reshape((gh - 1) * cell, (gw - 1) * cell)[:H, :W]
 
 
 def _fbm(W: int, H: int, cell: int, rng: np.random.Generator, octaves: int = 3) -> np.ndarray:
