@@ -234,6 +234,35 @@ typedef struct {
 rapid_status rapid_gate_train(rapid_ctx *ctx, const float *X_dev, const uint8_t *t_dev, int64_t n,
                               const rapid_train_cfg *cfg, float *master_dev, uint16_t *w_bf16_dev);
 
+/* ------------------------------------------------------------- slides
+ * A whole slide is cut into tiles of tile x tile pixels (the last row and
+ * column ragged), each refined as an independent image over its core plus a
+ * halo of `halo` pixels (clipped at the slide edge), all tiles in one
+ * launch.  A tile's grid is the slide-wide grid of cell x cell superpixel
+ * cells over its extended region (the last cell of an axis absorbs a
+ * remainder narrower than a cell).  Only core pixels are written, each with
+ * the slide-wide id (row * ceil(W / cell) + col) of the initial cell of its
+ * superpixel; superpixels are not stitched across tiles.  tile and halo must
+ * be multiples of cell, tile + 2 halo <= RAPID_MAX_DIM.  params->K, gx, gy
+ * are ignored. */
+typedef struct {
+    const uint8_t *rgb_dev;      /* HWC uint8 slide                           */
+    int64_t W, H, row_stride_bytes;
+    int32_t *labels_dev;         /* int32 slide labels, label_stride elements */
+    int64_t label_stride;
+    int32_t tile, halo, cell;
+    int32_t reserved;
+} rapid_slide;
+
+/* Number of tiles of a slide (host only). */
+rapid_status rapid_slide_tiles(const rapid_slide *slide, int32_t *n_tiles);
+
+/* Segment a slide (plain when model is NULL, else gated as in
+ * rapid_segment_gated).  reports: NULL or rapid_slide_tiles() entries, tile
+ * order row-major. */
+rapid_status rapid_segment_slide(rapid_ctx *ctx, const rapid_slide *slide, const rapid_params *params,
+                                 const rapid_gate_model *model, rapid_report *reports);
+
 /* Grid of a target count (see rapid_params.K).  Host only, no device. */
 rapid_status rapid_grid(int32_t W, int32_t H, int32_t K, int32_t *gx, int32_t *gy);
 

@@ -550,8 +550,14 @@ struct Batch {
     int64_t *xoff_dev = nullptr;
 };
 
+struct TileInfo {
+    int32_t gx, gy, core_x0, core_y0, core_w, core_h;
+    int64_t gid_x0, gid_y0, gid_w;
+};
+
 rapid_status prepare_batch(rapid_ctx *ctx, const rapid_image *imgs, int32_t n, const rapid_params *params,
-                           const uint8_t *gate_dev, bool gated, Batch &b)
+                           const uint8_t *gate_dev, bool gated, Batch &b,
+                           const TileInfo *tiles = nullptr)
 {
     rapid_status r = make_sched(params, &b.sc, nullptr);
     if (r) return r;
@@ -568,7 +574,15 @@ rapid_status prepare_batch(rapid_ctx *ctx, const rapid_image *imgs, int32_t n, c
     b.xoff.assign(n, 0);
     for (int i = 0; i < n; i++) {
         if ((r = check_image(&imgs[i], true))) return r;
-        if ((r = image_grid(&imgs[i], params, sc, &gxs[i], &gys[i]))) return r;
+        if (tiles) {
+            rapid_params pt = *params;
+            pt.K = 0;
+            pt.gx = tiles[i].gx;
+            pt.gy = tiles[i].gy;
+            if ((r = image_grid(&imgs[i], &pt, sc, &gxs[i], &gys[i]))) return r;
+        } else if ((r = image_grid(&imgs[i], params, sc, &gxs[i], &gys[i]))) {
+            return r;
+        }
         lay[i] = plan(imgs[i].W, imgs[i].H, gxs[i] * gys[i], sc);
         total += lay[i].bytes;
         b.Kmax = std::max(b.Kmax, gxs[i] * gys[i]);
@@ -603,10 +617,21 @@ rapid_status prepare_batch(rapid_ctx *ctx, const rapid_image *imgs, int32_t n, c
         fill_job(b.jobs[i], ctx->pool + off, lay[i], &imgs[i], gxs[i], gys[i], gate_dev);
         if (gated) b.jobs[i].moved = reinterpret_cast<int64_t *>(ctx->pool + off + lay[i].off_moved);
         off += lay[i].bytes;
-        // a final stage of single pixels writes its label map straight into
-        // the caller's contiguous label buffer
-        if (sc.B[sc.n_stages - 1] == 1 && imgs[i].label_stride == imgs[i].W)
+        if (tiles) {
+            Job &J = b.jobs[i];
+            J.tile = 1;
+            J.core_x0 = tiles[i].core_x0;
+            J.core_y0 = tiles[i].core_y0;
+            J.core_w = tiles[i].core_w;
+            J.core_h = tiles[i].core_h;
+            J.gid_x0 = tiles[i].gid_x0;
+            J.gid_y0 = tiles[i].gid_y0;
+            J.gid_w = tiles[i].gid_w;
+        } else if (sc.B[sc.n_stages - 1] == 1 && imgs[i].label_stride == imgs[i].W) {
+            // a final stage of single pixels writes its label map straight
+            // into the caller's contiguous label buffer
             b.jobs[i].lab[(sc.n_stages - 1) & 1] = imgs[i].labels_dev;
+        }
     }
     if (gated) {
         b.X = reinterpret_cast<float *>(ctx->pool + off_x);
@@ -638,13 +663,13 @@ extern "C" {
 
 static rapid_status segment_impl(rapid_ctx *ctx, const rapid_image *imgs, int32_t n,
                                  const rapid_params *params, const uint8_t *gate_dev,
-                                 rapid_report *reports)
+                                 rapid_report *reports, const TileInfo *tiles = nullptr)
 {
     if (!ctx || !imgs || n < 1 || !params) return RAPID_EINVAL;
     std::lock_guard<std::mutex> lock(ctx->mu);
     if (hipSetDevice(ctx->device) != hipSuccess) return RAPID_EDEVICE;
     Batch b;
-    rapid_status r = prepare_batch(ctx, imgs, n, params, gate_dev, false, b);
+    rapid_status r = prepare_batch(ctx, imgs, n, params, gate_dev, false, b, tiles);
     if (r) return r;
     if ((r = run_jobs(ctx, b.jobs, b.sc, 0, b.sc.n_stages, FLAG_INIT | FLAG_OUT, b.Kmax, b.nbF_max, b.max_nb)))
         return r;
@@ -664,19 +689,20 @@ rapid_status rapid_segment_batch(rapid_ctx *ctx, const rapid_image *imgs, int32_
     return segment_impl(ctx, imgs, n, params, nullptr, reports);
 }
 
-rapid_status rapid_segment_gated(rapid_ctx *ctx, const rapid_image *imgs, int32_t n,
-                                 const rapid_params *params, const rapid_gate_model *model,
-                                 float *features_dev, uint8_t *gate_dev, rapid_report *reports)
+static rapid_status gated_impl(rapid_ctx *ctx, const rapid_image *imgs, int32_t n,
+                               const rapid_params *params, const rapid_gate_model *model,
+                               float *features_dev, uint8_t *gate_dev, rapid_report *reports,
+                               const TileInfo *tiles = nullptr)
 {
     if (!ctx || !imgs || n < 1 || !params || !model || !model->w_bf16_dev) return RAPID_EINVAL;
     if (!model_finite(model->w_bf16_dev, ctx->stream)) {
-        rapid_status r = segment_impl(ctx, imgs, n, params, nullptr, reports);
+        rapid_status r = segment_impl(ctx, imgs, n, params, nullptr, reports, tiles);
         return r ? r : RAPID_EGATE;
     }
     std::lock_guard<std::mutex> lock(ctx->mu);
     if (hipSetDevice(ctx->device) != hipSuccess) return RAPID_EDEVICE;
     Batch b;
-    rapid_status r = prepare_batch(ctx, imgs, n, params, nullptr, true, b);
+    rapid_status r = prepare_batch(ctx, imgs, n, params, nullptr, true, b, tiles);
     if (r) return r;
     const int gs = b.sc.gate_stage;
     // levels before the gate
@@ -708,6 +734,69 @@ rapid_status rapid_segment_gated(rapid_ctx *ctx, const rapid_image *imgs, int32_
         }
     }
     return RAPID_OK;
+}
+
+rapid_status rapid_segment_gated(rapid_ctx *ctx, const rapid_image *imgs, int32_t n,
+                                 const rapid_params *params, const rapid_gate_model *model,
+                                 float *features_dev, uint8_t *gate_dev, rapid_report *reports)
+{
+    return gated_impl(ctx, imgs, n, params, model, features_dev, gate_dev, reports);
+}
+
+rapid_status rapid_slide_tiles(const rapid_slide *sl, int32_t *n_tiles)
+{
+    if (!sl || !n_tiles) return RAPID_EINVAL;
+    if (sl->W < 1 || sl->H < 1 || sl->tile < 1 || sl->halo < 0 || sl->cell < 1) return RAPID_EINVAL;
+    if (sl->tile % sl->cell || sl->halo % sl->cell) return RAPID_EINVAL;
+    if (sl->tile + 2 * (int64_t)sl->halo > RAPID_MAX_DIM) return RAPID_EINVAL;
+    int64_t nt = ((sl->W + sl->tile - 1) / sl->tile) * ((sl->H + sl->tile - 1) / sl->tile);
+    if (nt > (1 << 20)) return RAPID_EINVAL;
+    *n_tiles = (int32_t)nt;
+    return RAPID_OK;
+}
+
+rapid_status rapid_segment_slide(rapid_ctx *ctx, const rapid_slide *sl, const rapid_params *params,
+                                 const rapid_gate_model *model, rapid_report *reports)
+{
+    int32_t nt;
+    rapid_status r = rapid_slide_tiles(sl, &nt);
+    if (r) return r;
+    if (!ctx || !params || !sl->rgb_dev || !sl->labels_dev || sl->row_stride_bytes < 3 * sl->W ||
+        sl->label_stride < sl->W)
+        return RAPID_EINVAL;
+    const int64_t T = sl->tile, h = sl->halo, c = sl->cell;
+    const int64_t ntx = (sl->W + T - 1) / T;
+    const int64_t gid_w = (sl->W + c - 1) / c;
+    std::vector<rapid_image> imgs(nt);
+    std::vector<TileInfo> info(nt);
+    for (int32_t t = 0; t < nt; t++) {
+        const int64_t tx = t % ntx, ty = t / ntx;
+        const int64_t cx0 = tx * T, cy0 = ty * T;
+        const int64_t cx1 = std::min<int64_t>(cx0 + T, sl->W), cy1 = std::min<int64_t>(cy0 + T, sl->H);
+        const int64_t ex0 = std::max<int64_t>(0, cx0 - h), ey0 = std::max<int64_t>(0, cy0 - h);
+        const int64_t ex1 = std::min<int64_t>(sl->W, cx1 + h), ey1 = std::min<int64_t>(sl->H, cy1 + h);
+        rapid_image &im = imgs[t];
+        im.rgb_dev = sl->rgb_dev + ey0 * sl->row_stride_bytes + 3 * ex0;
+        im.W = (int32_t)(ex1 - ex0);
+        im.H = (int32_t)(ey1 - ey0);
+        im.row_stride_bytes = sl->row_stride_bytes;
+        im.labels_dev = sl->labels_dev + ey0 * sl->label_stride + ex0;
+        im.label_stride = sl->label_stride;
+        TileInfo &ti = info[t];
+        // cells of the slide-wide grid (the last one per axis absorbs a
+        // ragged remainder narrower than a cell)
+        ti.gx = (int32_t)std::max<int64_t>(1, im.W / c);
+        ti.gy = (int32_t)std::max<int64_t>(1, im.H / c);
+        ti.core_x0 = (int32_t)(cx0 - ex0);
+        ti.core_y0 = (int32_t)(cy0 - ey0);
+        ti.core_w = (int32_t)(cx1 - cx0);
+        ti.core_h = (int32_t)(cy1 - cy0);
+        ti.gid_x0 = ex0 / c;
+        ti.gid_y0 = ey0 / c;
+        ti.gid_w = gid_w;
+    }
+    if (model) return gated_impl(ctx, imgs.data(), nt, params, model, nullptr, nullptr, reports, info.data());
+    return segment_impl(ctx, imgs.data(), nt, params, nullptr, reports, info.data());
 }
 
 rapid_status rapid_state_create(rapid_ctx *ctx, const rapid_image *img, const rapid_params *params,

@@ -71,6 +71,11 @@ struct Job {
     // gate feature scratch
     int32_t *fmean;          // K x 3 fixed-point means
     int64_t *facc;           // K x FACC accumulators
+    // slide tiles: only the core [core_x0, +core_w) x [core_y0, +core_h) of
+    // the tile is written, label k as the slide cell id
+    // (gid_y0 + k / gx) * gid_w + gid_x0 + k % gx
+    int32_t tile, core_x0, core_y0, core_w, core_h, pad3;
+    int64_t gid_x0, gid_y0, gid_w;
 };
 
 hipError_t launch_block_sums(const Job *jobs_dev, int n_jobs, int s, int B, int64_t max_nb,

@@ -648,7 +648,19 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
     }
     if (LDS)
         for (int64_t i = tid; i < 6 * (int64_t)K; i += nt) J.stats[i] = st[i];
-    if ((flags & FLAG_OUT) && s_end > 0) {
+    if ((flags & FLAG_OUT) && s_end > 0 && J.tile) {
+        // slide tile: core pixels only, labels as slide-wide cell ids
+        const int B = sc.B[s_end - 1];
+        const int nbx = (W + B - 1) / B;
+        const int32_t *L = J.lab[(s_end - 1) & 1];
+        const int64_t ncore = (int64_t)J.core_w * J.core_h;
+        for (int64_t i = tid; i < ncore; i += nt) {
+            const int x = J.core_x0 + (int)(i % J.core_w), y = J.core_y0 + (int)(i / J.core_w);
+            const int32_t k = L[(y / B) * nbx + x / B];
+            J.out[(int64_t)y * J.out_stride + x] =
+                (int32_t)((J.gid_y0 + k / J.gx) * J.gid_w + J.gid_x0 + k % J.gx);
+        }
+    } else if ((flags & FLAG_OUT) && s_end > 0) {
         const int B = sc.B[s_end - 1];
         const int nbx = (W + B - 1) / B;
         const int32_t *L = J.lab[(s_end - 1) & 1];

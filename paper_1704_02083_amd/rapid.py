@@ -88,6 +88,13 @@ class TrainCfg(C.Structure):
                 ("seed", C.c_uint64)]
 
 
+class Slide(C.Structure):
+    _fields_ = [("rgb_dev", C.c_void_p), ("W", C.c_int64), ("H", C.c_int64),
+                ("row_stride_bytes", C.c_int64), ("labels_dev", C.c_void_p),
+                ("label_stride", C.c_int64), ("tile", C.c_int32), ("halo", C.c_int32),
+                ("cell", C.c_int32), ("reserved", C.c_int32)]
+
+
 MLP_PARAMS = 5313
 N_FEATURES = 16
 
@@ -117,13 +124,16 @@ _lib.rapid_state_features.argtypes = [_P, _P, _P]
 _lib.rapid_mlp_forward.argtypes = [_P, _P, C.c_int64, _P, C.c_float, _P, _P]
 _lib.rapid_mlp_grad.argtypes = [_P, _P, _P, _P, C.c_int32, _P, _P, _P]
 _lib.rapid_gate_train.argtypes = [_P, _P, _P, C.c_int64, C.POINTER(TrainCfg), _P, _P]
+_lib.rapid_slide_tiles.argtypes = [C.POINTER(Slide), C.POINTER(C.c_int32)]
+_lib.rapid_segment_slide.argtypes = [_P, C.POINTER(Slide), C.POINTER(Params), C.POINTER(GateModel),
+                                     C.POINTER(Report)]
 
 EXPORTED = ["rapid_init", "rapid_destroy", "rapid_segment", "rapid_segment_batch",
             "rapid_state_create", "rapid_refine_level", "rapid_state_export",
             "rapid_state_destroy", "rapid_grid", "rapid_status_str", "rapid_simple_lut",
             "rapid_check_params", "rapid_last_timings", "rapid_segment_gated",
             "rapid_state_track", "rapid_state_features", "rapid_mlp_forward", "rapid_mlp_grad",
-            "rapid_gate_train"]
+            "rapid_gate_train", "rapid_slide_tiles", "rapid_segment_slide"]
 
 
 def _check(rc: int, where: str):
@@ -166,6 +176,29 @@ def simple_lut() -> list:
     out = (C.c_uint32 * 8)()
     _check(_lib.rapid_simple_lut(out), "rapid_simple_lut")
     return [int(v) for v in out]
+
+
+def slide_tiles(W: int, H: int, tile: int, halo: int, cell: int) -> int:
+    sl = Slide(None, W, H, 3 * W, None, W, tile, halo, cell, 0)
+    n = C.c_int32()
+    _check(_lib.rapid_slide_tiles(C.byref(sl), C.byref(n)), "rapid_slide_tiles")
+    return n.value
+
+
+def tile_layout(W: int, H: int, tile: int, halo: int, cell: int):
+    """Tiles of a slide as dicts (core and extended rectangles, grid and the
+    slide-cell offset of the grid), in the library's row-major order."""
+    out = []
+    for ty in range(-(-H // tile)):
+        for tx in range(-(-W // tile)):
+            cx0, cy0 = tx * tile, ty * tile
+            cx1, cy1 = min(cx0 + tile, W), min(cy0 + tile, H)
+            ex0, ey0 = max(0, cx0 - halo), max(0, cy0 - halo)
+            ex1, ey1 = min(W, cx1 + halo), min(H, cy1 + halo)
+            out.append({"core": (cx0, cy0, cx1, cy1), "ext": (ex0, ey0, ex1, ey1),
+                        "gx": max(1, (ex1 - ex0) // cell), "gy": max(1, (ey1 - ey0) // cell),
+                        "gid_x0": ex0 // cell, "gid_y0": ey0 // cell, "gid_w": -(-W // cell)})
+    return out
 
 
 def check_params(W: int, H: int, d: dict) -> int:
@@ -267,6 +300,25 @@ class Context:
                                       C.c_void_p(g.data_ptr()), reps)
         _check(rc, "rapid_segment_gated")
         return labels, ([r.stages() for r in reps] if reps is not None else None), X, g
+
+    # rapid_segment_slide
+    def segment_slide(self, rgb, params: dict, tile: int = 2048, halo: int = 64, cell: int = 32,
+                      labels=None, w_bf16=None, thresh: float = 0.0, report: bool = False):
+        import torch
+        H, W = int(rgb.shape[0]), int(rgb.shape[1])
+        assert rgb.is_cuda and rgb.dtype == torch.uint8 and rgb.stride(1) == 3 and rgb.stride(2) == 1
+        if labels is None:
+            labels = torch.empty((H, W), dtype=torch.int32, device=rgb.device)
+        sl = Slide(rgb.data_ptr(), W, H, int(rgb.stride(0)), labels.data_ptr(), int(labels.stride(0)),
+                   tile, halo, cell, 0)
+        nt = slide_tiles(W, H, tile, halo, cell)
+        p = make_params(dict(params, K=0, gx=1, gy=1))
+        model = GateModel(w_bf16.data_ptr(), thresh) if w_bf16 is not None else None
+        reps = (Report * nt)() if report else None
+        _check(_lib.rapid_segment_slide(self._h, C.byref(sl), C.byref(p),
+                                        C.byref(model) if model is not None else None, reps),
+               "rapid_segment_slide")
+        return labels, ([r.stages() for r in reps] if reps is not None else None)
 
     def mlp_forward(self, X, w_bf16, thresh: float = 0.0):
         import torch

@@ -72,3 +72,24 @@ def test_check_params_rejects(mutate):
 def test_check_params_rejects_big_image():
     with pytest.raises(rapid.RapidError):
         rapid.check_params(8193, 16, params.default_params(8193, 16, 1))
+
+
+def test_slide_tile_counts():
+    assert rapid.slide_tiles(32768, 32768, 2048, 64, 32) == 256
+    assert rapid.slide_tiles(65536, 49152, 2048, 64, 32) == 768
+    assert rapid.slide_tiles(1000, 700, 256, 64, 32) == 12
+    lay = rapid.tile_layout(1000, 700, 256, 64, 32)
+    assert lay[-1]["core"] == (768, 512, 1000, 700) and lay[-1]["ext"] == (704, 448, 1000, 700)
+    # every slide pixel lies in exactly one core
+    cover = np.zeros((700, 1000), np.int32)
+    for t in lay:
+        x0, y0, x1, y1 = t["core"]
+        cover[y0:y1, x0:x1] += 1
+    assert (cover == 1).all()
+
+
+@pytest.mark.parametrize("args", [(100, 100, 48, 16, 32), (100, 100, 64, 10, 32), (100, 100, 64, 16, 0),
+                                  (100, 100, 8192, 64, 32)])
+def test_slide_rejects(args):
+    with pytest.raises(rapid.RapidError):
+        rapid.slide_tiles(*args)
