@@ -434,8 +434,19 @@ static int64_t propose(state *s, int32_t cls, const uint8_t *active,
     const orc_params *p = s->p;
     int64_t np = 0;
     int32_t ci = cls % 3, cj = cls / 3;
-    for (int64_t oi = 0; oi < norder; oi++) {
-        int64_t bi = order[oi];
+    /* the blocks of the class: in the given order, or (order == NULL) row by
+     * row stepping over the class's rows and columns */
+    int64_t ncls = order ? norder
+                         : (int64_t)((s->nby - cj + 2) / 3) * ((s->nbx - ci + 2) / 3);
+    int32_t ncol = (s->nbx - ci + 2) / 3;
+    for (int64_t oi = 0; oi < ncls; oi++) {
+        int64_t bi;
+        if (order) {
+            bi = order[oi];
+        } else {
+            if (ncol <= 0) break;
+            bi = (int64_t)(cj + 3 * (int32_t)(oi / ncol)) * s->nbx + ci + 3 * (int32_t)(oi % ncol);
+        }
         int32_t bx = (int32_t)(bi % s->nbx), by = (int32_t)(bi / s->nbx);
         if (bx % 3 != ci || by % 3 != cj) continue;
         if (active && !active[bi]) continue;
@@ -516,7 +527,7 @@ static int run_stage(state *s, int32_t level, int32_t B, int32_t *lab,
         int64_t sweep_commits = 0;
         for (int32_t cls = 0; cls < 9; cls++) {
             int64_t np = propose(s, cls, active, props, &rep->skip_min, &rep->skip_topo,
-                                 order, nb);
+                                 p->shuffle_seed ? order : NULL, nb);
             rep->proposals += np;
             if (np == 0) continue;
             /* class-wide size filter: out/in flows of every proposal */
@@ -577,16 +588,21 @@ static int run_stage(state *s, int32_t level, int32_t B, int32_t *lab,
         rep->sweeps = t + 1;
         if (sweep_commits == 0) { rep->converged = 1; break; }
         /* next active set: eligible blocks within one block of a changed one */
+        memset(active, 0, nb);
         for (int32_t by = 0; by < s->nby; by++)
             for (int32_t bx = 0; bx < s->nbx; bx++) {
-                int near = 0;
-                for (int dy = -1; dy <= 1 && !near; dy++)
-                    for (int dx = -1; dx <= 1 && !near; dx++) {
+                if (!changed[(int64_t)by * s->nbx + bx]) continue;
+                for (int dy = -1; dy <= 1; dy++)
+                    for (int dx = -1; dx <= 1; dx++) {
                         int32_t x = bx + dx, y = by + dy;
-                        if (x >= 0 && y >= 0 && x < s->nbx && y < s->nby &&
-                            changed[(int64_t)y * s->nbx + x]) near = 1;
+                        if (x >= 0 && y >= 0 && x < s->nbx && y < s->nby)
+                            active[(int64_t)y * s->nbx + x] = 1;   /* near a change */
                     }
-                active[(int64_t)by * s->nbx + bx] = (uint8_t)(near && eligible(s, bx, by));
+            }
+        for (int32_t by = 0; by < s->nby; by++)
+            for (int32_t bx = 0; bx < s->nbx; bx++) {
+                int64_t bi = (int64_t)by * s->nbx + bx;
+                if (active[bi]) active[bi] = (uint8_t)eligible(s, bx, by);
             }
     }
     /* write the block labels back to the pixels */
@@ -730,7 +746,7 @@ int orc_propose_class(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
     if (!pr || !act || !order) { rc = ORC_ENOMEM; goto done; }
     for (int64_t i = 0; i < nb; i++) { order[i] = i; act[i] = (uint8_t)eligible(&s, (int32_t)(i % s.nbx), (int32_t)(i / s.nbx)); }
     int64_t sm = 0, stp = 0;
-    int64_t np = propose(&s, cls, act, pr, &sm, &stp, order, nb);
+    int64_t np = propose(&s, cls, act, pr, &sm, &stp, NULL, nb);
     if (np > max_props) { rc = ORC_EINVAL; goto done; }
     for (int64_t q = 0; q < np; q++) {
         props[3 * q] = pr[q].b; props[3 * q + 1] = pr[q].a; props[3 * q + 2] = pr[q].k;
