@@ -39,6 +39,13 @@ def kernel_source_hash() -> str:
 
 def workload(name: str):
     from paper_1704_02083_amd import params, synth
+    if name == "slide":
+        return None, params.default_params(2048, 2048, 4096, levels=params.THREE_LEVEL, gate_level=1), (
+            "whole-slide-like: 32768x32768 RGB uint8 synthetic H&E (40% background), 2048x2048 tiles "
+            "with 64-px halo in one launch, 32-px cells (1,048,576 superpixels), three levels 16|8,4|2,1")
+    if name == "he4096":
+        return None, params.config3(gate_level=1), (
+            "one 4096x4096 RGB uint8 synthetic H&E tile (30% background), K=16384, three levels 16|8,4|2,1")
     if name == "batch":
         imgs = synth.batch_images(200)
         p = params.config2(481, 321)
@@ -67,6 +74,22 @@ def refine_alg_bytes(imgs, reports) -> float:
         for r in rep:
             B = r["block"]
             nb = -(-W // B) * -(-H // B)
+            sb = 3 if B == 1 else 8
+            total += 8 * nb + r["active"] * (36 + sb) + r["commits"] * (4 + sb)
+    return float(total)
+
+
+def tiles_alg_bytes(W, H, tiles, reports) -> float:
+    """As refine_alg_bytes for the tiles of a slide: the stages run over each
+    tile's extended rectangle (core plus halo), the final labels are written
+    for the core pixels only, so once per slide pixel."""
+    total = 4 * W * H
+    for t, rep in zip(tiles, reports):
+        x0, y0, x1, y1 = t["ext"]
+        w, h = x1 - x0, y1 - y0
+        for r in rep:
+            B = r["block"]
+            nb = -(-w // B) * -(-h // B)
             sb = 3 if B == 1 else 8
             total += 8 * nb + r["active"] * (36 + sb) + r["commits"] * (4 + sb)
     return float(total)
@@ -117,7 +140,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batch", choices=["batch", "single256"])
+    ap.add_argument("--workload", default="batch", choices=["batch", "single256", "he4096", "slide"])
+    ap.add_argument("--gated", action="store_true",
+                    help="H&E workloads: also train the gate on 32 tiles and time the gated path")
     ap.add_argument("--cpu-sample", type=int, default=80)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -142,6 +167,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": n, "launches": 3}), flush=True)
         return
+
+    if args.workload in ("slide", "he4096"):
+        return bench_he(args)
 
     imgs, p, desc = workload(args.workload)
     print("bench: workload %s, %d images generated" % (args.workload, len(imgs)), file=sys.stderr,
@@ -215,6 +243,104 @@ def main():
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(imgs, p, args.cpu_sample)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def train_gate(ctx, p_tile, seed=0):
+    """Gate network trained on 16 synthetic 2048x2048 H&E tiles with 32-px
+    cells (features and targets from plain runs, all on the GPU through the
+    C-ABI)."""
+    import torch
+    from paper_1704_02083_amd import gate, params, synth_gpu
+    tiles = [synth_gpu.he_slide(2048, 2048, seed=9000 + i, background=0.4, device="cuda")
+             for i in range(16)]
+    p = params.default_params(2048, 2048, 4096, levels=params.THREE_LEVEL, gate_level=1)
+    X, t = gate.training_set(ctx, tiles, p, tau=0.1)
+    master, w = gate.train(ctx, X, t, epochs=20, batch=4096, seed=seed)
+    torch.cuda.synchronize()
+    return w, {"samples": int(X.shape[0]), "positive_rate": round(float(t.float().mean().item()), 4)}
+
+
+def bench_he(args):
+    """H&E workloads: one 4096^2 image or a 32768^2 slide; plain, and gated
+    when asked."""
+    import torch
+    from paper_1704_02083_amd import metrics, rapid, synth_gpu
+    _, p, desc = workload(args.workload)
+    ctx = rapid.Context(0, timing=True)
+    if args.workload == "slide":
+        W = H = 32768
+        rgb = synth_gpu.he_slide(W, H, seed=4, background=0.4, device="cuda", band=2048)
+        labels = torch.empty((H, W), dtype=torch.int32, device="cuda")
+
+        def run(w=None, th=0.0):
+            ctx.segment_slide(rgb, p, tile=2048, halo=64, cell=32, labels=labels, w_bf16=w, thresh=th)
+    else:
+        W = H = 4096
+        rgb = synth_gpu.he_slide(W, H, seed=3, background=0.3, device="cuda")
+        labels = torch.empty((H, W), dtype=torch.int32, device="cuda")
+
+        def run(w=None, th=0.0):
+            if w is None:
+                ctx.segment(rgb, p, labels=labels, report=False)
+            else:
+                ctx.segment_gated([rgb], p, w, th, labels=[labels], report=False)
+    torch.cuda.synchronize()
+    print("bench: %s generated" % args.workload, file=sys.stderr, flush=True)
+
+    def timed(fn, steps, warm):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        ref_ms = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+            ref_ms.append(ctx.last_timings()["refine_ms"])
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, ref_ms
+
+    steps, warm = max(1, min(args.steps, 5)), max(0, min(args.warmup, 2))
+    dt, ref_ms = timed(lambda: run(), steps, warm)
+    plain = labels.clone()
+    # per-stage counters of the same deterministic work, from one untimed call
+    if args.workload == "slide":
+        _, reps = ctx.segment_slide(rgb, p, tile=2048, halo=64, cell=32, labels=labels, report=True)
+        alg = tiles_alg_bytes(W, H, rapid.tile_layout(W, H, 2048, 64, 32), reps)
+    else:
+        _, r = ctx.segment(rgb, p, labels=labels, report=True)
+        alg = refine_alg_bytes([rgb], [r])
+    avg_refine = sum(ref_ms) / len(ref_ms)
+    achieved = alg / (avg_refine * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(W * H / dt / 1e6, 3), "unit": "MPixel/s", "n_gpus": 1,
+        "steps": steps, "warmup": warm, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": desc, "pixels": W * H, "path": "plain"},
+        "roofline": {"bound": "hbm", "kernel": "k_refine", "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "avg_launch_ms": round(avg_refine, 3), "achieved": round(achieved, 3),
+                     "frac": round(achieved / HBM_PEAK_GBS, 6),
+                     "traffic": profile_traffic("k_refine", args.workload, kernel_source_hash()),
+                     "alg_bytes_per_launch": alg},
+    }
+    if args.gated:
+        w, info = train_gate(ctx, p)
+        # agreement on full-resolution 4096^2 crops (all of a single image)
+        crops = [(0, 0)] if args.workload != "slide" else [(1000, 3000), (9000, 17000), (20000, 7000),
+                                                             (28000, 28000)]
+        res = {}
+        for th in (0.0, -1.0, -2.0):
+            dtg, _ = timed(lambda: run(w, th), steps, 1)
+            ms = [metrics.agreement(plain[y:y + 4096, x:x + 4096].cpu().numpy(),
+                                    labels[y:y + 4096, x:x + 4096].cpu().numpy()) for y, x in crops]
+            res[str(th)] = {"MPixel/s": round(W * H / dtg / 1e6, 3), "ms": round(dtg * 1e3, 3),
+                            "speedup": round(dt / dtg, 4)}
+            for k in ("br", "ue", "disagreement"):
+                res[str(th)][k] = round(float(sum(m[k] for m in ms) / len(ms)), 6)
+        out["gated"] = {"train": info, "by_threshold": res,
+                        "note": "agreement of the gated labels with the plain labels on %d "
+                                "4096x4096 crops" % len(crops)}
     ctx.close()
     print(json.dumps(out), flush=True)
 
