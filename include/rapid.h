@@ -53,6 +53,11 @@ typedef struct rapid_state rapid_state;   /* opaque, library-owned */
 
 #define RAPID_CFG_TIMING 1   /* record HIP events around every kernel launch */
 
+/* rapid_params.gate_rule values */
+#define RAPID_GATE_EITHER 0
+#define RAPID_GATE_BOTH 1
+#define RAPID_GATE_DIFFER 2
+
 typedef struct {
     int32_t abi_version;   /* RAPID_ABI_VERSION */
     int32_t device;        /* HIP device ordinal */
@@ -82,6 +87,14 @@ typedef struct {
  *             the prediction at the second level); -1: never.
  *  frac_bits  F, fixed-point fraction bits of the means (0..4).
  *  max_sweeps sweep cap per stage (>= 1).
+ *  gate_rule  how the per-superpixel gate bits g select the pairs (a, k)
+ *             that may exchange blocks past the gate level (Eq. (7)):
+ *             RAPID_GATE_EITHER  g_a or g_k (g = 1 everywhere is the plain
+ *                                method),
+ *             RAPID_GATE_BOTH    g_a and g_k,
+ *             RAPID_GATE_DIFFER  g_a != g_k: g holds a predicted class and
+ *                                only pairs across a class border refine,
+ *                                as the paper's boundary superpixels.
  *  min_size, max_size  hard size bounds in pixels (Sec. 3.1, Eq. (5)).
  *  w_col, w_pos, w_bnd integer weights of colour, position and boundary
  *             terms (Eq. (1)); rejected when the worst-case block energy
@@ -95,7 +108,7 @@ typedef struct {
     int32_t gate_level;
     int32_t frac_bits;
     int32_t max_sweeps;
-    int32_t reserved;
+    int32_t gate_rule;     /* RAPID_GATE_*: which pairs a gate lets move */
     int64_t min_size, max_size;
     int64_t w_col, w_pos, w_bnd;
 } rapid_params;
@@ -208,6 +221,21 @@ rapid_status rapid_state_track(rapid_state *st, uint8_t *involved_dev, int64_t *
  * (X_dev: gx*gy rows of 16 float32).  Feature 13 uses the moved counts
  * tracked so far (zero when not tracked). */
 rapid_status rapid_state_features(rapid_ctx *ctx, rapid_state *st, float *X_dev);
+
+/* Misses of the boundary recall (Sec. 4.2) of test against ref, two W x H
+ * int32 label maps on the device with the same row stride (in elements):
+ * a boundary pixel of ref (one with a 4-neighbour of another label) is
+ * missed when test has no boundary pixel within Chebyshev distance radius
+ * (0..4).  Each miss adds 1 to miss_dev[ref label] and 1 to
+ * miss_dev[test label] (2 when they agree) for labels in [0, K); miss_dev
+ * (nullable, K int32) and totals_dev (nullable, 2 int64: ref boundary
+ * pixels, misses) accumulate, so the caller zeroes them.  Boundary recall is
+ * 1 - totals[1] / totals[0].  With ref the final plain labels and test the
+ * labels at the gate point, miss_dev counts how far each superpixel's
+ * boundary still travels: the gate's training target.  Stream-ordered. */
+rapid_status rapid_boundary_miss(rapid_ctx *ctx, const int32_t *ref_dev, const int32_t *test_dev, int32_t W,
+                                 int32_t H, int64_t stride, int32_t radius, int32_t K, int32_t *miss_dev,
+                                 int64_t *totals_dev);
 
 /* Network forward pass on n feature rows: logits_dev (nullable) receives
  * h(x); gate_dev (nullable) receives [h(x) >= thresh]. */

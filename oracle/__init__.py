@@ -10,6 +10,8 @@ Parameter dictionary (also accepted by the GPU binding):
     gx, gy       explicit grid when K == 0
     levels       list of (factor, [block sizes in level pixels]) coarse→fine
     gate_level   first level refined under the gate (-1: never)
+    gate_rule    "either" (default), "both" or "differ": the pairs a gate lets
+                 move
     frac_bits    fixed-point fraction bits F of the means
     max_sweeps   sweep cap per stage
     min_size, max_size   hard size bounds in pixels
@@ -28,6 +30,7 @@ _SRC = os.path.join(_HERE, "rapid_oracle.c")
 _LIB = os.path.join(_HERE, "librapid_oracle.so")
 
 MAX_LEVELS = 4
+GATE_RULES = {"either": 0, "both": 1, "differ": 2}
 MAX_STAGES = 8
 
 
@@ -53,7 +56,7 @@ class OrcParams(C.Structure):
         ("n_stages", C.c_int32 * MAX_LEVELS),
         ("stages", (C.c_int32 * MAX_STAGES) * MAX_LEVELS),
         ("gate_level", C.c_int32), ("frac_bits", C.c_int32),
-        ("max_sweeps", C.c_int32), ("shuffle_seed", C.c_int32),
+        ("max_sweeps", C.c_int32), ("shuffle_seed", C.c_int32), ("gate_rule", C.c_int32),
         ("min_size", C.c_int64), ("max_size", C.c_int64),
         ("w_col", C.c_int64), ("w_pos", C.c_int64), ("w_bnd", C.c_int64),
     ]
@@ -112,6 +115,7 @@ def make_params(d: dict, shuffle_seed: int = 0) -> OrcParams:
     p.frac_bits = int(d.get("frac_bits", 4))
     p.max_sweeps = int(d.get("max_sweeps", 64))
     p.shuffle_seed = int(shuffle_seed)
+    p.gate_rule = GATE_RULES[d.get("gate_rule", "either")]
     p.min_size = int(d["min_size"])
     p.max_size = int(d["max_size"])
     p.w_col = int(d["w_col"])

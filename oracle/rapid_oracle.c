@@ -19,8 +19,10 @@
  *   - the stage loop of Algorithm RAPID: grid initialisation, blocks that
  *     shrink stage by stage, a boundary set that is processed until no block
  *     changes, statistics kept up to date after moves;
- *   - the prediction gate of Eqs. (6)-(7): past the gate level only pairs of
- *     superpixels at least one of which the gate marks take part;
+ *   - the prediction gate of Eqs. (6)-(7): past the gate level only some
+ *     pairs of superpixels take part: those with at least one marked side
+ *     (rule "either"), with both sides marked ("both"), or whose predicted
+ *     classes differ (rule "differ", the paper's boundary superpixels);
  *   - the adaptive multi-level framework of Sec. 3.2 (Eq. (8)): statistics
  *     are computed once, at the first level, and carried to finer levels.
  *     Levels are exact integer box sums of the fine image, so a level-l block
@@ -249,10 +251,15 @@ static inline int32_t blabel(const state *s, int32_t bx, int32_t by)
 
 static inline int pair_active(const state *s, int32_t a, int32_t k)
 {
-    /* Eq. (7) realised per superpixel: a pair takes part when either side is
-     * marked by the gate (no gate: every pair). */
+    /* Eq. (7): which pairs of superpixels may exchange blocks under the
+     * gate (no gate: every pair). */
     if (!s->gate) return 1;
-    return s->gate[a] || s->gate[k];
+    int ga = s->gate[a] != 0, gk = s->gate[k] != 0;
+    switch (s->p->gate_rule) {
+    case ORC_GATE_BOTH: return ga && gk;
+    case ORC_GATE_DIFFER: return ga != gk;   /* classes differ across the pair */
+    default: return ga || gk;
+    }
 }
 
 /* A block is a boundary element (Eq. (2), or Eq. (7) under the gate) when a
@@ -622,6 +629,7 @@ static int check_params(const orc_params *p, int32_t W, int32_t H)
     if (W < 1 || H < 1 || W > 8192 || H > 8192) return ORC_EINVAL;
     if (p->n_levels < 1 || p->n_levels > ORC_MAX_LEVELS) return ORC_EINVAL;
     if (p->frac_bits < 0 || p->frac_bits > 8 || p->max_sweeps < 1) return ORC_EINVAL;
+    if (p->gate_rule < ORC_GATE_EITHER || p->gate_rule > ORC_GATE_DIFFER) return ORC_EINVAL;
     if (p->w_col < 0 || p->w_pos < 0 || p->w_bnd < 0) return ORC_EINVAL;
     int32_t prev = 0;
     for (int l = 0; l < p->n_levels; l++) {

@@ -32,6 +32,7 @@ typedef struct {
     int32_t frac_bits;         /* F: fixed-point fraction bits of the means      */
     int32_t max_sweeps;
     int32_t shuffle_seed;      /* 0: natural block order; else a permutation    */
+    int32_t gate_rule;         /* ORC_GATE_*: pairs a gate lets move            */
     int64_t min_size, max_size;
     int64_t w_col, w_pos, w_bnd;
 } orc_params;
@@ -40,6 +41,11 @@ typedef struct {
     int32_t level, block, sweeps, converged;
     int64_t active, proposals, commits, skip_min, skip_topo;
 } orc_stage_report;
+
+/* gate rules (which pairs (a, k) may move past the gate level) */
+#define ORC_GATE_EITHER 0      /* g_a or g_k                                    */
+#define ORC_GATE_BOTH   1      /* g_a and g_k                                   */
+#define ORC_GATE_DIFFER 2      /* g_a != g_k (predicted classes differ)         */
 
 /* error codes */
 #define ORC_OK        0

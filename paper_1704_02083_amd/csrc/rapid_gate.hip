@@ -14,168 +14,41 @@
 //
 // Parameter vector (5313 values): W1 (64x16, row = output neuron), b1 (64),
 // W2 (64x64), b2 (64), w3 (64), b3 (1).
-#include "rapid_internal.h"
+#include "rapid_gate_dev.h"
 
 namespace rapid {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-constexpr int P_W1 = 0, P_B1 = 1024, P_W2 = 1088, P_B2 = 5184, P_W3 = 5248, P_B3 = 5312;
-
-// fp32 -> bf16 bits, round to nearest even (finite inputs)
-__device__ __forceinline__ uint16_t f2bf(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
-__device__ __forceinline__ float bf2f(uint16_t b)
-{
-    return __uint_as_float((uint32_t)b << 16);
-}
-
-__device__ __forceinline__ v4s pack4(float a, float b, float c, float d)
-{
-    v4s r;
-    r[0] = (short)f2bf(a);
-    r[1] = (short)f2bf(b);
-    r[2] = (short)f2bf(c);
-    r[3] = (short)f2bf(d);
-    return r;
-}
-
-__device__ __forceinline__ v4s load4bf(const uint16_t *p)
-{
-    v4s r;
-    r[0] = (short)p[0];
-    r[1] = (short)p[1];
-    r[2] = (short)p[2];
-    r[3] = (short)p[3];
-    return r;
-}
-
-__device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c)
-{
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-}
-
 // ------------------------------------------------------------- features
 
-// Pass A: fixed-point means of every superpixel, accumulators cleared.
+// Stand-alone feature passes (one job per blockIdx.y); the steps are the
+// device functions of rapid_gate_dev.h.
 __global__ void k_feat_init(const Job *__restrict__ jobs, int F)
 {
     const Job &J = jobs[blockIdx.y];
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < J.K; k += gridDim.x * blockDim.x) {
-        const int64_t *r = J.stats + 6 * (int64_t)k;
-        const int64_t n = r[0];
-        for (int ch = 0; ch < 3; ch++) J.fmean[3 * k + ch] = (int32_t)(((r[1 + ch] << (F + 1)) + n) / (2 * n));
-        int64_t *a = J.facc + FACC * (int64_t)k;
-        for (int q = 0; q < FACC; q++) a[q] = 0;
-        a[7] = INT64_MAX;   // min contrast
-    }
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < J.K; k += gridDim.x * blockDim.x)
+        feat_init_sp(J.stats, J.fmean, J.facc, k, F);
 }
 
-// Pass B: one thread per block of the last stage before the gate.  Pixel
-// second moments of the block, and for its right and lower neighbour blocks
-// of another label: the shared edge length and the squared distance of the
-// two fixed-point means, accumulated for both superpixels.
 __global__ void k_feat_blocks(const Job *__restrict__ jobs, int B, int lab_buf)
 {
     const Job &J = jobs[blockIdx.y];
-    const int W = J.W, H = J.H;
-    const int nbx = (W + B - 1) / B, nby = (H + B - 1) / B;
-    const int32_t *L = J.lab[lab_buf];
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nbx * nby; i += gridDim.x * blockDim.x) {
-        const int bx = i % nbx, by = i / nbx;
-        const int x0 = bx * B, y0 = by * B, x1 = min(x0 + B, W), y1 = min(y0 + B, H);
-        const int32_t k = L[i];
-        int64_t q0 = 0, q1 = 0, q2 = 0;
-        for (int y = y0; y < y1; y++) {
-            const uint8_t *row = J.rgb + (int64_t)y * J.rgb_stride + 3 * (int64_t)x0;
-            for (int x = 0; x < x1 - x0; x++) {
-                int r = row[3 * x], g = row[3 * x + 1], b = row[3 * x + 2];
-                q0 += r * r;
-                q1 += g * g;
-                q2 += b * b;
-            }
-        }
-        int64_t *ak = J.facc + FACC * (int64_t)k;
-        atomicAdd(reinterpret_cast<unsigned long long *>(ak + 0), (unsigned long long)q0);
-        atomicAdd(reinterpret_cast<unsigned long long *>(ak + 1), (unsigned long long)q1);
-        atomicAdd(reinterpret_cast<unsigned long long *>(ak + 2), (unsigned long long)q2);
-        for (int d = 0; d < 2; d++) {
-            const int nx = bx + (d == 0), ny = by + (d == 1);
-            if (nx >= nbx || ny >= nby) continue;
-            const int32_t j = L[ny * nbx + nx];
-            if (j == k) continue;
-            const int64_t e = d == 0 ? (y1 - y0) : (x1 - x0);
-            int64_t d2 = 0;
-            for (int ch = 0; ch < 3; ch++) {
-                int64_t df = (int64_t)J.fmean[3 * k + ch] - J.fmean[3 * j + ch];
-                d2 += df * df;
-            }
-            const int32_t both[2] = {k, j};
-            for (int u = 0; u < 2; u++) {
-                int64_t *a = J.facc + FACC * (int64_t)both[u];
-                atomicAdd(reinterpret_cast<unsigned long long *>(a + 3), (unsigned long long)e);
-                atomicAdd(reinterpret_cast<unsigned long long *>(a + 4), (unsigned long long)(e * d2));
-                atomicMax(reinterpret_cast<unsigned long long *>(a + 6), (unsigned long long)d2);
-                atomicMin(reinterpret_cast<unsigned long long *>(a + 7), (unsigned long long)d2);
-            }
-        }
+    const int nbx = (J.W + B - 1) / B, nby = (J.H + B - 1) / B;
+    const int64_t nb = (int64_t)nbx * nby;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // wave-uniform loop: every lane takes part in the run sums
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); i0 < nb; i0 += stride) {
+        const int64_t i = i0 + (threadIdx.x & 63);
+        feat_block(J, J.lab[lab_buf], B, nbx, nby, i, i < nb, nullptr, J.fmean, J.facc);
     }
 }
 
-// Pass C: the sixteen features (double arithmetic without contraction, so
-// that every value is the correctly rounded result of the same expression
-// on any IEEE machine):
-//   0-2 mean colour / 255, 3-5 colour std / 64, 6 size / A, 7 boundary
-//   length / (4 sqrt A), 8 compactness bl^2 / (16 n), 9 centroid drift from
-//   the initial cell centre / sqrt A, 10-12 max / edge-weighted rms / min
-//   neighbour contrast / (255 2^F), 13 moved pixels / n, 14 max colour std
-//   / 64, 15 one.
 __global__ void k_feat_final(const Job *__restrict__ jobs, const int64_t *__restrict__ xoff, int F,
                              float *__restrict__ X)
 {
-#pragma clang fp contract(off)
     const Job &J = jobs[blockIdx.y];
     float *Xj = X + 16 * xoff[blockIdx.y];
-    const double A = (double)(((int64_t)J.W * J.H) / J.K);
-    const double sA = sqrt(A);
-    const double cs = 255.0 * (double)(1 << F);
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < J.K; k += gridDim.x * blockDim.x) {
-        const int64_t *r = J.stats + 6 * (int64_t)k;
-        const int64_t *a = J.facc + FACC * (int64_t)k;
-        const double n = (double)r[0];
-        float *f = Xj + 16 * (int64_t)k;
-        double sd[3];
-        for (int ch = 0; ch < 3; ch++) {
-            double mu = (double)r[1 + ch] / n;
-            double v = (double)a[ch] / n - mu * mu;
-            sd[ch] = sqrt(v > 0.0 ? v : 0.0);
-            f[ch] = (float)(mu / 255.0);
-            f[3 + ch] = (float)(sd[ch] / 64.0);
-        }
-        const double bl = (double)a[3];
-        f[6] = (float)(n / A);
-        f[7] = (float)(bl / (4.0 * sA));
-        f[8] = (float)(bl * bl / (16.0 * n));
-        const int col = k % J.gx, row = k / J.gx;
-        const double cx0 = (double)(2 * col + 1) * (double)J.W / (2.0 * J.gx) - 0.5;
-        const double cy0 = (double)(2 * row + 1) * (double)J.H / (2.0 * J.gy) - 0.5;
-        const double dx = (double)r[4] / n - cx0, dy = (double)r[5] / n - cy0;
-        f[9] = (float)(sqrt(dx * dx + dy * dy) / sA);
-        f[10] = (float)(sqrt((double)a[6]) / cs);
-        f[11] = (float)(a[3] ? sqrt((double)a[4] / bl) / cs : 0.0);
-        f[12] = (float)(a[7] != INT64_MAX ? sqrt((double)a[7]) / cs : 0.0);
-        f[13] = (float)((J.moved ? (double)J.moved[k] : 0.0) / n);
-        double m3 = sd[0] > sd[1] ? sd[0] : sd[1];
-        m3 = m3 > sd[2] ? m3 : sd[2];
-        f[14] = (float)(m3 / 64.0);
-        f[15] = 1.0f;
-    }
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < J.K; k += gridDim.x * blockDim.x)
+        feat_final_sp(J, J.stats, J.facc, J.moved, k, F, Xj + 16 * (int64_t)k);
 }
 
 // ------------------------------------------------------------ MLP forward
@@ -236,18 +109,8 @@ __device__ __forceinline__ void mlp_tile(const WFrag &w, v4s bx, int lane, Fwd &
     o.z = c[0];   // row 0: meaningful in lanes 0-15
 }
 
-__device__ __forceinline__ v4s load_x(const float *__restrict__ X, int64_t n, int64_t N, int grp)
-{
-    if (n >= N) {
-        v4s z = {0, 0, 0, 0};
-        return z;
-    }
-    const float *p = X + 16 * n + 4 * grp;
-    return pack4(p[0], p[1], p[2], p[3]);
-}
-
 // logits of N samples; gate[n] = logit >= thresh (gate may be null).  One
-// wave per 16-sample tile, weights kept in registers across tiles.
+// wave per 16-sample tile.
 __global__ __launch_bounds__(256) void k_mlp_fwd(const float *__restrict__ X, int64_t N,
                                                  const uint16_t *__restrict__ P, float thresh,
                                                  float *__restrict__ logits, uint8_t *__restrict__ gate)
@@ -255,16 +118,13 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float *__restrict__ X, in
     const int lane = threadIdx.x & 63;
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    WFrag w;
-    load_wfrag(w, P, lane);
     const int64_t ntiles = (N + 15) / 16;
     for (int64_t t = wave; t < ntiles; t += nwaves) {
         const int64_t n = 16 * t + (lane & 15);
-        Fwd o;
-        mlp_tile(w, load_x(X, n, N, lane >> 4), lane, o);
+        const float z = mlp_logit(P, load_x(X, n, N, lane >> 4), lane);
         if (lane < 16 && n < N) {
-            if (logits) logits[n] = o.z;
-            if (gate) gate[n] = o.z >= thresh ? 1 : 0;
+            if (logits) logits[n] = z;
+            if (gate) gate[n] = z >= thresh ? 1 : 0;
         }
     }
 }
@@ -458,7 +318,78 @@ __global__ void k_to_bf16(const float *__restrict__ src, uint16_t *__restrict__ 
         dst[i] = f2bf(src[i]);
 }
 
+// ------------------------------------------------- boundary-recall misses
+
+// Boundary pixels of `ref` (a 4-neighbour with another label) with no
+// boundary pixel of `test` within Chebyshev distance r: the misses of the
+// boundary recall of Sec. 4.2.  Each miss adds 1 to miss[ref label] and 1 to
+// miss[test label]; totals gets (ref boundary pixels, misses).  One
+// workgroup per 64 x 16 pixel tile; the test boundary of the tile plus an
+// r-pixel apron is staged in LDS as bytes.
+constexpr int BM_TX = 64, BM_TY = 16, BM_RMAX = 4;
+
+__device__ __forceinline__ bool is_bnd(const int32_t *__restrict__ M, int x, int y, int W, int H, int64_t stride)
+{
+    const int32_t *row = M + (int64_t)y * stride;
+    const int32_t l = row[x];
+    return (x > 0 && row[x - 1] != l) || (x + 1 < W && row[x + 1] != l) ||
+           (y > 0 && row[x - stride] != l) || (y + 1 < H && row[x + stride] != l);
+}
+
+__global__ __launch_bounds__(256) void k_boundary_miss(const int32_t *__restrict__ ref,
+                                                       const int32_t *__restrict__ test, int W, int H,
+                                                       int64_t stride, int r, int32_t K,
+                                                       int32_t *__restrict__ miss,
+                                                       unsigned long long *__restrict__ totals)
+{
+    __shared__ uint8_t tb[(BM_TY + 2 * BM_RMAX) * (BM_TX + 2 * BM_RMAX)];
+    __shared__ unsigned s_tot[2];
+    const int tid = threadIdx.x;
+    const int x0 = blockIdx.x * BM_TX, y0 = blockIdx.y * BM_TY;
+    const int EW = BM_TX + 2 * r, EH = BM_TY + 2 * r;
+    if (tid < 2) s_tot[tid] = 0;
+    for (int i = tid; i < EW * EH; i += 256) {
+        const int x = x0 - r + i % EW, y = y0 - r + i / EW;
+        tb[i] = (x >= 0 && y >= 0 && x < W && y < H) ? is_bnd(test, x, y, W, H, stride) : 0;
+    }
+    __syncthreads();
+    unsigned nb = 0, nm = 0;
+    for (int i = tid; i < BM_TX * BM_TY; i += 256) {
+        const int tx = i % BM_TX, ty = i / BM_TX;
+        const int x = x0 + tx, y = y0 + ty;
+        if (x >= W || y >= H || !is_bnd(ref, x, y, W, H, stride)) continue;
+        nb++;
+        bool near = false;
+        for (int dy = 0; dy <= 2 * r && !near; dy++)
+            for (int dx = 0; dx <= 2 * r; dx++) near |= tb[(ty + dy) * EW + tx + dx] != 0;
+        if (near) continue;
+        nm++;
+        if (miss) {
+            const int64_t o = (int64_t)y * stride + x;
+            const int32_t la = ref[o], lb = test[o];
+            if ((uint32_t)la < (uint32_t)K) atomicAdd(&miss[la], 1);
+            if ((uint32_t)lb < (uint32_t)K) atomicAdd(&miss[lb], 1);
+        }
+    }
+    if (nb) atomicAdd(&s_tot[0], nb);
+    if (nm) atomicAdd(&s_tot[1], nm);
+    __syncthreads();
+    if (tid == 0 && totals) {
+        atomicAdd(&totals[0], (unsigned long long)s_tot[0]);
+        atomicAdd(&totals[1], (unsigned long long)s_tot[1]);
+    }
+}
+
 // ------------------------------------------------------------- launchers
+
+hipError_t launch_boundary_miss(const int32_t *ref, const int32_t *test, int W, int H, int64_t stride, int r,
+                                int32_t K, int32_t *miss, int64_t *totals, hipStream_t stream)
+{
+    dim3 grid((unsigned)((W + BM_TX - 1) / BM_TX), (unsigned)((H + BM_TY - 1) / BM_TY));
+    hipLaunchKernelGGL(k_boundary_miss, grid, dim3(256), 0, stream, ref, test, W, H, stride, r, K, miss,
+                       reinterpret_cast<unsigned long long *>(totals));
+    return hipGetLastError();
+}
 
 hipError_t launch_features(const Job *jobs_dev, int n_jobs, int B, int lab_buf, int F, int32_t Kmax,
                            int64_t max_nb, const int64_t *xoff_dev, float *X, hipStream_t stream)

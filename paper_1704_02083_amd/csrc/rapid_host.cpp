@@ -151,6 +151,8 @@ rapid_status make_sched(const rapid_params *p, Sched *sc, int32_t level_first[RA
         sc->gate_stage = first;
     }
     if (p->frac_bits < 0 || p->frac_bits > 4 || p->max_sweeps < 1) return RAPID_EINVAL;
+    if (p->gate_rule < RAPID_GATE_EITHER || p->gate_rule > RAPID_GATE_DIFFER) return RAPID_EINVAL;
+    sc->gate_rule = p->gate_rule;
     if (p->w_col < 0 || p->w_pos < 0 || p->w_bnd < 0 || p->min_size < 0 || p->max_size < 1)
         return RAPID_EINVAL;
     sc->F = p->frac_bits;
@@ -246,11 +248,12 @@ struct Layout {
     size_t bytes = 0;
     size_t off_lab[2], off_sums[MAXST], off_lists, off_props, off_changed, off_stamp;
     size_t off_stats, off_means, off_flow, off_mdbl, off_rep;
-    size_t off_fmean, off_facc, off_moved;
+    size_t off_fmean, off_facc, off_moved, off_moms;
     int64_t capc = 0;
 };
 
-Layout plan(int32_t W, int32_t H, int32_t K, const Sched &sc)
+// moms_stage: stage whose per-block second moments the gate reads (-1: none)
+Layout plan(int32_t W, int32_t H, int32_t K, const Sched &sc, int moms_stage = -1)
 {
     Layout L;
     size_t o = 0;
@@ -280,6 +283,11 @@ Layout plan(int32_t W, int32_t H, int32_t K, const Sched &sc)
     L.off_fmean = take(4 * 3 * (size_t)K);
     L.off_facc = take(8 * FACC * (size_t)K);
     L.off_moved = take(8 * (size_t)K);
+    L.off_moms = (size_t)-1;
+    if (moms_stage >= 0) {
+        const int B = sc.B[moms_stage];
+        L.off_moms = take(12 * (size_t)((W + B - 1) / B) * ((H + B - 1) / B));
+    }
     L.bytes = o;
     return L;
 }
@@ -314,6 +322,8 @@ void fill_job(Job &J, char *base, const Layout &L, const rapid_image *img, int32
     J.gate = gate;
     J.fmean = reinterpret_cast<int32_t *>(base + L.off_fmean);
     J.facc = reinterpret_cast<int64_t *>(base + L.off_facc);
+    J.moms = L.off_moms == (size_t)-1 ? nullptr : reinterpret_cast<uint32_t *>(base + L.off_moms);
+    J.moms_stage = -1;
 }
 
 rapid_status dev_err(hipError_t e) { return e == hipSuccess ? RAPID_OK : RAPID_EDEVICE; }
@@ -327,17 +337,21 @@ rapid_status dev_err(hipError_t e) { return e == hipSuccess ? RAPID_OK : RAPID_E
 // Carve the LDS of the refinement kernel: statistics first (when they fit
 // with room to spare), then the class lists, proposals, the frontier visit
 // bitmap and the changed list, each within a share of what remains.
-LdsPlan plan_lds(size_t limit, int32_t Kmax, int64_t nbF)
+LdsPlan plan_lds(size_t limit, int32_t Kmax, int64_t nbF, bool gated)
 {
     LdsPlan p;
     std::memset(&p, 0, sizeof p);
     auto a16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
     size_t off = 0;
+    const size_t gwords = gated ? ((size_t)Kmax + 31) / 32 : 0;   // at most MAX_GATE_WORDS (run_jobs)
     size_t stats = (size_t)Kmax * LDS_PER_SP;
-    if (stats + 48 * 1024 <= limit) {
+    if (stats + 48 * 1024 + 4 * gwords <= limit) {
         p.stats_lds = 1;
         off = a16(stats);
     }
+    p.gate_words = (int32_t)gwords;
+    p.off_gate = (uint32_t)off;
+    off = a16(off + 4 * gwords);
     size_t rem = limit > off ? limit - off : 0;
     p.capl = (int)std::min<size_t>(1024, rem * 35 / 100 / (9 * 4));
     p.capp = (int)std::min<size_t>(1024, rem * 25 / 100 / sizeof(Prop));
@@ -386,11 +400,18 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
             if (sc.B[s] >= 2)
                 HIPCHK(launch_block_sums(ctx->jobs_dev, (int)n, s, sc.B[s], max_nb[s], ctx->stream));
     }
-    LdsPlan lp = plan_lds(ctx->lds_limit, Kmax, nbF_max);
+    // the gate bits live in LDS during the gated stages
+    bool gated = (flags & FLAG_GATE) != 0;
+    if (s_end > sc.gate_stage)
+        for (const Job &J : jobs) gated |= J.gate != nullptr;
+    if (gated && ((int64_t)Kmax + 31) / 32 > MAX_GATE_WORDS) return RAPID_EINVAL;
+    LdsPlan lp = plan_lds(ctx->lds_limit, Kmax, nbF_max, gated);
     if (ctx->verbose)
         std::fprintf(stderr,
-                     "rapid: lds limit %zu, stats_lds %d, capl %d capp %d capx %d bm_words %d total %u\n",
-                     ctx->lds_limit, lp.stats_lds, lp.capl, lp.capp, lp.capx, lp.bm_words, lp.total);
+                     "rapid: lds limit %zu, stats_lds %d, capl %d capp %d capx %d bm_words %d gate_words %d "
+                     "total %u\n",
+                     ctx->lds_limit, lp.stats_lds, lp.capl, lp.capp, lp.capx, lp.bm_words, lp.gate_words,
+                     lp.total);
     if (ctx->timing) HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
     HIPCHK(launch_refine(ctx->jobs_dev, (int)n, sc, lp, s_begin, s_end, flags, ctx->lut_dev,
                          ctx->threads, ctx->stream));
@@ -583,7 +604,9 @@ rapid_status prepare_batch(rapid_ctx *ctx, const rapid_image *imgs, int32_t n, c
         } else if ((r = image_grid(&imgs[i], params, sc, &gxs[i], &gys[i]))) {
             return r;
         }
-        lay[i] = plan(imgs[i].W, imgs[i].H, gxs[i] * gys[i], sc);
+        // the gate's features read second moments of the stage before it
+        const int ms = (gated && sc.B[sc.gate_stage - 1] >= 2) ? sc.gate_stage - 1 : -1;
+        lay[i] = plan(imgs[i].W, imgs[i].H, gxs[i] * gys[i], sc, ms);
         total += lay[i].bytes;
         b.Kmax = std::max(b.Kmax, gxs[i] * gys[i]);
         b.xoff[i] = b.Ktot;
@@ -638,8 +661,14 @@ rapid_status prepare_batch(rapid_ctx *ctx, const rapid_image *imgs, int32_t n, c
         b.gates = reinterpret_cast<uint8_t *>(ctx->pool + off_g);
         b.xoff_dev = reinterpret_cast<int64_t *>(ctx->pool + off_xo);
         HIPCHK(hipMemcpyAsync(b.xoff_dev, b.xoff.data(), 8 * (size_t)n, hipMemcpyHostToDevice, ctx->stream));
+        // the gate is evaluated inside the refinement launch (FLAG_GATE),
+        // which also clears the moved counters
         for (int i = 0; i < n; i++) {
-            HIPCHK(hipMemsetAsync(b.jobs[i].moved, 0, 8 * (size_t)b.jobs[i].K, ctx->stream));
+            Job &J = b.jobs[i];
+            J.xrow = b.X + 16 * b.xoff[i];
+            J.gate_out = b.gates + b.xoff[i];
+            J.gate = J.gate_out;
+            if (J.moms) J.moms_stage = sc.gate_stage - 1;
         }
     }
     set_exactness(sc, Wmax, Hmax);
@@ -704,23 +733,18 @@ static rapid_status gated_impl(rapid_ctx *ctx, const rapid_image *imgs, int32_t 
     Batch b;
     rapid_status r = prepare_batch(ctx, imgs, n, params, nullptr, true, b, tiles);
     if (r) return r;
-    const int gs = b.sc.gate_stage;
-    // levels before the gate
-    if ((r = run_jobs(ctx, b.jobs, b.sc, 0, gs, FLAG_INIT, b.Kmax, b.nbF_max, b.max_nb))) return r;
-    // features of every superpixel and the network's decision (Eq. (6))
-    HIPCHK(launch_features(ctx->jobs_dev, n, b.sc.B[gs - 1], (gs - 1) & 1, b.sc.F, b.Kmax, b.max_nb[gs - 1],
-                           b.xoff_dev, b.X, ctx->stream));
-    HIPCHK(launch_mlp_fwd(b.X, b.Ktot, model->w_bf16_dev, model->thresh, nullptr, b.gates, ctx->stream));
+    // one launch: the levels before the gate, then in every workgroup the
+    // features of its superpixels and the network's decision (Eq. (6)),
+    // then the finer levels under the gate (Eq. (7))
+    b.sc.mlp_w = model->w_bf16_dev;
+    b.sc.mlp_thresh = model->thresh;
+    if ((r = run_jobs(ctx, b.jobs, b.sc, 0, b.sc.n_stages, FLAG_INIT | FLAG_OUT | FLAG_GATE, b.Kmax, b.nbF_max,
+                      b.max_nb)))
+        return r;
     if (features_dev)
         HIPCHK(hipMemcpyAsync(features_dev, b.X, 4 * 16 * (size_t)b.Ktot, hipMemcpyDeviceToDevice, ctx->stream));
     if (gate_dev)
         HIPCHK(hipMemcpyAsync(gate_dev, b.gates, (size_t)b.Ktot, hipMemcpyDeviceToDevice, ctx->stream));
-    // the finer levels under the gate (Eq. (7))
-    for (int i = 0; i < n; i++) {
-        b.jobs[i].gate = b.gates + b.xoff[i];
-        b.jobs[i].moved = nullptr;
-    }
-    if ((r = run_jobs(ctx, b.jobs, b.sc, gs, b.sc.n_stages, FLAG_OUT, b.Kmax, b.nbF_max, b.max_nb))) return r;
     if (reports) {
         // one report per image over all stages
         HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -924,6 +948,19 @@ rapid_status rapid_state_features(rapid_ctx *ctx, rapid_state *st, float *X_dev)
     const int64_t nb = (int64_t)((st->W + B - 1) / B) * ((st->H + B - 1) / B);
     HIPCHK(launch_features(st->job_dev, 1, B, s & 1, st->sc.F, st->job.K, nb, st->zero_dev, X_dev, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RAPID_OK;
+}
+
+rapid_status rapid_boundary_miss(rapid_ctx *ctx, const int32_t *ref_dev, const int32_t *test_dev, int32_t W,
+                                 int32_t H, int64_t stride, int32_t radius, int32_t K, int32_t *miss_dev,
+                                 int64_t *totals_dev)
+{
+    if (!ctx || !ref_dev || !test_dev || W < 1 || H < 1 || W > (1 << 22) || H > (1 << 20) || stride < W ||
+        radius < 0 || radius > BOUNDARY_MISS_RMAX || (!miss_dev && !totals_dev) || (miss_dev && K < 1))
+        return RAPID_EINVAL;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return RAPID_EDEVICE;
+    HIPCHK(launch_boundary_miss(ref_dev, test_dev, W, H, stride, radius, K, miss_dev, totals_dev, ctx->stream));
     return RAPID_OK;
 }
 

@@ -9,8 +9,13 @@
 namespace rapid {
 
 constexpr int MAXST = RAPID_MAX_LEVELS * RAPID_MAX_STAGES;
+// gated runs keep one gate bit per superpixel in LDS: at most 2^18 per image
+constexpr int MAX_GATE_WORDS = 8192;
 
-enum { FLAG_INIT = 1, FLAG_OUT = 2 };
+// FLAG_INIT: grid labels and statistics first; FLAG_OUT: write the pixel
+// labels; FLAG_GATE: evaluate the gate in place at the first gated stage
+// (features, network, gate bits) and track moved pixels before it.
+enum { FLAG_INIT = 1, FLAG_OUT = 2, FLAG_GATE = 4 };
 
 // The schedule, flattened: effective block size of every stage.
 struct Sched {
@@ -20,10 +25,13 @@ struct Sched {
     int32_t f64[MAXST];      // 1: every intermediate of E' at this stage is an
                              // integer below 2^53, so fp64 evaluates it exactly
     int32_t gate_stage;      // first stage refined under the gate
+    int32_t gate_rule;       // RAPID_GATE_*
     int32_t F, max_sweeps;
     int64_t min_size, max_size, w_col, w_pos, w_bnd;
     double d_wc, d_wp, d_wb, d_fs;   // w_col, w_pos, w_bnd 2^(2F), 2^(F+1) as doubles
     double d_wcfs, d_wpfs;           // w_col 2^(F+1), w_pos 2^(F+1)
+    const uint16_t *mlp_w;           // FLAG_GATE: bf16 network parameters
+    float mlp_thresh;                // FLAG_GATE: gate bit = logit >= mlp_thresh
 };
 
 // A proposal: block, source and destination labels, packed colour sum of
@@ -40,7 +48,8 @@ struct Prop {
 struct LdsPlan {
     int32_t stats_lds;
     int32_t capl, capp, capx, bm_words;
-    uint32_t off_lists, off_props, off_chg, off_bm;
+    int32_t gate_words;      // LDS bitmap of the gate bits (0: no gate in this launch)
+    uint32_t off_lists, off_props, off_chg, off_bm, off_gate;
     uint32_t total;
 };
 
@@ -71,6 +80,14 @@ struct Job {
     // gate feature scratch
     int32_t *fmean;          // K x 3 fixed-point means
     int64_t *facc;           // K x FACC accumulators
+    // FLAG_GATE outputs: K feature rows of 16 floats and K gate bytes (the
+    // gated stages then read gate == gate_out)
+    float *xrow;
+    uint8_t *gate_out;
+    // per-block pixel second moments (3 x uint32 per block) of stage
+    // moms_stage, written by the block-sum pass for the gate's features
+    uint32_t *moms;
+    int32_t moms_stage, pad4;
     // slide tiles: only the core [core_x0, +core_w) x [core_y0, +core_h) of
     // the tile is written, label k as the slide cell id
     // (gid_y0 + k / gx) * gid_w + gid_x0 + k % gx
@@ -105,6 +122,9 @@ hipError_t launch_mlp_grad(const float *X, const uint8_t *T, const int32_t *idx,
 hipError_t launch_adam(float *theta, float *m, float *v, const float *g, uint16_t *wbf, float lr, float b1,
                        float b2, float eps, int step, hipStream_t stream);
 hipError_t launch_to_bf16(const float *src, uint16_t *dst, int64_t n, hipStream_t stream);
+constexpr int BOUNDARY_MISS_RMAX = 4;
+hipError_t launch_boundary_miss(const int32_t *ref, const int32_t *test, int W, int H, int64_t stride, int r,
+                                int32_t K, int32_t *miss, int64_t *totals, hipStream_t stream);
 
 // bytes of LDS per superpixel when the statistics live in LDS: sums,
 // fp64 energy record, means record, flow counters

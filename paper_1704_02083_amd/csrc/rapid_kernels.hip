@@ -15,7 +15,7 @@
 //       P2 class-wide size filter, commit, integer stat moves
 //       P3 refresh means of the moved superpixels, clear the flow counters
 //     rebuild the boundary set around changed blocks
-#include "rapid_internal.h"
+#include "rapid_gate_dev.h"
 
 namespace rapid {
 
@@ -160,20 +160,43 @@ __device__ __forceinline__ int32_t lab_at(const int32_t *L, int bx, int by, int 
     return (bx >= 0 && by >= 0 && bx < nbx && by < nby) ? L[by * nbx + bx] : -1;
 }
 
-__device__ __forceinline__ bool pair_on(const uint8_t *gate, int a, int k)
+// Gate modes of the refinement kernel (a template parameter, so that the
+// plain kernel carries no gate code): no gate, gate bits from the caller,
+// gate evaluated in place at the gate point (FLAG_GATE).
+enum { GM_NONE = 0, GM_BITS = 1, GM_FUSED = 2 };
+
+// The gate of a stage: the gate bits of all superpixels as an LDS bitmap
+// (nullptr: no gate, every pair active) and the pair rule as a truth table
+// indexed by 2 g_a + g_k.
+struct GateView {
+    const uint32_t *bits;
+    uint32_t tt;
+};
+
+__device__ __forceinline__ uint32_t rule_table(int rule)
 {
-    return gate == nullptr || gate[a] || gate[k];
+    // (g_a, g_k) = (0,0) (0,1) (1,0) (1,1) -> bits 0..3
+    return rule == RAPID_GATE_BOTH ? 0x8u : rule == RAPID_GATE_DIFFER ? 0x6u : 0xEu;
+}
+
+// Eq. (7): may superpixels a and k exchange blocks under the gate?
+__device__ __forceinline__ bool pair_on(const GateView &gv, int a, int k)
+{
+    if (gv.bits == nullptr) return true;
+    const uint32_t ga = (gv.bits[a >> 5] >> (a & 31)) & 1u;
+    const uint32_t gk = (gv.bits[k >> 5] >> (k & 31)) & 1u;
+    return (gv.tt >> (2 * ga + gk)) & 1u;
 }
 
 __device__ __forceinline__ bool eligible(const int32_t *L, int bx, int by, int nbx, int nby,
-                                         const uint8_t *gate)
+                                         const GateView &gv)
 {
     int32_t a = L[by * nbx + bx];
     int32_t k;
-    if ((k = lab_at(L, bx - 1, by, nbx, nby)) >= 0 && k != a && pair_on(gate, a, k)) return true;
-    if ((k = lab_at(L, bx + 1, by, nbx, nby)) >= 0 && k != a && pair_on(gate, a, k)) return true;
-    if ((k = lab_at(L, bx, by - 1, nbx, nby)) >= 0 && k != a && pair_on(gate, a, k)) return true;
-    if ((k = lab_at(L, bx, by + 1, nbx, nby)) >= 0 && k != a && pair_on(gate, a, k)) return true;
+    if ((k = lab_at(L, bx - 1, by, nbx, nby)) >= 0 && k != a && pair_on(gv, a, k)) return true;
+    if ((k = lab_at(L, bx + 1, by, nbx, nby)) >= 0 && k != a && pair_on(gv, a, k)) return true;
+    if ((k = lab_at(L, bx, by - 1, nbx, nby)) >= 0 && k != a && pair_on(gv, a, k)) return true;
+    if ((k = lab_at(L, bx, by + 1, nbx, nby)) >= 0 && k != a && pair_on(gv, a, k)) return true;
     return false;
 }
 
@@ -183,10 +206,12 @@ __device__ __forceinline__ void wg_sync()
 }
 
 // --------------------------------------------------------------- k_sums
-// Packed per-block RGB sums (21 bits per channel) for a stage of block size B.
-__global__ void k_block_sums(const Job *__restrict__ jobs, int s, int B)
+// Packed per-block RGB sums (21 bits per channel) for a stage of block size
+// B; for the stage the gate's features read (J.moms_stage) also the pixel
+// second moments per channel (at most 64^2 * 255^2 < 2^32).
+template <bool MOMS>
+__device__ __forceinline__ void block_sums_of(const Job &J, int s, int B)
 {
-    const Job &J = jobs[blockIdx.y];
     int nbx = (J.W + B - 1) / B, nby = (J.H + B - 1) / B;
     int64_t nb = (int64_t)nbx * nby;
     uint64_t *out = J.sums[s];
@@ -195,17 +220,35 @@ __global__ void k_block_sums(const Job *__restrict__ jobs, int s, int B)
         int bx = (int)(i % nbx), by = (int)(i / nbx);
         int x0 = bx * B, y0 = by * B;
         int x1 = min(x0 + B, J.W), y1 = min(y0 + B, J.H);
-        uint32_t r = 0, g = 0, b = 0;
+        uint32_t r = 0, g = 0, b = 0, qr = 0, qg = 0, qb = 0;
         for (int y = y0; y < y1; y++) {
             const uint8_t *row = J.rgb + (int64_t)y * J.rgb_stride + 3 * (int64_t)x0;
             for (int x = 0; x < x1 - x0; x++) {
-                r += row[3 * x];
-                g += row[3 * x + 1];
-                b += row[3 * x + 2];
+                const uint32_t pr = row[3 * x], pg = row[3 * x + 1], pb = row[3 * x + 2];
+                r += pr;
+                g += pg;
+                b += pb;
+                if (MOMS) {
+                    qr += pr * pr;
+                    qg += pg * pg;
+                    qb += pb * pb;
+                }
             }
         }
         out[i] = (uint64_t)r | ((uint64_t)g << 21) | ((uint64_t)b << 42);
+        if (MOMS) {
+            J.moms[3 * i] = qr;
+            J.moms[3 * i + 1] = qg;
+            J.moms[3 * i + 2] = qb;
+        }
     }
+}
+
+__global__ void k_block_sums(const Job *__restrict__ jobs, int s, int B)
+{
+    const Job &J = jobs[blockIdx.y];
+    if (J.moms && s == J.moms_stage) block_sums_of<true>(J, s, B);
+    else block_sums_of<false>(J, s, B);
 }
 
 // ------------------------------------------------------------- k_expand
@@ -254,7 +297,38 @@ __device__ __forceinline__ void class_push(int32_t *cnt, int32_t *lds, int capl,
     list_put(lds + cls * capl, capl, glob, cls * capg, slot, v);
 }
 
-template <bool LDS>
+// The gate point of a fused launch (Algorithm RAPID, before the gated
+// level), run by the whole workgroup: features of every superpixel on the
+// labels of the previous stage (block size Bq), the network's logit and the
+// gate bits (Eq. (6)).  Only the fused-gate instantiation of the kernel
+// contains it, so the plain kernel's registers are not affected.
+__device__ __attribute__((noinline)) void gate_point(const Job &J, const int64_t *st, int stage_q, int Bq, int F,
+                                                     const uint16_t *mlp_w, float thresh, int tid, int nt)
+{
+    const int K = J.K;
+    const int nbxq = (J.W + Bq - 1) / Bq, nbyq = (J.H + Bq - 1) / Bq;
+    const int64_t nbq = (int64_t)nbxq * nbyq;
+    const int32_t *Lq = J.lab[stage_q & 1];
+    for (int k = tid; k < K; k += nt) feat_init_sp(st, J.fmean, J.facc, k, F);
+    wg_sync();
+    for (int64_t i0 = tid & ~63; i0 < nbq; i0 += nt) {
+        const int64_t i = i0 + (tid & 63);
+        feat_block(J, Lq, Bq, nbxq, nbyq, i, i < nbq, (J.moms && J.moms_stage == stage_q) ? J.moms : nullptr,
+                   J.fmean, J.facc);
+    }
+    wg_sync();
+    for (int k = tid; k < K; k += nt) feat_final_sp(J, st, J.facc, J.moved, k, F, J.xrow + 16 * (int64_t)k);
+    wg_sync();
+    const int lane = tid & 63;
+    for (int t = tid >> 6; t < (K + 15) / 16; t += nt >> 6) {
+        const int n = 16 * t + (lane & 15);
+        const float z = mlp_logit(mlp_w, load_x(J.xrow, n, K, lane >> 4), lane);
+        if (lane < 16 && n < K) J.gate_out[n] = z >= thresh ? 1 : 0;
+    }
+    wg_sync();
+}
+
+template <bool LDS, int GM>
 __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, Sched sc, LdsPlan lp,
                                                   int s_begin, int s_end, int flags,
                                                   const uint32_t *__restrict__ lut_g)
@@ -286,6 +360,8 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
     Prop *l_props = reinterpret_cast<Prop *>(smem + lp.off_props);
     int32_t *l_chg = reinterpret_cast<int32_t *>(smem + lp.off_chg);
     uint32_t *l_bm = reinterpret_cast<uint32_t *>(smem + lp.off_bm);
+    uint32_t *l_gate = reinterpret_cast<uint32_t *>(smem + lp.off_gate);
+    bool gate_loaded = false;
     Prop *g_props = J.props;
     const int capl = lp.capl, capp = lp.capp, capx = lp.capx;
     const int64_t capg = J.capc;
@@ -296,6 +372,8 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
         s_nchg = 0;
     }
     for (int64_t i = tid; i < 2 * (int64_t)K; i += nt) fl[i] = 0;
+    if (GM == GM_FUSED)
+        for (int64_t i = tid; i < K; i += nt) J.moved[i] = 0;
     for (int i = tid; i < lp.bm_words; i += nt) l_bm[i] = 0;
 
     if (flags & FLAG_INIT) {
@@ -335,7 +413,27 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
         const int nbx = (W + B - 1) / B, nby = (H + B - 1) / B;
         const int64_t nb = (int64_t)nbx * nby;
         int32_t *L = J.lab[s & 1];
-        const uint8_t *gate = (J.gate && s >= sc.gate_stage) ? J.gate : nullptr;
+        if (GM == GM_FUSED && s == sc.gate_stage && s > 0)
+            gate_point(J, st, s - 1, sc.B[s - 1], sc.F, sc.mlp_w, sc.mlp_thresh, tid, nt);
+        // moved pixels feed the gate's features: past the gate point of a
+        // fused launch nothing needs them
+        int64_t *const mv = (GM == GM_FUSED && s >= sc.gate_stage) ? nullptr : J.moved;
+        GateView gv;
+        gv.bits = nullptr;
+        gv.tt = rule_table(sc.gate_rule);
+        if (GM != GM_NONE && J.gate && s >= sc.gate_stage) {
+            if (!gate_loaded) {
+                // first gated stage of the launch: the gate bits into LDS
+                // (the host guarantees 32 * gate_words >= K)
+                for (int w = tid; w < (K + 31) / 32; w += nt) {
+                    uint32_t v = 0;
+                    for (int b = 0; b < 32 && 32 * w + b < K; b++) v |= (J.gate[32 * w + b] != 0 ? 1u : 0u) << b;
+                    l_gate[w] = v;
+                }
+                gate_loaded = true;   // uniform: the workgroup syncs below before any use
+            }
+            gv.bits = l_gate;
+        }
         const bool use_bm = (int64_t)lp.bm_words * 32 >= nb;
         const bool use_f64 = sc.f64[s] != 0;
         if (tid < 9) s_cnt[tid] = 0;
@@ -362,13 +460,13 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                     a = Lp[p];
                     int32_t k;
                     k = lab_at(Lp, pxb - 1, pyb, nbxp, nbyp);
-                    sw = k >= 0 && k != a && pair_on(gate, a, k);
+                    sw = k >= 0 && k != a && pair_on(gv, a, k);
                     k = lab_at(Lp, pxb + 1, pyb, nbxp, nbyp);
-                    se = k >= 0 && k != a && pair_on(gate, a, k);
+                    se = k >= 0 && k != a && pair_on(gv, a, k);
                     k = lab_at(Lp, pxb, pyb - 1, nbxp, nbyp);
-                    sn = k >= 0 && k != a && pair_on(gate, a, k);
+                    sn = k >= 0 && k != a && pair_on(gv, a, k);
                     k = lab_at(Lp, pxb, pyb + 1, nbxp, nbyp);
-                    ss = k >= 0 && k != a && pair_on(gate, a, k);
+                    ss = k >= 0 && k != a && pair_on(gv, a, k);
                 }
 #pragma unroll 1
                 for (int ch = 0; ch < r * r; ch++) {
@@ -389,7 +487,7 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                 int cls = 0;
                 if (i < nb) {
                     int bx = (int)(i % nbx), by = (int)(i / nbx);
-                    e = eligible(L, bx, by, nbx, nby, gate);
+                    e = eligible(L, bx, by, nbx, nby, gv);
                     cls = 3 * (by % 3) + (bx % 3);
                 }
                 if (e) class_push(s_cnt, l_lists, capl, J.lists, capg, cls, (int32_t)i);
@@ -502,7 +600,7 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                                         }
                                     }
                                 }
-                                prop = best != a && pair_on(gate, a, best);
+                                prop = best != a && pair_on(gv, a, best);
                             }
                         }
                     }
@@ -555,8 +653,8 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                             add64(rr + 3, sg * (int64_t)(rec.I >> 42));
                             add64(rr + 4, sg * g.px);
                             add64(rr + 5, sg * g.py);
-                            if (J.moved)
-                                atomicAdd(reinterpret_cast<unsigned long long *>(J.moved + (side ? k : a)),
+                            if (mv)
+                                atomicAdd(reinterpret_cast<unsigned long long *>(mv + (side ? k : a)),
                                           (unsigned long long)g.m);
                             if (side == 0) {
                                 L[bi] = k;
@@ -618,7 +716,7 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                 } else {
                     first = atomicExch(&J.stamp[ni], stamp) != stamp;
                 }
-                if (first && eligible(L, bx, by, nbx, nby, gate))
+                if (first && eligible(L, bx, by, nbx, nby, gv))
                     class_push(s_cnt, l_lists, capl, J.lists, capg, 3 * (by % 3) + (bx % 3), ni);
             }
             wg_sync();
@@ -700,15 +798,15 @@ hipError_t launch_refine(const Job *jobs_dev, int n_jobs, const Sched &sc, const
                          int s_begin, int s_end, int flags, const uint32_t *lut_dev, int threads,
                          hipStream_t stream)
 {
-    const void *fn = lp.stats_lds ? (const void *)k_refine<true> : (const void *)k_refine<false>;
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp.total);
+    typedef void (*Kern)(const Job *, Sched, LdsPlan, int, int, int, const uint32_t *);
+    static const Kern table[2][3] = {{k_refine<false, GM_NONE>, k_refine<false, GM_BITS>, k_refine<false, GM_FUSED>},
+                                     {k_refine<true, GM_NONE>, k_refine<true, GM_BITS>, k_refine<true, GM_FUSED>}};
+    const int gm = (flags & FLAG_GATE) ? GM_FUSED : lp.gate_words > 0 ? GM_BITS : GM_NONE;
+    const Kern fn = table[lp.stats_lds ? 1 : 0][gm];
+    hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp.total);
     if (e != hipSuccess) return e;
-    if (lp.stats_lds)
-        hipLaunchKernelGGL(k_refine<true>, dim3((unsigned)n_jobs), dim3(threads), lp.total, stream,
-                           jobs_dev, sc, lp, s_begin, s_end, flags, lut_dev);
-    else
-        hipLaunchKernelGGL(k_refine<false>, dim3((unsigned)n_jobs), dim3(threads), lp.total, stream,
-                           jobs_dev, sc, lp, s_begin, s_end, flags, lut_dev);
+    hipLaunchKernelGGL(fn, dim3((unsigned)n_jobs), dim3(threads), lp.total, stream, jobs_dev, sc, lp, s_begin,
+                       s_end, flags, lut_dev);
     return hipGetLastError();
 }
 

@@ -1,22 +1,24 @@
 """Training data, training and calibration of the prediction gate.
 
 Every step runs on the GPU through the C-ABI (``rapid.py``): plain
-refinements of training tiles produce the features (at the start of the
-gate level) and the targets, ``rapid_gate_train`` fits the network, and
-``rapid_segment_gated`` applies it.
+refinements of training tiles produce the features at the gate point and the
+targets, ``rapid_gate_train`` fits the network, and ``rapid_segment_gated``
+applies it.
 
 Target (this project's reading of "which superpixels need refinement at
-finer levels"): superpixel k is positive when the plain run moves at least
-a fraction ``tau`` of its pixels into or out of it after the gate point.
+finer levels"): superpixel k is positive when, in the plain run, at least
+``min_miss`` boundary pixels charged to k (``rapid_boundary_miss``) end up
+more than ``radius`` pixels away from every boundary pixel at the gate
+point: freezing k there would cost boundary recall.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import metrics, rapid
+from . import rapid
 
 
-def tile_samples(ctx, rgb, p: dict, tau: float):
+def tile_samples(ctx, rgb, p: dict, radius: int = 2, min_miss: int = 1):
     """Plain run of one image through the level-by-level API.  Returns the
     gate features (K, 16), targets (K,) uint8 and the plain labels."""
     import torch
@@ -28,23 +30,20 @@ def tile_samples(ctx, rgb, p: dict, tau: float):
     for l in range(gl):
         st.refine_level(l, report=False)
     X = st.features()
-    _, stats = st.export()
-    moved_gate = moved.clone()
+    lab_gate, _ = st.export()
     for l in range(gl, len(p["levels"])):
         st.refine_level(l, report=False)
     lab, _ = st.export()
     st.close()
-    after = (moved - moved_gate).to(torch.float64)
-    n = stats[:, 0].to(torch.float64)
-    t = (after >= tau * n).to(torch.uint8)
-    return X, t, lab
+    miss, _, _ = ctx.boundary_miss(lab, lab_gate, radius=radius, K=K)
+    return X, (miss >= min_miss).to(torch.uint8), lab
 
 
-def training_set(ctx, rgbs, p: dict, tau: float):
+def training_set(ctx, rgbs, p: dict, radius: int = 2, min_miss: int = 1):
     import torch
     Xs, ts = [], []
     for r in rgbs:
-        X, t, _ = tile_samples(ctx, r, p, tau)
+        X, t, _ = tile_samples(ctx, r, p, radius, min_miss)
         Xs.append(X)
         ts.append(t)
     return torch.cat(Xs), torch.cat(ts)
@@ -67,37 +66,34 @@ def train(ctx, X, t, epochs: int = 20, batch: int = 4096, lr: float = 1e-3, seed
     return master, w
 
 
-def evaluate(ctx, rgbs, p: dict, w, thresh: float, plain_labels=None, timing: bool = True):
-    """Gated vs plain on the same images: agreement metrics and the share
-    of superpixels the gate marks."""
+def boundary_recall(ctx, ref, test, radius: int = 2) -> float:
+    """Boundary recall of test against ref, on the GPU (any map size)."""
+    _, nb, nm = ctx.boundary_miss(ref, test, radius=radius, counts=False)
+    return 1.0 - nm / nb if nb else 1.0
+
+
+def evaluate(ctx, rgbs, p: dict, w, thresh: float, plain_labels=None):
+    """Gated vs plain on the same images: mean boundary recall, its minimum,
+    the share of differing labels and the share of superpixels marked."""
     import torch
     if plain_labels is None:
         plain_labels, _ = ctx.segment_batch(rgbs, p, report=False)
     labs, _, _, g = ctx.segment_gated(rgbs, p, w, thresh, report=False)
-    torch.cuda.synchronize()
-    m = {"br": [], "ue": [], "disagreement": []}
-    for a, b in zip(plain_labels, labs):
-        r = metrics.agreement(a.cpu().numpy(), b.cpu().numpy())
-        for k in m:
-            m[k].append(r[k])
-    out = {k: float(np.mean(v)) for k, v in m.items()}
-    out["br_min"] = float(np.min(m["br"]))
-    out["marked"] = float(g.to(torch.float32).mean().item())
-    return out
+    brs = [boundary_recall(ctx, a, b) for a, b in zip(plain_labels, labs)]
+    dis = [float((a != b).float().mean().item()) for a, b in zip(plain_labels, labs)]
+    return {"br": float(np.mean(brs)), "br_min": float(np.min(brs)), "disagreement": float(np.mean(dis)),
+            "marked": float(g.to(torch.float32).mean().item())}
 
 
 def calibrate(ctx, rgbs, p: dict, w, target_br: float = 0.99, candidates=None):
-    """Largest logit threshold whose mean boundary recall against the plain
-    result is at least target_br on the given (held-out) images."""
-    import torch
+    """Largest logit threshold (fewest superpixels marked) whose mean
+    boundary recall against the plain result is at least target_br on the
+    given (held-out) images.  Returns (threshold, evaluation) or None."""
     plain, _ = ctx.segment_batch(rgbs, p, report=False)
-    torch.cuda.synchronize()
     if candidates is None:
-        candidates = [4.0, 3.0, 2.0, 1.5, 1.0, 0.5, 0.0, -0.5, -1.0, -2.0, -3.0, -4.0, -6.0, -8.0]
-    best = None
+        candidates = [4.0, 3.0, 2.0, 1.5, 1.0, 0.5, 0.0, -0.5, -1.0, -1.5, -2.0, -3.0, -4.0, -6.0]
     for th in candidates:
         r = evaluate(ctx, rgbs, p, w, th, plain_labels=plain)
         if r["br"] >= target_br:
-            best = (th, r)
-            break
-    return best
+            return th, r
+    return None

@@ -49,7 +49,7 @@ class Params(C.Structure):
         ("factor", C.c_int32 * MAX_LEVELS), ("n_stages", C.c_int32 * MAX_LEVELS),
         ("stages", (C.c_int32 * MAX_STAGES) * MAX_LEVELS),
         ("gate_level", C.c_int32), ("frac_bits", C.c_int32), ("max_sweeps", C.c_int32),
-        ("reserved", C.c_int32),
+        ("gate_rule", C.c_int32),
         ("min_size", C.c_int64), ("max_size", C.c_int64),
         ("w_col", C.c_int64), ("w_pos", C.c_int64), ("w_bnd", C.c_int64),
     ]
@@ -121,6 +121,8 @@ _lib.rapid_segment_gated.argtypes = [_P, C.POINTER(Image), C.c_int32, C.POINTER(
                                      C.POINTER(GateModel), _P, _P, C.POINTER(Report)]
 _lib.rapid_state_track.argtypes = [_P, _P, _P]
 _lib.rapid_state_features.argtypes = [_P, _P, _P]
+_lib.rapid_boundary_miss.argtypes = [_P, _P, _P, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_int32,
+                                     _P, _P]
 _lib.rapid_mlp_forward.argtypes = [_P, _P, C.c_int64, _P, C.c_float, _P, _P]
 _lib.rapid_mlp_grad.argtypes = [_P, _P, _P, _P, C.c_int32, _P, _P, _P]
 _lib.rapid_gate_train.argtypes = [_P, _P, _P, C.c_int64, C.POINTER(TrainCfg), _P, _P]
@@ -133,12 +135,15 @@ EXPORTED = ["rapid_init", "rapid_destroy", "rapid_segment", "rapid_segment_batch
             "rapid_state_destroy", "rapid_grid", "rapid_status_str", "rapid_simple_lut",
             "rapid_check_params", "rapid_last_timings", "rapid_segment_gated",
             "rapid_state_track", "rapid_state_features", "rapid_mlp_forward", "rapid_mlp_grad",
-            "rapid_gate_train", "rapid_slide_tiles", "rapid_segment_slide"]
+            "rapid_gate_train", "rapid_slide_tiles", "rapid_segment_slide", "rapid_boundary_miss"]
 
 
 def _check(rc: int, where: str):
     if rc != 0:
         raise RapidError(rc, where)
+
+
+GATE_RULES = {"either": 0, "both": 1, "differ": 2}   # RAPID_GATE_*
 
 
 def make_params(d: dict) -> Params:
@@ -156,6 +161,7 @@ def make_params(d: dict) -> Params:
     p.gate_level = int(d.get("gate_level", -1))
     p.frac_bits = int(d.get("frac_bits", 4))
     p.max_sweeps = int(d.get("max_sweeps", 64))
+    p.gate_rule = GATE_RULES[d.get("gate_rule", "either")]
     p.min_size = int(d["min_size"])
     p.max_size = int(d["max_size"])
     p.w_col = int(d["w_col"])
@@ -319,6 +325,22 @@ class Context:
                                         C.byref(model) if model is not None else None, reps),
                "rapid_segment_slide")
         return labels, ([r.stages() for r in reps] if reps is not None else None)
+
+    def boundary_miss(self, ref, test, radius: int = 2, K: int = 0, counts: bool = True):
+        """Boundary-recall misses of test against ref (two (H, W) int32
+        device maps with the same strides).  Returns (per-label counts (K,)
+        int32 or None, ref boundary pixels, missed pixels)."""
+        import torch
+        assert ref.shape == test.shape and ref.stride() == test.stride() and ref.stride(1) == 1
+        H, W = int(ref.shape[0]), int(ref.shape[1])
+        miss = torch.zeros(K, dtype=torch.int32, device=ref.device) if counts else None
+        tot = torch.zeros(2, dtype=torch.int64, device=ref.device)
+        _check(_lib.rapid_boundary_miss(self._h, C.c_void_p(ref.data_ptr()), C.c_void_p(test.data_ptr()), W, H,
+                                        int(ref.stride(0)), radius, K,
+                                        C.c_void_p(miss.data_ptr()) if miss is not None else None,
+                                        C.c_void_p(tot.data_ptr())), "rapid_boundary_miss")
+        t = tot.cpu()
+        return miss, int(t[0]), int(t[1])
 
     def mlp_forward(self, X, w_bf16, thresh: float = 0.0):
         import torch

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle import mlp
+from oracle import mlp, targets
 from paper_1704_02083_amd import params, synth
 
 pytestmark = pytest.mark.gpu
@@ -199,3 +199,27 @@ def test_non_finite_model_falls_back_to_plain(ctx, gpu_lib):
     assert e.value.code == -5
     plain, _ = ctx.segment(_dev(img), p)
     assert (lab.cpu().numpy() == plain.cpu().numpy()).all()
+
+
+@pytest.mark.parametrize("r", [0, 2, 4])
+def test_boundary_miss_matches_oracle(ctx, r):
+    """Per-label misses and totals of the boundary-recall kernel equal the
+    pixel-by-pixel reference, on maps of ragged size (not multiples of the
+    64 x 16 tiles), in strided views, with some labels outside [0, K)."""
+    import torch
+    rng = np.random.default_rng(40 + r)
+    H, W, K = 77, 301, 60
+    a = np.kron(rng.integers(0, K, size=(20, 60)), np.ones((5, 6), np.int64))[:H, :W].astype(np.int32)
+    b = np.kron(rng.integers(0, K, size=(16, 40)), np.ones((6, 8), np.int64))[:H, :W].astype(np.int32)
+    b[3:9, 100:140] = K + 5      # out of range: never charged
+    b[50:60, 7:30] = -1
+    _say("case: boundary miss %dx%d r=%d" % (W, H, r))
+    big_a = torch.zeros((H, W + 13), dtype=torch.int32, device="cuda")
+    big_b = torch.zeros((H, W + 13), dtype=torch.int32, device="cuda")
+    big_a[:, :W] = torch.from_numpy(a).cuda()
+    big_b[:, :W] = torch.from_numpy(b).cuda()
+    miss, nb, nm = ctx.boundary_miss(big_a[:, :W], big_b[:, :W], radius=r, K=K)
+    mo, nbo, nmo = targets.boundary_miss(a, b, r, K)
+    assert (nb, nm) == (nbo, nmo)
+    assert nm > 0
+    assert (miss.cpu().numpy() == mo).all()

@@ -92,17 +92,34 @@ def test_random_weights_bit_exact(ctx, seed):
     _assert_same(got, rep, oracle_out[0], oracle_out[2], "random weights")
 
 
-def test_gate_bit_exact(ctx):
+@pytest.mark.parametrize("rule", ["either", "both", "differ"])
+def test_gate_bit_exact(ctx, rule):
     """A seeded gate (input to both sides) restricts moves past the gate
-    level (Eq. (7)); labels and counters must still agree exactly."""
+    level (Eq. (7)) under each pair rule; labels and counters must still
+    agree exactly."""
     img = synth.voronoi_blur(160, 128, regions=14, seed=21)
     p = params.default_params(160, 128, 20, levels=params.THREE_LEVEL, gate_level=1)
+    p["gate_rule"] = rule
     K = oracle.n_superpixels(160, 128, p)
-    gate = (np.random.default_rng(4).random(K) < 0.4).astype(np.uint8)
-    _say("case: gate 160x128 K=%d marked=%d" % (K, int(gate.sum())))
+    gate = (np.random.default_rng(4).random(K) < (0.4 if rule == "either" else 0.7)).astype(np.uint8)
+    _say("case: gate %s 160x128 K=%d marked=%d" % (rule, K, int(gate.sum())))
     got, rep = _gpu_segment(ctx, img, p, gate=gate)
     ref, _, ref_rep = oracle.segment(img, p, gate=gate)
     _assert_same(got, rep, ref, ref_rep, "gate")
+
+
+def test_gate_beyond_lds_bitmap_refused(ctx, gpu_lib):
+    """A gated run keeps one bit per superpixel in LDS (at most 2^18
+    superpixels per image); a larger grid is refused before any launch."""
+    import torch
+    W = H = 1040
+    p = {"K": 0, "gx": 520, "gy": 520, "levels": [(1, [2, 1])], "gate_level": 0, "frac_bits": 4,
+         "max_sweeps": 4, "min_size": 0, "max_size": 64, "w_col": 1, "w_pos": 1, "w_bnd": 1}
+    rgb = torch.zeros((H, W, 3), dtype=torch.uint8, device="cuda")
+    gate = torch.ones(520 * 520, dtype=torch.uint8, device="cuda")
+    with pytest.raises(gpu_lib.RapidError) as e:
+        ctx.segment(rgb, p, gate=gate)
+    assert e.value.code == -1
 
 
 def test_state_api_level_by_level(ctx):

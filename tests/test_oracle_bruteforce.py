@@ -50,7 +50,14 @@ def _brute_force(img, p, lab, K, B, cls, gate):
         return int(bl[by, bx]) if 0 <= bx < nbx and 0 <= by < nby else -1
 
     def active(a, k):
-        return gate is None or gate[a] or gate[k]
+        if gate is None:
+            return True
+        rule = p.get("gate_rule", "either")
+        if rule == "both":
+            return bool(gate[a]) and bool(gate[k])
+        if rule == "differ":
+            return bool(gate[a]) != bool(gate[k])
+        return bool(gate[a]) or bool(gate[k])
 
     out = {}
     for by in range(cls // 3, nby, 3):
@@ -106,6 +113,7 @@ def test_proposals_equal_global_argmin(trial):
         gate = None
         if trial % 3 == 2:
             gate = rng.integers(0, 2, size=K).astype(np.uint8)
+            p["gate_rule"] = ("either", "both", "differ")[(trial // 3) % 3]
         for cls in range(9):
             props, de = oracle.propose_class(img, p, lab, K, B, cls, gate=gate)
             got = {int(b): (int(a), int(k), int(e)) for (b, a, k), e in zip(props, de)}

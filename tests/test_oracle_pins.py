@@ -331,6 +331,65 @@ def test_gate_all_zero_freezes_after_gate_level():
     assert all(r["proposals"] == 0 and r["active"] == 0 for r in gated[2][1:])
 
 
+def _gate_case():
+    img = synth.voronoi_blur(128, 128, regions=12, seed=6)
+    p = params.default_params(128, 128, 16, levels=params.THREE_LEVEL, gate_level=1)
+    K = oracle.n_superpixels(128, 128, p)
+    lvl1 = oracle.segment(img, dict(p, levels=p["levels"][:1], gate_level=-1))
+    return img, p, K, lvl1
+
+
+def test_gate_rule_both_all_ones_is_plain():
+    img, p, K, _ = _gate_case()
+    plain = oracle.segment(img, p)
+    gated = oracle.segment(img, dict(p, gate_rule="both"), gate=np.ones(K, np.uint8))
+    assert (plain[0] == gated[0]).all() and plain[2] == gated[2]
+
+
+def test_gate_rule_differ_one_class_freezes():
+    """Pairs refine only across a class border: one class everywhere means
+    no pair is active past the gate level."""
+    img, p, K, lvl1 = _gate_case()
+    for v in (0, 1):
+        gated = oracle.segment(img, dict(p, gate_rule="differ"), gate=np.full(K, v, np.uint8))
+        assert (gated[0] == lvl1[0]).all()
+        assert all(r["active"] == 0 for r in gated[2][1:])
+
+
+def test_gate_rule_both_freezes_unmarked_superpixels():
+    """Under the rule "both" a superpixel the gate leaves unmarked takes
+    part in no pair, so it keeps exactly the pixels it had at the gate
+    point, while marked ones still move."""
+    img, p, K, lvl1 = _gate_case()
+    g = (np.random.default_rng(3).random(K) < 0.5).astype(np.uint8)
+    lab = oracle.segment(img, dict(p, gate_rule="both"), gate=g)[0]
+    for k in range(K):
+        if not g[k]:
+            assert ((lab == k) == (lvl1[0] == k)).all(), k
+    assert (lab != lvl1[0]).any()
+
+
+def test_gate_rule_differ_moves_only_across_classes():
+    """Under the rule "differ" with two classes that split the image into
+    halves, every pixel that changes label past the gate point lies near the
+    class border (a move needs a neighbour of the other class)."""
+    img, p, K, lvl1 = _gate_case()
+    gx, gy = oracle.grid(128, 128, 16)
+    g = np.array([1 if (k % gx) >= gx // 2 else 0 for k in range(K)], np.uint8)
+    lab = oracle.segment(img, dict(p, gate_rule="differ"), gate=g)[0]
+    # a superpixel not adjacent to the other class at the gate point and
+    # whose neighbours are all of its own class cannot change
+    changed = lab != lvl1[0]
+    assert changed.any()
+    cls_before = g[lvl1[0]]
+    cls_after = g[lab]
+    # pixels keep their class unless they sit in a superpixel that touched
+    # the border; the class map changes only in the columns around it
+    xs = np.nonzero((cls_before != cls_after).any(axis=0))[0]
+    border = 128 * (gx // 2) // gx
+    assert xs.size and xs.min() >= border - 48 and xs.max() < border + 48
+
+
 # --------------------------------------------------------- class size filter
 
 def _filter_case(min_size, max_size):
