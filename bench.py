@@ -142,7 +142,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batch", choices=["batch", "single256", "he4096", "slide"])
     ap.add_argument("--gated", action="store_true",
-                    help="H&E workloads: also train the gate on 32 tiles and time the gated path")
+                    help="H&E workloads: also train the gate and time the gated path")
+    ap.add_argument("--gate-rule", default="both", choices=["either", "both"])
+    ap.add_argument("--train-tiles", type=int, default=64, help="4096x4096 training tiles of the gate")
     ap.add_argument("--cpu-sample", type=int, default=80)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -247,19 +249,82 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def train_gate(ctx, p_tile, seed=0):
-    """Gate network trained on 16 synthetic 2048x2048 H&E tiles with 32-px
-    cells (features and targets from plain runs, all on the GPU through the
-    C-ABI)."""
+def train_gate(ctx, rule: str, n_tiles: int, seed: int = 0):
+    """Gate network trained on n_tiles synthetic 4096x4096 H&E tiles (seeds
+    5000...) with 32-px cells: features and targets from plain runs, the
+    training itself, all on the GPU through the C-ABI."""
     import torch
     from paper_1704_02083_amd import gate, params, synth_gpu
-    tiles = [synth_gpu.he_slide(2048, 2048, seed=9000 + i, background=0.4, device="cuda")
-             for i in range(16)]
-    p = params.default_params(2048, 2048, 4096, levels=params.THREE_LEVEL, gate_level=1)
-    X, t = gate.training_set(ctx, tiles, p, tau=0.1)
+    p = params.gated(4096, 4096, 16384, rule=rule)
+    Xs, ts = [], []
+    for i in range(n_tiles):
+        rgb = synth_gpu.he_slide(4096, 4096, seed=5000 + i, background=0.4, device="cuda")
+        X, t, _ = gate.tile_samples(ctx, rgb, p)
+        Xs.append(X)
+        ts.append(t)
+        del rgb
+    X, t = torch.cat(Xs), torch.cat(ts)
+    t0 = time.perf_counter()
     master, w = gate.train(ctx, X, t, epochs=20, batch=4096, seed=seed)
     torch.cuda.synchronize()
-    return w, {"samples": int(X.shape[0]), "positive_rate": round(float(t.float().mean().item()), 4)}
+    return w, {"tiles": n_tiles, "samples": int(X.shape[0]), "positive_rate": round(float(t.float().mean().item()), 4),
+               "train_s": round(time.perf_counter() - t0, 3)}
+
+
+def bench_gated(args, ctx, rgb, labels, plain, W, H, dt_plain):
+    """The learned gate on the same image: the gated schedule (the plain
+    one with the single-pixel stage as its own, gated level), thresholds
+    from 'nothing refined past the gate point' to 'everything', and the one
+    calibrated on held-out tiles for boundary recall >= 0.99."""
+    import torch
+    from paper_1704_02083_amd import gate, metrics, params, synth_gpu
+    w, info = train_gate(ctx, args.gate_rule, args.train_tiles)
+    print("bench: gate trained (%s)" % info, file=sys.stderr, flush=True)
+    if args.workload == "slide":
+        pg = params.gated(2048, 2048, 4096, rule=args.gate_rule)
+
+        def run(th):
+            ctx.segment_slide(rgb, pg, tile=2048, halo=64, cell=32, labels=labels, w_bf16=w, thresh=th)
+    else:
+        pg = params.gated(W, H, 16384, rule=args.gate_rule)
+
+        def run(th):
+            ctx.segment_gated([rgb], pg, w, th, labels=[labels], report=False)
+    hold = [synth_gpu.he_slide(2048, 2048, seed=7100 + i, background=0.4, device="cuda") for i in range(4)]
+    crops = [(0, 0)] if args.workload != "slide" else [(1000, 3000), (9000, 17000), (20000, 7000), (28000, 28000)]
+
+    def point(th):
+        run(th)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            run(th)
+        torch.cuda.synchronize()
+        dtg = (time.perf_counter() - t0) / 3
+        ue = [metrics.undersegmentation_error(plain[y:y + 4096, x:x + 4096].cpu().numpy(),
+                                              labels[y:y + 4096, x:x + 4096].cpu().numpy()) for y, x in crops]
+        return {"thresh": th, "MPixel/s": round(W * H / dtg / 1e6, 3), "ms": round(dtg * 1e3, 3),
+                "speedup": round(dt_plain / dtg, 4), "br": round(gate.boundary_recall(ctx, plain, labels), 6),
+                "disagreement": round(float((plain != labels).float().mean().item()), 6),
+                "ue": round(float(sum(ue) / len(ue)), 6)}
+
+    curve = [point(th) for th in (1e9, 2.0, 1.0, 0.0, -1e9)]
+    res = {"train": info, "rule": args.gate_rule, "schedule": "16 | 8,4 | 2 | 1 (gate before the last level)",
+           "curve": curve,
+           "note": "thresh 1e9 refines nothing past the gate point, -1e9 everything; br and disagreement "
+                   "over the whole image against the plain labels, ue on %d 4096x4096 crops" % len(crops)}
+    # thresholds calibrated on the held-out tiles: the largest (fewest
+    # superpixels refined) that keeps their mean boundary recall at 0.99, and
+    # at the stricter 0.995 where refining nothing is no longer enough
+    res["calibrated"] = []
+    for target in (0.99, 0.995):
+        cal = gate.calibrate(ctx, hold, params.gated(2048, 2048, 4096, rule=args.gate_rule), w, target,
+                             candidates=[1e9, 4.0, 3.0, 2.0, 1.5, 1.0, 0.5, 0.0, -0.5, -1.0, -2.0, -1e9])
+        if cal is not None:
+            c = point(cal[0])
+            c["held_out"] = {k: round(v, 6) for k, v in cal[1].items()}
+            res["calibrated"].append(dict(c, target_br=target))
+    return res
 
 
 def bench_he(args):
@@ -325,22 +390,7 @@ def bench_he(args):
                      "alg_bytes_per_launch": alg},
     }
     if args.gated:
-        w, info = train_gate(ctx, p)
-        # agreement on full-resolution 4096^2 crops (all of a single image)
-        crops = [(0, 0)] if args.workload != "slide" else [(1000, 3000), (9000, 17000), (20000, 7000),
-                                                             (28000, 28000)]
-        res = {}
-        for th in (0.0, -1.0, -2.0):
-            dtg, _ = timed(lambda: run(w, th), steps, 1)
-            ms = [metrics.agreement(plain[y:y + 4096, x:x + 4096].cpu().numpy(),
-                                    labels[y:y + 4096, x:x + 4096].cpu().numpy()) for y, x in crops]
-            res[str(th)] = {"MPixel/s": round(W * H / dtg / 1e6, 3), "ms": round(dtg * 1e3, 3),
-                            "speedup": round(dt / dtg, 4)}
-            for k in ("br", "ue", "disagreement"):
-                res[str(th)][k] = round(float(sum(m[k] for m in ms) / len(ms)), 6)
-        out["gated"] = {"train": info, "by_threshold": res,
-                        "note": "agreement of the gated labels with the plain labels on %d "
-                                "4096x4096 crops" % len(crops)}
+        out["gated"] = bench_gated(args, ctx, rgb, labels, plain, W, H, dt)
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -33,12 +33,15 @@ __global__ void k_feat_blocks(const Job *__restrict__ jobs, int B, int lab_buf)
 {
     const Job &J = jobs[blockIdx.y];
     const int nbx = (J.W + B - 1) / B, nby = (J.H + B - 1) / B;
-    const int64_t nb = (int64_t)nbx * nby;
+    const int spr = (nbx + FEAT_SEG - 1) / FEAT_SEG;
+    const int64_t nseg = (int64_t)spr * nby;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    // wave-uniform loop: every lane takes part in the run sums
-    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); i0 < nb; i0 += stride) {
-        const int64_t i = i0 + (threadIdx.x & 63);
-        feat_block(J, J.lab[lab_buf], B, nbx, nby, i, i < nb, nullptr, J.fmean, J.facc);
+    const int32_t *L = J.lab[lab_buf];
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nseg; g += stride) {
+        const int by = (int)(g / spr), bx0 = (int)(g % spr) * FEAT_SEG;
+        const int32_t *row = L + (int64_t)by * nbx;
+        feat_segment(J, row, by > 0 ? row - nbx : nullptr, by + 1 < nby ? row + nbx : nullptr, B, nbx, by, bx0,
+                     min(bx0 + FEAT_SEG, nbx), nullptr, J.fmean, GlobalSink{J.facc});
     }
 }
 

@@ -115,95 +115,113 @@ __device__ __forceinline__ void feat_init_sp(const int64_t *st, int32_t *fmean, 
     a[7] = INT64_MAX;   // min contrast
 }
 
-// Sums of three values over the runs of equal keys in consecutive lanes of
-// a wave (a segmented inclusive scan); true in the last lane of each run,
-// which then holds the run's sums.  Every lane of the wave must call it.
-__device__ __forceinline__ bool run_sums3(int32_t key, int64_t &a, int64_t &b, int64_t &c)
+// Per-block contributions to a superpixel's feature accumulators.
+struct FeatAcc {
+    int64_t q[3];    // pixel second moments per channel
+    int64_t bl;      // boundary edge length (pixel edges to other labels)
+    int64_t ed2;     // sum over those edges of length x squared mean distance
+    uint64_t mx;     // largest squared mean distance to a neighbour
+    uint64_t mn;     // smallest (UINT64_MAX: none)
+};
+
+__device__ __forceinline__ void feat_zero(FeatAcc &v)
 {
-    const int lane = threadIdx.x & 63;
-    const int32_t kup = __shfl_up(key, 1);
-    int head = (lane == 0 || kup != key) ? 1 : 0;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int64_t ua = __shfl_up(a, off), ub = __shfl_up(b, off), uc = __shfl_up(c, off);
-        const int uh = __shfl_up(head, off);
-        if (lane >= off && !head) {
-            a += ua;
-            b += ub;
-            c += uc;
-            head = uh;
-        }
-    }
-    const int32_t kdn = __shfl_down(key, 1);
-    return lane == 63 || kdn != key;
+    v.q[0] = v.q[1] = v.q[2] = 0;
+    v.bl = v.ed2 = 0;
+    v.mx = 0;
+    v.mn = ~0ull;
 }
 
-// Step B for the blocks i of one wave (valid: i < number of blocks; every
-// lane of the wave calls it): pixel second moments of the block (from moms
-// when the block-sum pass stored them, else from the pixels) per
-// superpixel, and for its right and lower neighbour blocks of another label
-// the shared edge length and the squared distance of the two fixed-point
-// means, for both superpixels.
-__device__ __forceinline__ void feat_block(const Job &J, const int32_t *__restrict__ L, int B, int nbx, int nby,
-                                           int64_t i, bool valid, const uint32_t *__restrict__ moms,
-                                           const int32_t *__restrict__ fmean, int64_t *__restrict__ facc)
+// Adds one run's totals to superpixel k's accumulators in global memory.
+__device__ __forceinline__ void feat_flush(int64_t *__restrict__ facc, int32_t k, const FeatAcc &v)
+{
+    unsigned long long *a = reinterpret_cast<unsigned long long *>(facc + FACC * (int64_t)k);
+    atomicAdd(a + 0, (unsigned long long)v.q[0]);
+    atomicAdd(a + 1, (unsigned long long)v.q[1]);
+    atomicAdd(a + 2, (unsigned long long)v.q[2]);
+    if (v.bl) {
+        atomicAdd(a + 3, (unsigned long long)v.bl);
+        atomicAdd(a + 4, (unsigned long long)v.ed2);
+        atomicMax(a + 6, (unsigned long long)v.mx);
+        atomicMin(a + 7, (unsigned long long)v.mn);
+    }
+}
+
+// Blocks per segment of a row in step B.
+constexpr int FEAT_SEG = 16;
+
+// Step B for one segment: blocks [bx0, bx1) of block row by, whose labels
+// are row[], the row above up[] and below dn[] (nullptr, or -1 entries,
+// outside the image).  A block adds to its own superpixel:
+// the pixel second moments of the block (from moms when the block-sum pass
+// stored them, else from the pixels) and, for each 4-neighbour block of
+// another label, the shared edge length and the squared distance of the two
+// fixed-point means.  Both sides of an edge count it for their own
+// superpixel, so every total is a sum over the superpixel's boundary edges.
+// The lane walks its segment in order and adds to the accumulators once per
+// run of equal labels.
+struct GlobalSink {
+    int64_t *facc;
+    __device__ void operator()(int32_t k, const FeatAcc &v) const { feat_flush(facc, k, v); }
+};
+
+template <class Sink>
+__device__ __forceinline__ void feat_segment(const Job &J, const int32_t *row, const int32_t *up, const int32_t *dn,
+                                             int B, int nbx, int by, int bx0, int bx1,
+                                             const uint32_t *__restrict__ moms, const int32_t *fmean,
+                                             const Sink &sink)
 {
     const int W = J.W, H = J.H;
-    int32_t k = -1;
-    int64_t q0 = 0, q1 = 0, q2 = 0;
-    int bx = 0, by = 0, x0 = 0, y0 = 0, x1 = 0, y1 = 0;
-    if (valid) {
-        bx = (int)(i % nbx);
-        by = (int)(i / nbx);
-        x0 = bx * B;
-        y0 = by * B;
-        x1 = min(x0 + B, W);
-        y1 = min(y0 + B, H);
-        k = L[i];
+    const int y0 = by * B, y1 = min(y0 + B, H);
+    int32_t cur = -1;
+    FeatAcc v;
+    feat_zero(v);
+    int32_t left = bx0 > 0 ? row[bx0 - 1] : -1;
+    int32_t k = row[bx0];
+    for (int bx = bx0; bx < bx1; bx++) {
+        const int32_t right = bx + 1 < nbx ? row[bx + 1] : -1;
+        if (k != cur) {
+            if (cur >= 0) sink(cur, v);
+            cur = k;
+            feat_zero(v);
+        }
+        const int x0 = bx * B, x1 = min(x0 + B, W);
+        const int64_t i = (int64_t)by * nbx + bx;
         if (moms) {
-            // written by the block-sum pass of this stage
-            q0 = moms[3 * i];
-            q1 = moms[3 * i + 1];
-            q2 = moms[3 * i + 2];
+            v.q[0] += moms[3 * i];
+            v.q[1] += moms[3 * i + 1];
+            v.q[2] += moms[3 * i + 2];
         } else {
             for (int y = y0; y < y1; y++) {
-                const uint8_t *row = J.rgb + (int64_t)y * J.rgb_stride + 3 * (int64_t)x0;
+                const uint8_t *px = J.rgb + (int64_t)y * J.rgb_stride + 3 * (int64_t)x0;
                 for (int x = 0; x < x1 - x0; x++) {
-                    const int r = row[3 * x], g = row[3 * x + 1], b = row[3 * x + 2];
-                    q0 += r * r;
-                    q1 += g * g;
-                    q2 += b * b;
+                    const int r = px[3 * x], gg = px[3 * x + 1], b = px[3 * x + 2];
+                    v.q[0] += r * r;
+                    v.q[1] += gg * gg;
+                    v.q[2] += b * b;
                 }
             }
         }
-    }
-    if (run_sums3(k, q0, q1, q2) && k >= 0) {
-        int64_t *ak = facc + FACC * (int64_t)k;
-        atomicAdd(reinterpret_cast<unsigned long long *>(ak + 0), (unsigned long long)q0);
-        atomicAdd(reinterpret_cast<unsigned long long *>(ak + 1), (unsigned long long)q1);
-        atomicAdd(reinterpret_cast<unsigned long long *>(ak + 2), (unsigned long long)q2);
-    }
-    if (!valid) return;
-    for (int d = 0; d < 2; d++) {
-        const int nx = bx + (d == 0), ny = by + (d == 1);
-        if (nx >= nbx || ny >= nby) continue;
-        const int32_t j = L[(int64_t)ny * nbx + nx];
-        if (j == k) continue;
-        const int64_t e = d == 0 ? (y1 - y0) : (x1 - x0);
-        int64_t d2 = 0;
-        for (int ch = 0; ch < 3; ch++) {
-            const int64_t df = (int64_t)fmean[3 * k + ch] - fmean[3 * j + ch];
-            d2 += df * df;
+        const int32_t nbr[4] = {left, right, up ? up[bx] : -1, dn ? dn[bx] : -1};
+#pragma unroll
+        for (int d = 0; d < 4; d++) {
+            const int32_t j = nbr[d];
+            if (j < 0 || j == k) continue;
+            const int64_t e = d < 2 ? (y1 - y0) : (x1 - x0);
+            int64_t d2 = 0;
+            for (int ch = 0; ch < 3; ch++) {
+                const int64_t df = (int64_t)fmean[3 * k + ch] - fmean[3 * j + ch];
+                d2 += df * df;
+            }
+            v.bl += e;
+            v.ed2 += e * d2;
+            v.mx = (uint64_t)d2 > v.mx ? (uint64_t)d2 : v.mx;
+            v.mn = (uint64_t)d2 < v.mn ? (uint64_t)d2 : v.mn;
         }
-        const int32_t both[2] = {k, j};
-        for (int u = 0; u < 2; u++) {
-            int64_t *a = facc + FACC * (int64_t)both[u];
-            atomicAdd(reinterpret_cast<unsigned long long *>(a + 3), (unsigned long long)e);
-            atomicAdd(reinterpret_cast<unsigned long long *>(a + 4), (unsigned long long)(e * d2));
-            atomicMax(reinterpret_cast<unsigned long long *>(a + 6), (unsigned long long)d2);
-            atomicMin(reinterpret_cast<unsigned long long *>(a + 7), (unsigned long long)d2);
-        }
+        left = k;
+        k = right;
     }
+    if (cur >= 0) sink(cur, v);
 }
 
 // Step C for superpixel k: the sixteen features (double arithmetic without

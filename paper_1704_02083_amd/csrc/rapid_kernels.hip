@@ -297,26 +297,149 @@ __device__ __forceinline__ void class_push(int32_t *cnt, int32_t *lds, int capl,
     list_put(lds + cls * capl, capl, glob, cls * capg, slot, v);
 }
 
+// Accumulators of one superpixel in the LDS window of the gate point.
+struct WinAcc {
+    unsigned long long q[3], ed2;
+    unsigned bl, mx, mn, pad;
+};
+
+// Runs of superpixels whose initial grid row lies in [ky0, ky0 + rows) go
+// to the LDS window (LDS atomics), any other run straight to global memory.
+struct WindowSink {
+    WinAcc *win;
+    int64_t *facc;
+    int gx, ky0, rows;
+    __device__ void operator()(int32_t k, const FeatAcc &v) const
+    {
+        const int r = k / gx - ky0;
+        if (r < 0 || r >= rows) {
+            feat_flush(facc, k, v);
+            return;
+        }
+        WinAcc &w = win[r * gx + k % gx];
+        atomicAdd(&w.q[0], (unsigned long long)v.q[0]);
+        atomicAdd(&w.q[1], (unsigned long long)v.q[1]);
+        atomicAdd(&w.q[2], (unsigned long long)v.q[2]);
+        if (v.bl) {
+            atomicAdd(&w.bl, (unsigned)v.bl);
+            atomicAdd(&w.ed2, (unsigned long long)v.ed2);
+            atomicMax(&w.mx, (unsigned)v.mx);
+            atomicMin(&w.mn, (unsigned)v.mn);
+        }
+    }
+};
+
 // The gate point of a fused launch (Algorithm RAPID, before the gated
 // level), run by the whole workgroup: features of every superpixel on the
 // labels of the previous stage (block size Bq), the network's logit and the
 // gate bits (Eq. (6)).  Only the fused-gate instantiation of the kernel
 // contains it, so the plain kernel's registers are not affected.
+//
+// The work lists' LDS (lds, lds_bytes) is free here.  It holds the
+// fixed-point means of all superpixels, then bands of RB block rows of the
+// label map (with a halo row above and below) loaded with coalesced bulk
+// reads, which the lanes walk in segments, and a window of accumulators for
+// the superpixels whose initial grid rows meet the band: runs add to the
+// window with LDS atomics, the window goes to global memory once per band.
+// A band of a few cells' height touches few grid rows, so this replaces
+// most global atomics (which contend on the same lines) with LDS ones.  The
+// squared mean distances fit 32 bits (F <= 4).  Falls back to the label
+// map in global memory when the LDS is too small.
 __device__ __attribute__((noinline)) void gate_point(const Job &J, const int64_t *st, int stage_q, int Bq, int F,
-                                                     const uint16_t *mlp_w, float thresh, int tid, int nt)
+                                                     const uint16_t *mlp_w, float thresh, char *lds,
+                                                     uint32_t lds_bytes, int tid, int nt)
 {
     const int K = J.K;
     const int nbxq = (J.W + Bq - 1) / Bq, nbyq = (J.H + Bq - 1) / Bq;
-    const int64_t nbq = (int64_t)nbxq * nbyq;
     const int32_t *Lq = J.lab[stage_q & 1];
-    for (int k = tid; k < K; k += nt) feat_init_sp(st, J.fmean, J.facc, k, F);
-    wg_sync();
-    for (int64_t i0 = tid & ~63; i0 < nbq; i0 += nt) {
-        const int64_t i = i0 + (tid & 63);
-        feat_block(J, Lq, Bq, nbxq, nbyq, i, i < nbq, (J.moms && J.moms_stage == stage_q) ? J.moms : nullptr,
-                   J.fmean, J.facc);
+    const uint32_t *moms = (J.moms && J.moms_stage == stage_q) ? J.moms : nullptr;
+    const int spr = (nbxq + FEAT_SEG - 1) / FEAT_SEG;
+    // LDS carve-up: means, window, band
+    const int64_t fm_bytes = (12 * (int64_t)K + 15) & ~15ll;
+    // a band of about one cell height (at least one block row)
+    const int cell_rows = max(1, (int)(((int64_t)J.H / J.gy) / Bq));
+    int RB = min(cell_rows, nbyq);
+    int WR = 0;
+    int64_t win_bytes = 0, band_bytes = 0;
+    bool staged = false;
+    for (; RB >= 1; RB >>= 1) {
+        // grid rows met by RB block rows: the rows of their pixel span, one
+        // more for the block-centre rule's rounding, two for drift
+        WR = min(J.gy, (int)(((int64_t)RB * Bq * J.gy + J.H - 1) / J.H) + 3);
+        win_bytes = (int64_t)WR * J.gx * (int64_t)sizeof(WinAcc);
+        band_bytes = 4 * (int64_t)(RB + 2) * nbxq;
+        if (fm_bytes + win_bytes + band_bytes <= (int64_t)lds_bytes) {
+            staged = true;
+            break;
+        }
+    }
+    int32_t *fm_l = reinterpret_cast<int32_t *>(lds);
+    WinAcc *win = reinterpret_cast<WinAcc *>(lds + fm_bytes);
+    int32_t *band = reinterpret_cast<int32_t *>(lds + fm_bytes + win_bytes);
+    for (int k = tid; k < K; k += nt) {
+        feat_init_sp(st, J.fmean, J.facc, k, F);
+        if (staged)
+            for (int ch = 0; ch < 3; ch++) fm_l[3 * k + ch] = J.fmean[3 * k + ch];
+    }
+    if (staged) {
+        for (int e = tid; e < WR * J.gx; e += nt) {
+            WinAcc &w = win[e];
+            w.q[0] = w.q[1] = w.q[2] = w.ed2 = 0;
+            w.bl = w.mx = 0;
+            w.mn = 0xFFFFFFFFu;
+        }
     }
     wg_sync();
+    if (staged) {
+        for (int by0 = 0; by0 < nbyq; by0 += RB) {
+            const int rows = min(RB, nbyq - by0);
+            // rows by0 - 1 .. by0 + rows of the label map, -1 outside it
+            for (int r = 0; r < rows + 2; r++) {
+                const int y = by0 - 1 + r;
+                for (int x = tid; x < nbxq; x += nt)
+                    band[r * nbxq + x] = (y >= 0 && y < nbyq) ? Lq[(int64_t)y * nbxq + x] : -1;
+            }
+            // grid rows of the band's first pixel row, minus one
+            const int ky0 = (int)(((int64_t)by0 * Bq * J.gy) / J.H) - 1;
+            WindowSink sink{win, J.facc, J.gx, ky0, WR};
+            wg_sync();
+            for (int g = tid; g < rows * spr; g += nt) {
+                const int r = g / spr, bx0 = (g - r * spr) * FEAT_SEG;
+                const int32_t *row = band + (r + 1) * nbxq;
+                feat_segment(J, row, row - nbxq, row + nbxq, Bq, nbxq, by0 + r, bx0, min(bx0 + FEAT_SEG, nbxq), moms,
+                             fm_l, sink);
+            }
+            wg_sync();
+            // the window to global memory, then cleared for the next band
+            for (int e = tid; e < WR * J.gx; e += nt) {
+                WinAcc &w = win[e];
+                const int k = (ky0 + e / J.gx) * J.gx + e % J.gx;
+                if (w.q[0] | w.q[1] | w.q[2] | w.bl) {
+                    FeatAcc v;
+                    v.q[0] = (int64_t)w.q[0];
+                    v.q[1] = (int64_t)w.q[1];
+                    v.q[2] = (int64_t)w.q[2];
+                    v.bl = w.bl;
+                    v.ed2 = (int64_t)w.ed2;
+                    v.mx = w.mx;
+                    v.mn = w.mn;
+                    feat_flush(J.facc, k, v);
+                    w.q[0] = w.q[1] = w.q[2] = w.ed2 = 0;
+                    w.bl = w.mx = 0;
+                    w.mn = 0xFFFFFFFFu;
+                }
+            }
+            wg_sync();
+        }
+    } else {
+        for (int64_t g = tid; g < (int64_t)spr * nbyq; g += nt) {
+            const int by = (int)(g / spr), bx0 = (int)(g % spr) * FEAT_SEG;
+            const int32_t *row = Lq + (int64_t)by * nbxq;
+            feat_segment(J, row, by > 0 ? row - nbxq : nullptr, by + 1 < nbyq ? row + nbxq : nullptr, Bq, nbxq, by,
+                         bx0, min(bx0 + FEAT_SEG, nbxq), moms, J.fmean, GlobalSink{J.facc});
+        }
+        wg_sync();
+    }
     for (int k = tid; k < K; k += nt) feat_final_sp(J, st, J.facc, J.moved, k, F, J.xrow + 16 * (int64_t)k);
     wg_sync();
     const int lane = tid & 63;
@@ -413,8 +536,12 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
         const int nbx = (W + B - 1) / B, nby = (H + B - 1) / B;
         const int64_t nb = (int64_t)nbx * nby;
         int32_t *L = J.lab[s & 1];
-        if (GM == GM_FUSED && s == sc.gate_stage && s > 0)
-            gate_point(J, st, s - 1, sc.B[s - 1], sc.F, sc.mlp_w, sc.mlp_thresh, tid, nt);
+        if (GM == GM_FUSED && s == sc.gate_stage && s > 0) {
+            gate_point(J, st, s - 1, sc.B[s - 1], sc.F, sc.mlp_w, sc.mlp_thresh, smem + lp.off_lists,
+                       lp.total - lp.off_lists, tid, nt);
+            // the frontier bitmap shares that LDS and must start the stage clear
+            for (int i = tid; i < lp.bm_words; i += nt) l_bm[i] = 0;
+        }
         // moved pixels feed the gate's features: past the gate point of a
         // fused launch nothing needs them
         int64_t *const mv = (GM == GM_FUSED && s >= sc.gate_stage) ? nullptr : J.moved;

@@ -18,6 +18,11 @@ from __future__ import annotations
 SINGLE_LEVEL = [(1, [16, 8, 4, 2, 1])]
 # three levels with linear ratio 4: effective block sizes 16 | 8, 4 | 2, 1
 THREE_LEVEL = [(16, [1]), (4, [2, 1]), (1, [2, 1])]
+# the same effective block sizes with the last level split in two (levels
+# are exact box sums, so the plain result is identical): 16 | 8, 4 | 2 | 1.
+# The gated workloads gate the last level, the single-pixel stage.
+GATED_LEVELS = [(16, [1]), (4, [2, 1]), (2, [1]), (1, [1])]
+GATE_LEVEL = 3
 
 
 def default_params(W: int, H: int, K: int, levels=None, min_size: int | None = None,
@@ -50,3 +55,11 @@ def config2(W: int, H: int) -> dict:
 def config3(W: int = 4096, H: int = 4096, K: int = 16384, gate_level: int = -1) -> dict:
     """H&E tile, three levels of ratio 4."""
     return default_params(W, H, K, levels=THREE_LEVEL, gate_level=gate_level)
+
+
+def gated(W: int, H: int, K: int, rule: str = "both") -> dict:
+    """H&E tile or slide tile under the learned gate: the schedule of
+    config3 with the single-pixel stage as the gated level."""
+    p = default_params(W, H, K, levels=GATED_LEVELS, gate_level=GATE_LEVEL)
+    p["gate_rule"] = rule
+    return p
