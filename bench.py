@@ -40,9 +40,14 @@ def kernel_source_hash() -> str:
 def workload(name: str):
     from paper_1704_02083_amd import params, synth
     if name == "slide":
-        return None, params.default_params(2048, 2048, 4096, levels=params.THREE_LEVEL, gate_level=1), (
+        return None, params.default_params(2048, 2048, 4096, levels=params.THREE_LEVEL), (
             "whole-slide-like: 32768x32768 RGB uint8 synthetic H&E (40% background), 2048x2048 tiles "
             "with 64-px halo in one launch, 32-px cells (1,048,576 superpixels), three levels 16|8,4|2,1")
+    if name == "slide65k":
+        return None, params.default_params(2048, 2048, 4096, levels=params.THREE_LEVEL), (
+            "whole-slide-like: 65536x49152 RGB uint8 synthetic H&E (3.22 GPixel, 40% background), 768 "
+            "2048x2048 tiles with 64-px halo in one launch, 32-px cells (3,145,728 superpixels), three "
+            "levels 16|8,4|2,1")
     if name == "he4096":
         return None, params.config3(gate_level=1), (
             "one 4096x4096 RGB uint8 synthetic H&E tile (30% background), K=16384, three levels 16|8,4|2,1")
@@ -140,7 +145,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batch", choices=["batch", "single256", "he4096", "slide"])
+    ap.add_argument("--workload", default="batch", choices=["batch", "single256", "he4096", "slide", "slide65k"])
     ap.add_argument("--gated", action="store_true",
                     help="H&E workloads: also train the gate and time the gated path")
     ap.add_argument("--gate-rule", default="both", choices=["either", "both"])
@@ -161,16 +166,26 @@ def main():
     from paper_1704_02083_amd import rapid
 
     if args.copy_calibration:
+        # a plain 1 GiB device copy: scales the byte counters of rocprofv3
+        # --pmc, and its rate is the achievable HBM bandwidth to set beside
+        # the 8 TB/s peak (read + write bytes over the copy's duration)
         n = 1 << 30
         src = torch.ones(n, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(3):
             dst.copy_(src)
+        e1.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_bytes": n, "launches": 3}), flush=True)
+        ms = e0.elapsed_time(e1) / 3
+        print(json.dumps({"copy_calibration_bytes": n, "launches": 4, "copy_ms": round(ms, 4),
+                          "copy_GBps": round(2 * n / (ms * 1e-3) / 1e9, 1)}), flush=True)
         return
 
-    if args.workload in ("slide", "he4096"):
+    if args.workload in ("slide", "slide65k", "he4096"):
         return bench_he(args)
 
     imgs, p, desc = workload(args.workload)
@@ -280,7 +295,7 @@ def bench_gated(args, ctx, rgb, labels, plain, W, H, dt_plain):
     from paper_1704_02083_amd import gate, metrics, params, synth_gpu
     w, info = train_gate(ctx, args.gate_rule, args.train_tiles)
     print("bench: gate trained (%s)" % info, file=sys.stderr, flush=True)
-    if args.workload == "slide":
+    if args.workload in ("slide", "slide65k"):
         pg = params.gated(2048, 2048, 4096, rule=args.gate_rule)
 
         def run(th):
@@ -291,7 +306,7 @@ def bench_gated(args, ctx, rgb, labels, plain, W, H, dt_plain):
         def run(th):
             ctx.segment_gated([rgb], pg, w, th, labels=[labels], report=False)
     hold = [synth_gpu.he_slide(2048, 2048, seed=7100 + i, background=0.4, device="cuda") for i in range(4)]
-    crops = [(0, 0)] if args.workload != "slide" else [(1000, 3000), (9000, 17000), (20000, 7000), (28000, 28000)]
+    crops = [(0, 0)] if args.workload == "he4096" else [(1000, 3000), (9000, 17000), (20000, 7000), (28000, 28000)]
 
     def point(th):
         run(th)
@@ -334,9 +349,9 @@ def bench_he(args):
     from paper_1704_02083_amd import metrics, rapid, synth_gpu
     _, p, desc = workload(args.workload)
     ctx = rapid.Context(0, timing=True)
-    if args.workload == "slide":
-        W = H = 32768
-        rgb = synth_gpu.he_slide(W, H, seed=4, background=0.4, device="cuda", band=2048)
+    if args.workload in ("slide", "slide65k"):
+        W, H, seed = (32768, 32768, 4) if args.workload == "slide" else (65536, 49152, 5)
+        rgb = synth_gpu.he_slide(W, H, seed=seed, background=0.4, device="cuda", band=1024)
         labels = torch.empty((H, W), dtype=torch.int32, device="cuda")
 
         def run(w=None, th=0.0):
@@ -370,7 +385,7 @@ def bench_he(args):
     dt, ref_ms = timed(lambda: run(), steps, warm)
     plain = labels.clone()
     # per-stage counters of the same deterministic work, from one untimed call
-    if args.workload == "slide":
+    if args.workload in ("slide", "slide65k"):
         _, reps = ctx.segment_slide(rgb, p, tile=2048, halo=64, cell=32, labels=labels, report=True)
         alg = tiles_alg_bytes(W, H, rapid.tile_layout(W, H, 2048, 64, 32), reps)
     else:
