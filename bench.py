@@ -150,7 +150,7 @@ def main():
                     help="H&E workloads: also train the gate and time the gated path")
     ap.add_argument("--gate-rule", default="both", choices=["either", "both"])
     ap.add_argument("--train-tiles", type=int, default=64, help="4096x4096 training tiles of the gate")
-    ap.add_argument("--cpu-sample", type=int, default=80)
+    ap.add_argument("--cpu-sample", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy three times (scales the HBM "
