@@ -247,7 +247,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
     size_t bytes = 0;
     size_t off_lab[2], off_sums[MAXST], off_lists, off_props, off_changed, off_stamp;
-    size_t off_stats, off_means, off_flow, off_mdbl, off_rep;
+    size_t off_stats, off_means, off_flow, off_rep;
     size_t off_fmean, off_facc, off_moved, off_moms;
     int64_t capc = 0;
 };
@@ -278,7 +278,6 @@ Layout plan(int32_t W, int32_t H, int32_t K, const Sched &sc, int moms_stage = -
     L.off_stats = take(8 * 6 * (size_t)K);
     L.off_means = take(4 * MN_STRIDE * (size_t)K);
     L.off_flow = take(4 * 2 * (size_t)K);
-    L.off_mdbl = take(8 * MD_STRIDE * (size_t)K);
     L.off_rep = take(sizeof(rapid_stage_report) * MAXST);
     L.off_fmean = take(4 * 3 * (size_t)K);
     L.off_facc = take(8 * FACC * (size_t)K);
@@ -317,7 +316,6 @@ void fill_job(Job &J, char *base, const Layout &L, const rapid_image *img, int32
     J.stats = reinterpret_cast<int64_t *>(base + L.off_stats);
     J.means = reinterpret_cast<int32_t *>(base + L.off_means);
     J.flow = reinterpret_cast<int32_t *>(base + L.off_flow);
-    J.mdbl = reinterpret_cast<double *>(base + L.off_mdbl);
     J.rep = reinterpret_cast<rapid_stage_report *>(base + L.off_rep);
     J.gate = gate;
     J.fmean = reinterpret_cast<int32_t *>(base + L.off_fmean);

@@ -70,7 +70,6 @@ struct Job {
     int64_t *stats;          // K x 6 int64: n, S_r, S_g, S_b, T_x, T_y
     int32_t *means;          // K x MN_STRIDE (global working set)
     int32_t *flow;           // K x 2 out/in (global working set)
-    double *mdbl;            // K x MD_STRIDE (global working set)
     rapid_stage_report *rep; // per stage
     const uint8_t *gate;     // K bytes or null
     // optional tracking (null: off)
@@ -107,10 +106,9 @@ hipError_t launch_refine(const Job *jobs_dev, int n_jobs, const Sched &sc, const
 constexpr int MLP_PARAMS = 5313;
 constexpr int FACC = 8;
 
-// per-superpixel means record: c_r c_g c_b mu_x mu_y n (int32)
-constexpr int MN_STRIDE = 6;
-// per-superpixel fp64 energy record: A c'_r c'_g c'_b mu'_x mu'_y
-constexpr int MD_STRIDE = 6;
+// per-superpixel means record: c_r c_g c_b mu_x mu_y n and two pad words
+// (int32; 32 bytes, one aligned sector per superpixel)
+constexpr int MN_STRIDE = 8;
 
 hipError_t launch_features(const Job *jobs_dev, int n_jobs, int B, int lab_buf, int F, int32_t Kmax,
                            int64_t max_nb, const int64_t *xoff_dev, float *X, hipStream_t stream);
@@ -126,8 +124,8 @@ constexpr int BOUNDARY_MISS_RMAX = 4;
 hipError_t launch_boundary_miss(const int32_t *ref, const int32_t *test, int W, int H, int64_t stride, int r,
                                 int32_t K, int32_t *miss, int64_t *totals, hipStream_t stream);
 
-// bytes of LDS per superpixel when the statistics live in LDS: sums,
-// fp64 energy record, means record, flow counters
-constexpr size_t LDS_PER_SP = 6 * 8 + MD_STRIDE * 8 + MN_STRIDE * 4 + 2 * 4;
+// bytes of LDS per superpixel when the statistics live in LDS: sums, means
+// record, flow counters
+constexpr size_t LDS_PER_SP = 6 * 8 + MN_STRIDE * 4 + 2 * 4;
 
 }  // namespace rapid

@@ -104,22 +104,13 @@ __device__ __forceinline__ int64_t block_energy(const int32_t *mn, int k, const 
     return sc.w_col * e_col + sc.w_pos * e_pos + ((sc.w_bnd * (int64_t)bnd) << (2 * sc.F));
 }
 
-// Means in fixed point, rounded half up, plus the size n: the class-start
-// snapshot that every proposal and every size-filter decision of the next
-// class reads while the integer atomics of that class update the sums.
-// Refresh superpixel k from its exact integer sums (st[k]):
-//  mn[k]: means in fixed point, floor((2^(F+1) S + n) / (2 n)) (rounded half
-//         up), and the size n -- the class-start snapshot every proposal and
-//         every size-filter decision of the next class reads;
-//  md[k]: the same means folded into the fp64 form of E',
-//         A = w_col |c|^2 + w_pos |mu|^2, c' = w_col 2^(F+1) c,
-//         mu' = w_pos 2^(F+1) mu, so that E' = m A - <c', I> - <mu', P>
-//         + w_bnd 2^(2F) bnd.  Used only where every term is an integer
-//         below 2^53 (then exact).
-// The quotients use one reciprocal and an exact correction step (all
-// products stay below 2^53).
-__device__ __forceinline__ void refresh_sp(const int64_t *st, int32_t *mn, double *md, int k,
-                                           const Sched &sc)
+// Refresh superpixel k from its exact integer sums (st[k]): mn[k] holds its
+// means in fixed point, floor((2^(F+1) S + n) / (2 n)) (rounded half up),
+// and its size n -- the class-start snapshot every proposal and every
+// size-filter decision of the next class reads while the integer atomics of
+// that class update the sums.  The quotients use one reciprocal and an exact
+// correction step (all products stay below 2^53).
+__device__ __forceinline__ void refresh_sp(const int64_t *st, int32_t *mn, int k, const Sched &sc)
 {
     const int64_t *r = st + 6 * (int64_t)k;
     const int64_t n = r[0];
@@ -137,22 +128,29 @@ __device__ __forceinline__ void refresh_sp(const int64_t *st, int32_t *mn, doubl
         o[j] = (int32_t)v;
     }
     o[5] = (int32_t)n;
-    double *d = md + MD_STRIDE * k;
-    d[0] = fma(sc.d_wc, fma(q[0], q[0], fma(q[1], q[1], q[2] * q[2])), sc.d_wp * fma(q[3], q[3], q[4] * q[4]));
-    d[1] = sc.d_wcfs * q[0];
-    d[2] = sc.d_wcfs * q[1];
-    d[3] = sc.d_wcfs * q[2];
-    d[4] = sc.d_wpfs * q[3];
-    d[5] = sc.d_wpfs * q[4];
 }
 
-// fp64 E' from the folded superpixel record (see refresh_sp).
-__device__ __forceinline__ double energy_md(const double *md, int k, double m, double I0, double I1,
-                                            double I2, double px, double py, double wbnd)
+// Superpixel k's means record as two vector loads: (c_r, c_g, c_b, mu_x)
+// and (mu_y, n).
+__device__ __forceinline__ void load_mn(const int32_t *mn, int k, int4 &lo, int2 &hi)
 {
-    const double *d = md + MD_STRIDE * k;
-    const double lin = fma(d[1], I0, fma(d[2], I1, fma(d[3], I2, fma(d[4], px, d[5] * py))));
-    return fma(m, d[0], -lin) + wbnd;
+    const int4 *p = reinterpret_cast<const int4 *>(mn + MN_STRIDE * (int64_t)k);
+    lo = p[0];
+    hi = *reinterpret_cast<const int2 *>(p + 1);
+}
+
+// E' in fp64 from a means record: m A - <c', I> - <mu', P> + w_bnd 2^(2F) bnd
+// with A = w_col |c|^2 + w_pos |mu|^2, c' = w_col 2^(F+1) c and
+// mu' = w_pos 2^(F+1) mu.  Used only where every product and partial sum is
+// an integer below 2^53 (checked on the host per stage): then exact.
+__device__ __forceinline__ double energy_f64(const int4 &lo, const int2 &hi, const Sched &sc, double m, double I0,
+                                             double I1, double I2, double px, double py, double wbnd)
+{
+    const double q0 = lo.x, q1 = lo.y, q2 = lo.z, q3 = lo.w, q4 = hi.x;
+    const double A = fma(sc.d_wc, fma(q0, q0, fma(q1, q1, q2 * q2)), sc.d_wp * fma(q3, q3, q4 * q4));
+    const double lin =
+        fma(sc.d_wcfs * q0, I0, fma(sc.d_wcfs * q1, I1, fma(sc.d_wcfs * q2, I2, fma(sc.d_wpfs * q3, px, (sc.d_wpfs * q4) * py))));
+    return fma(m, A, -lin) + wbnd;
 }
 
 __device__ __forceinline__ int32_t lab_at(const int32_t *L, int bx, int by, int nbx, int nby)
@@ -466,16 +464,13 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
     const int tid = threadIdx.x, nt = blockDim.x;
     const int W = J.W, H = J.H, K = J.K;
     int64_t *st;
-    double *md;
     int32_t *mn, *fl;
     if (LDS) {
         st = reinterpret_cast<int64_t *>(smem);
-        md = reinterpret_cast<double *>(st + 6 * (int64_t)K);   // K x MD_STRIDE
-        mn = reinterpret_cast<int32_t *>(md + MD_STRIDE * (int64_t)K);  // K x MN_STRIDE
+        mn = reinterpret_cast<int32_t *>(st + 6 * (int64_t)K);   // K x MN_STRIDE, 16-byte aligned
         fl = mn + MN_STRIDE * (int64_t)K;
     } else {
         st = J.stats;
-        md = J.mdbl;
         mn = J.means;
         fl = J.flow;
     }
@@ -528,7 +523,7 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
         for (int64_t i = tid; i < 6 * (int64_t)K; i += nt) st[i] = J.stats[i];
     }
     wg_sync();
-    for (int k = tid; k < K; k += nt) refresh_sp(st, mn, md, k, sc);
+    for (int k = tid; k < K; k += nt) refresh_sp(st, mn, k, sc);
     wg_sync();
 
     for (int s = s_begin; s < s_end; s++) {
@@ -695,16 +690,22 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                                 if (use_f64) {
                                     const double dm = (double)g.m, dI0 = (double)I[0], dI1 = (double)I[1],
                                                  dI2 = (double)I[2], dpx = (double)g.px, dpy = (double)g.py;
-                                    double estar = energy_md(md, a, dm, dI0, dI1, dI2, dpx, dpy, sc.d_wb * (double)bnd_a);
+                                    int4 ra;
+                                    int2 rb;
+                                    load_mn(mn, a, ra, rb);
+                                    double estar = energy_f64(ra, rb, sc, dm, dI0, dI1, dI2, dpx, dpy, sc.d_wb * (double)bnd_a);
 #pragma unroll
                                     for (int u = 0; u < 4; u++) {
                                         const int32_t k = cs[u];
                                         if (k == INT32_MAX || (u > 0 && k == cs[u - 1])) continue;
-                                        if ((int64_t)mn[MN_STRIDE * k + 5] + g.m > sc.max_size) continue;
+                                        int4 ka;
+                                        int2 kb;
+                                        load_mn(mn, k, ka, kb);
+                                        if ((int64_t)kb.y + g.m > sc.max_size) continue;
                                         int bnd = 0;
 #pragma unroll
                                         for (int d = 0; d < 4; d++) bnd += (nl[d] >= 0 && nl[d] != k) ? el[d] : 0;
-                                        double ek = energy_md(md, k, dm, dI0, dI1, dI2, dpx, dpy, sc.d_wb * (double)bnd);
+                                        double ek = energy_f64(ka, kb, sc, dm, dI0, dI1, dI2, dpx, dpy, sc.d_wb * (double)bnd);
                                         if (ek < estar) {
                                             estar = ek;
                                             best = k;
@@ -805,7 +806,7 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                     const Prop rec = e < capp ? l_props[e] : g_props[e];
                     const int32_t sp = side ? rec.k : rec.a;
                     fl[2 * sp + side] = 0;
-                    if (rec.pad) refresh_sp(st, mn, md, sp, sc);
+                    if (rec.pad) refresh_sp(st, mn, sp, sc);
                 }
                 // every thread read np before the P2 barrier: safe to reset
                 if (tid == 0) {
