@@ -31,7 +31,7 @@ METRIC = "MPixel/s segmented (all levels) at 1 MI355X, gated vs plain, % HBM pea
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("rapid_kernels.hip", "rapid_internal.h"):
+    for f in ("rapid_kernels.hip", "rapid_internal.h", "rapid_gate_dev.h"):
         with open(os.path.join(ROOT, "paper_1704_02083_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

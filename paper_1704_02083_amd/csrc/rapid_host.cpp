@@ -555,8 +555,8 @@ rapid_status rapid_last_timings(rapid_ctx *ctx, rapid_timings *out)
 namespace {
 
 // A batch of images laid out in the context's scratch pool: per image its
-// Job scratch, then (for the gate) the feature rows of all superpixels,
-// their gate bits and the per-image row offsets.
+// Job scratch, then (for the gate) the feature rows and the gate bits of
+// all superpixels, image after image.
 struct Batch {
     std::vector<Job> jobs;
     std::vector<int64_t> xoff;
@@ -566,7 +566,6 @@ struct Batch {
     int64_t max_nb[MAXST] = {};
     float *X = nullptr;
     uint8_t *gates = nullptr;
-    int64_t *xoff_dev = nullptr;
 };
 
 struct TileInfo {
@@ -617,12 +616,11 @@ rapid_status prepare_batch(rapid_ctx *ctx, const rapid_image *imgs, int32_t n, c
         Wmax = std::max(Wmax, imgs[i].W);
         Hmax = std::max(Hmax, imgs[i].H);
     }
-    size_t off_x = total, off_g = 0, off_xo = 0;
+    size_t off_x = total, off_g = 0;
     if (gated) {
         off_x = align256(total);
         off_g = align256(off_x + 4 * 16 * (size_t)b.Ktot);
-        off_xo = align256(off_g + (size_t)b.Ktot);
-        total = align256(off_xo + 8 * (size_t)n);
+        total = align256(off_g + (size_t)b.Ktot);
     }
     if (total > ctx->pool_size) {
         HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -657,8 +655,6 @@ rapid_status prepare_batch(rapid_ctx *ctx, const rapid_image *imgs, int32_t n, c
     if (gated) {
         b.X = reinterpret_cast<float *>(ctx->pool + off_x);
         b.gates = reinterpret_cast<uint8_t *>(ctx->pool + off_g);
-        b.xoff_dev = reinterpret_cast<int64_t *>(ctx->pool + off_xo);
-        HIPCHK(hipMemcpyAsync(b.xoff_dev, b.xoff.data(), 8 * (size_t)n, hipMemcpyHostToDevice, ctx->stream));
         // the gate is evaluated inside the refinement launch (FLAG_GATE),
         // which also clears the moved counters
         for (int i = 0; i < n; i++) {
