@@ -86,7 +86,7 @@ typedef struct {
  *  gate_level first level refined under a gate (Algorithm RAPID applies
  *             the prediction at the second level); -1: never.
  *  frac_bits  F, fixed-point fraction bits of the means (0..4).
- *  max_sweeps sweep cap per stage (>= 1).
+ *  max_sweeps sweep cap per stage (1 .. 2^20).
  *  gate_rule  how the per-superpixel gate bits g select the pairs (a, k)
  *             that may exchange blocks past the gate level (Eq. (7)):
  *             RAPID_GATE_EITHER  g_a or g_k (g = 1 everywhere is the plain

@@ -150,7 +150,7 @@ rapid_status make_sched(const rapid_params *p, Sched *sc, int32_t level_first[RA
         for (int l = 0; l < p->gate_level; l++) first += p->n_stages[l];
         sc->gate_stage = first;
     }
-    if (p->frac_bits < 0 || p->frac_bits > 4 || p->max_sweeps < 1) return RAPID_EINVAL;
+    if (p->frac_bits < 0 || p->frac_bits > 4 || p->max_sweeps < 1 || p->max_sweeps > (1 << 20)) return RAPID_EINVAL;
     if (p->gate_rule < RAPID_GATE_EITHER || p->gate_rule > RAPID_GATE_DIFFER) return RAPID_EINVAL;
     sc->gate_rule = p->gate_rule;
     if (p->w_col < 0 || p->w_pos < 0 || p->w_bnd < 0 || p->min_size < 0 || p->max_size < 1)

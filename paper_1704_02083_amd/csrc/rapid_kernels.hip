@@ -198,6 +198,23 @@ __device__ __forceinline__ bool eligible(const int32_t *L, int bx, int by, int n
     return false;
 }
 
+// Inserts block index ni into the LDS hash set tab (mask + 1 words, keys
+// stored as ni + 1, 0 = empty, linear probing).  True for the first
+// insertion of ni.  The caller keeps the load at most one half, so a free
+// word is always found.
+__device__ __forceinline__ bool hash_insert(uint32_t *tab, int mask, int32_t ni)
+{
+    const uint32_t key = (uint32_t)ni + 1u;
+    uint32_t h = ((uint32_t)ni * 2654435761u) & (uint32_t)mask;
+    for (int probe = 0; probe <= mask; probe++) {
+        const uint32_t old = atomicCAS(&tab[h], 0u, key);
+        if (old == 0u) return true;
+        if (old == key) return false;
+        h = (h + 1u) & (uint32_t)mask;
+    }
+    return false;
+}
+
 __device__ __forceinline__ void wg_sync()
 {
     __syncthreads();
@@ -478,6 +495,12 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
     Prop *l_props = reinterpret_cast<Prop *>(smem + lp.off_props);
     int32_t *l_chg = reinterpret_cast<int32_t *>(smem + lp.off_chg);
     uint32_t *l_bm = reinterpret_cast<uint32_t *>(smem + lp.off_bm);
+    // the bitmap's words as an open-addressing hash set: a power of two
+    int ht_cap = 0;
+    if (lp.bm_words >= 64) {
+        ht_cap = 64;
+        while (2 * ht_cap <= lp.bm_words) ht_cap *= 2;
+    }
     uint32_t *l_gate = reinterpret_cast<uint32_t *>(smem + lp.off_gate);
     bool gate_loaded = false;
     Prop *g_props = J.props;
@@ -490,6 +513,14 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
         s_nchg = 0;
     }
     for (int64_t i = tid; i < 2 * (int64_t)K; i += nt) fl[i] = 0;
+    if (s_end > s_begin) {
+        // visit stamps are unique per (stage, sweep) of this launch: cleared
+        // once, for the largest stage whose blocks the LDS bitmap cannot cover
+        const int Bf = sc.B[s_end - 1];
+        const int64_t nbf = (int64_t)((W + Bf - 1) / Bf) * ((H + Bf - 1) / Bf);
+        if ((int64_t)lp.bm_words * 32 < nbf)
+            for (int64_t i = tid; i < nbf; i += nt) J.stamp[i] = 0;
+    }
     if (GM == GM_FUSED)
         for (int64_t i = tid; i < K; i += nt) J.moved[i] = 0;
     for (int i = tid; i < lp.bm_words; i += nt) l_bm[i] = 0;
@@ -615,8 +646,6 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                 if (e) class_push(s_cnt, l_lists, capl, J.lists, capg, cls, (int32_t)i);
             }
         }
-        if (!use_bm)
-            for (int64_t i = tid; i < nb; i += nt) J.stamp[i] = 0;
         wg_sync();
 
         int sweeps = 0, converged = 0;
@@ -829,8 +858,12 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
             if (tid < 9) s_cnt[tid] = 0;
             wg_sync();
             // nine lanes per changed block, one per block of its 3x3
-            // neighbourhood; the first visitor of a block checks eligibility
-            const int32_t stamp = t + 1;
+            // neighbourhood; the first visitor of a block checks eligibility.
+            // First visits are found with the LDS bitmap when it covers the
+            // stage, else with an LDS hash set in the same words when the
+            // visits fit it at half load, else with the global stamps.
+            const int32_t stamp = s * (sc.max_sweeps + 1) + t + 1;
+            const bool use_hash = !use_bm && 9 * nchg <= ht_cap / 2;
             for (int q = tid; q < 9 * nchg; q += nt) {
                 int32_t bi = list_get(l_chg, capx, J.changed, 0, q / 9);
                 int d = q % 9;
@@ -841,6 +874,8 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                 if (use_bm) {
                     uint32_t bit = 1u << (ni & 31);
                     first = (atomicOr(&l_bm[ni >> 5], bit) & bit) == 0;
+                } else if (use_hash) {
+                    first = hash_insert(l_bm, ht_cap - 1, ni);
                 } else {
                     first = atomicExch(&J.stamp[ni], stamp) != stamp;
                 }
@@ -850,6 +885,8 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
             wg_sync();
             if (use_bm)
                 for (int i = tid; i < (int)((nb + 31) >> 5); i += nt) l_bm[i] = 0;
+            else if (use_hash)
+                for (int i = tid; i < ht_cap; i += nt) l_bm[i] = 0;
             if (tid == 0) s_nchg = 0;
             wg_sync();
         }
