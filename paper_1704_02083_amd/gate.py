@@ -97,3 +97,49 @@ def calibrate(ctx, rgbs, p: dict, w, target_br: float = 0.99, candidates=None):
         if r["br"] >= target_br:
             return th, r
     return None
+
+
+# ----------------------------------------------------- region of interest
+#
+# The paper's own prediction step: a classifier labels every superpixel ROI
+# or not at the gate point, and past it only pairs of superpixels of
+# different predicted classes refine (Eq. (7), rule "differ").  Here the
+# classifier is the same network trained on "most of the superpixel's pixels
+# lie in the region of interest" (on the synthetic H&E images: tissue, as
+# opposed to background).
+
+def roi_samples(ctx, rgb, roi, p: dict):
+    """Plain run to the gate point: features (K, 16) and ROI targets (K,)
+    uint8 (at least half of the superpixel's pixels in roi)."""
+    import torch
+    st = ctx.state(rgb, p)
+    K = st.K
+    moved = torch.zeros(K, dtype=torch.int64, device=rgb.device)
+    st.track(None, moved)
+    for l in range(p["gate_level"]):
+        st.refine_level(l, report=False)
+    X = st.features()
+    lab, _ = st.export()
+    st.close()
+    lab = lab.reshape(-1).long()
+    n = torch.bincount(lab, minlength=K)
+    inside = torch.bincount(lab[roi.reshape(-1)], minlength=K)
+    return X, (2 * inside >= n).to(torch.uint8)
+
+
+def roi_mask(labels, gate):
+    """Pixel ROI mask of a segmentation: the predicted class of each pixel's
+    superpixel."""
+    return gate[labels.long()].bool()
+
+
+def roi_scores(pred, truth) -> dict:
+    """Pixel precision, recall and F1 of a predicted ROI mask (Sec. 4's ROI
+    detection measures)."""
+    tp = int((pred & truth).sum().item())
+    fp = int((pred & ~truth).sum().item())
+    fn = int((~pred & truth).sum().item())
+    prec = tp / (tp + fp) if tp + fp else 1.0
+    rec = tp / (tp + fn) if tp + fn else 1.0
+    f1 = 2 * prec * rec / (prec + rec) if prec + rec else 0.0
+    return {"precision": prec, "recall": rec, "f1": f1}

@@ -176,3 +176,16 @@ def he_slide(W: int, H: int, seed: int = 4, background: float = 0.4, device="cud
         y1 = min(H, y0 + band)
         out[y0:y1] = he_band(W, y0, y1, seed, thresh, device)
     return out
+
+
+def tissue_mask(W: int, H: int, seed: int = 4, background: float = 0.4, device="cuda",
+                band: int = 1024) -> torch.Tensor:
+    """(H, W) bool: the pixels he_slide draws as tissue (not background) --
+    the ground truth of the region-of-interest task on these images."""
+    thresh = background_threshold(W, H, seed, background, device)
+    out = torch.empty((H, W), dtype=torch.bool, device=device)
+    xs = torch.arange(W, device=device)
+    for y0 in range(0, H, band):
+        y1 = min(H, y0 + band)
+        out[y0:y1] = _fbm(xs, torch.arange(y0, y1, device=device), 512, seed, 1) > thresh
+    return out

@@ -261,3 +261,31 @@ def test_learned_gate_beats_random_gate(ctx):
     _say("BR learned %.5f random %s none %.5f (marked %d of %d)" % (br_learned, brs_random, br_none, m, K))
     assert br_learned > max(brs_random)
     assert br_learned > br_none
+
+
+def test_roi_gate_matches_oracle_and_finds_tissue(ctx):
+    """The paper's prediction step: a classifier (the gate network trained
+    on "most pixels are tissue") labels superpixels at the second level and
+    only pairs across the predicted border refine (rule differ).  The gated
+    labels equal the oracle run with the same gate bits, and the ROI mask
+    (each pixel takes its superpixel's class) recovers the generator's
+    tissue mask."""
+    import torch
+    from paper_1704_02083_amd import gate, synth_gpu
+    p = params.default_params(512, 512, 256, levels=params.THREE_LEVEL, gate_level=1)
+    p["gate_rule"] = "differ"
+    Xs, ts = [], []
+    for i in range(4):
+        rgb = synth_gpu.he_slide(512, 512, seed=600 + i, background=0.4, device="cuda")
+        X, t = gate.roi_samples(ctx, rgb, synth_gpu.tissue_mask(512, 512, seed=600 + i, background=0.4), p)
+        Xs.append(X)
+        ts.append(t)
+    _, w = gate.train(ctx, torch.cat(Xs), torch.cat(ts), epochs=20, batch=512, seed=0)
+    rgb = synth_gpu.he_slide(512, 512, seed=699, background=0.4, device="cuda")
+    labs, _, _, g = ctx.segment_gated([rgb], p, w, 0.0, report=False)
+    _say("case: roi gate 512^2, ROI superpixels %d of %d" % (int(g.sum().item()), g.numel()))
+    ref, _, _ = oracle.segment(rgb.cpu().numpy(), p, gate=g.cpu().numpy())
+    assert (labs[0].cpu().numpy() == ref).all()
+    sc = gate.roi_scores(gate.roi_mask(labs[0], g), synth_gpu.tissue_mask(512, 512, seed=699, background=0.4))
+    _say("ROI %s" % sc)
+    assert sc["f1"] >= 0.9

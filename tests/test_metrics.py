@@ -44,3 +44,23 @@ def test_undersegmentation_of_a_merge():
     ref[:, 7:] = 1
     test = np.zeros((10, 10), np.int32)
     assert abs(metrics.undersegmentation_error(ref, test) - 2 * 30 / 100) < 1e-12
+
+
+def test_roi_scores_by_hand():
+    """Pixel precision/recall/F1 of a predicted ROI mask: 4 true positives,
+    2 false positives, 1 false negative."""
+    import torch
+    from paper_1704_02083_amd import gate
+    truth = torch.tensor([[1, 1, 1, 1, 1, 0, 0, 0]], dtype=torch.bool)
+    pred = torch.tensor([[1, 1, 1, 1, 0, 1, 1, 0]], dtype=torch.bool)
+    r = gate.roi_scores(pred, truth)
+    assert abs(r["precision"] - 4 / 6) < 1e-12 and abs(r["recall"] - 4 / 5) < 1e-12
+    assert abs(r["f1"] - 2 * (4 / 6) * (4 / 5) / (4 / 6 + 4 / 5)) < 1e-12
+
+
+def test_roi_mask_maps_superpixel_classes():
+    import torch
+    from paper_1704_02083_amd import gate
+    labels = torch.tensor([[0, 0, 1], [2, 1, 1]], dtype=torch.int32)
+    g = torch.tensor([1, 0, 1], dtype=torch.uint8)
+    assert gate.roi_mask(labels, g).tolist() == [[True, True, False], [True, False, False]]
