@@ -65,22 +65,36 @@ def workload(name: str):
     return imgs, p, desc
 
 
+PYRAMID_MIN_JOBS = 128   # from this many images or tiles the refinement kernel builds the pyramids
+
+
+def stage_alg_bytes(W, H, rep, pyramid: bool) -> int:
+    """Algorithmic bytes of the stages of one image or tile: with pyramid,
+    the block-sum pyramid (built inside the refinement kernel) reads the RGB
+    pixels once (3 B per pixel) and writes 8 B per block of every stage with
+    B >= 2; per stage the label map is written
+    once and read once by the boundary scan (8 B per block); every block
+    visit reads its 3x3 label window (36 B) and its colour sum (8 B packed,
+    3 B at B = 1); every commit writes a label (4 B) and reads the sum
+    again.  Per-superpixel statistics count zero (on chip, or a small set)."""
+    total = 3 * W * H if pyramid else 0
+    for r in rep:
+        B = r["block"]
+        nb = -(-W // B) * -(-H // B)
+        sb = 3 if B == 1 else 8
+        total += 8 * nb + r["active"] * (36 + sb) + r["commits"] * (4 + sb)
+        if B >= 2 and pyramid:
+            total += 8 * nb
+    return total
+
+
 def refine_alg_bytes(imgs, reports) -> float:
-    """Algorithmic bytes of one refinement launch: per stage the label map is
-    written once and read once by the boundary scan (8 B per block); every
-    block visit reads its 3x3 label window (36 B) and its colour sum (8 B
-    packed, 3 B at B = 1); every commit writes a label (4 B) and reads the
-    sum again; the final pixel labels are written once (4 B per pixel).
-    Per-superpixel statistics stay on chip (LDS) and count zero."""
+    """Algorithmic bytes of one refinement launch over whole images: the
+    stages' bytes plus the final pixel labels written once (4 B per pixel)."""
     total = 0
     for img, rep in zip(imgs, reports):
         H, W = img.shape[:2]
-        total += 4 * W * H
-        for r in rep:
-            B = r["block"]
-            nb = -(-W // B) * -(-H // B)
-            sb = 3 if B == 1 else 8
-            total += 8 * nb + r["active"] * (36 + sb) + r["commits"] * (4 + sb)
+        total += 4 * W * H + stage_alg_bytes(W, H, rep, len(imgs) >= PYRAMID_MIN_JOBS)
     return float(total)
 
 
@@ -91,24 +105,7 @@ def tiles_alg_bytes(W, H, tiles, reports) -> float:
     total = 4 * W * H
     for t, rep in zip(tiles, reports):
         x0, y0, x1, y1 = t["ext"]
-        w, h = x1 - x0, y1 - y0
-        for r in rep:
-            B = r["block"]
-            nb = -(-w // B) * -(-h // B)
-            sb = 3 if B == 1 else 8
-            total += 8 * nb + r["active"] * (36 + sb) + r["commits"] * (4 + sb)
-    return float(total)
-
-
-def block_sums_alg_bytes(imgs, p) -> float:
-    total = 0
-    for img in imgs:
-        H, W = img.shape[:2]
-        for f, st in p["levels"]:
-            for b in st:
-                B = b * f
-                if B >= 2:
-                    total += 3 * W * H + 8 * (-(-W // B) * -(-H // B))
+        total += stage_alg_bytes(x1 - x0, y1 - y0, rep, len(tiles) >= PYRAMID_MIN_JOBS)
     return float(total)
 
 
@@ -210,16 +207,19 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    refine_ms, sums_ms = [], []
+    # the timed steps run back to back (launches queue while the GPU works)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
-        t = ctx.last_timings()
-        refine_ms.append(t["refine_ms"])
-        sums_ms.append(t["block_sums_ms"])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     print("bench: timed %d steps in %.3f s" % (args.steps, dt), file=sys.stderr, flush=True)
+    # kernel durations (HIP events on the library's stream) from the same
+    # steps once more: reading them waits for each step
+    refine_ms = []
+    for _ in range(args.steps):
+        step()
+        refine_ms.append(ctx.last_timings()["refine_ms"])
 
     # counters of the same (deterministic) work, from one untimed call
     if len(rgbs) == 1:
@@ -258,7 +258,6 @@ def main():
             "traffic": traffic,
             "alg_bytes_per_launch": alg,
             "avg_launch_ms": round(avg_refine, 4),
-            "block_sums_ms": round(sum(sums_ms) / len(sums_ms), 4),
             "source_hash": src_hash,
         },
     }
@@ -466,13 +465,16 @@ def bench_he(args):
         for _ in range(warm):
             fn()
         torch.cuda.synchronize()
-        ref_ms = []
         t0 = time.perf_counter()
         for _ in range(steps):
             fn()
-            ref_ms.append(ctx.last_timings()["refine_ms"])
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps, ref_ms
+        dt = (time.perf_counter() - t0) / steps
+        ref_ms = []
+        for _ in range(steps):
+            fn()
+            ref_ms.append(ctx.last_timings()["refine_ms"])
+        return dt, ref_ms
 
     steps, warm = max(1, min(args.steps, 5)), max(0, min(args.warmup, 2))
     dt, ref_ms = timed(lambda: run(), steps, warm)

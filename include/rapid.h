@@ -69,7 +69,9 @@ typedef struct {
 /* Kernel durations of the last segmentation call (context created with
  * RAPID_CFG_TIMING), measured with HIP events on the context's stream. */
 typedef struct {
-    float block_sums_ms;   /* block-sum pyramid kernels            */
+    float block_sums_ms;   /* block-sum launches before the refinement
+                              kernel (0 when that kernel builds the
+                              pyramids itself: 128 jobs or more)      */
     float refine_ms;       /* the refinement kernel (all stages)   */
 } rapid_timings;
 

@@ -369,7 +369,7 @@ LdsPlan plan_lds(size_t limit, int32_t Kmax, int64_t nbF, bool gated)
 }
 
 rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched &sc, int s_begin,
-                      int s_end, int flags, int32_t Kmax, int64_t nbF_max, int64_t max_nb[MAXST])
+                      int s_end, int flags, int32_t Kmax, int64_t nbF_max)
 {
     size_t n = jobs.size();
     if (n > ctx->jobs_cap) {
@@ -394,9 +394,18 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
     HIPCHK(hipEventRecord(ctx->jobs_copied, ctx->stream));
     if (ctx->timing) HIPCHK(hipEventRecord(ctx->ev[0], ctx->stream));
     if (flags & FLAG_INIT) {
-        for (int s = 0; s < sc.n_stages; s++)
-            if (sc.B[s] >= 2)
-                HIPCHK(launch_block_sums(ctx->jobs_dev, (int)n, s, sc.B[s], max_nb[s], ctx->stream));
+        if ((int)n >= PYRAMID_MIN_JOBS) {
+            flags |= FLAG_PYRAMID;   // enough workgroups to fill the chip
+        } else {
+            // few jobs: chip-wide launches, one per stage with B >= 2
+            for (int s = 0; s < sc.n_stages; s++) {
+                const int B = sc.B[s];
+                if (B < 2) continue;
+                int64_t nb = 0;
+                for (const Job &J : jobs) nb = std::max<int64_t>(nb, (int64_t)((J.W + B - 1) / B) * ((J.H + B - 1) / B));
+                HIPCHK(launch_block_sums(ctx->jobs_dev, (int)n, s, B, nb, ctx->stream));
+            }
+        }
     }
     // the gate bits live in LDS during the gated stages
     bool gated = (flags & FLAG_GATE) != 0;
@@ -694,7 +703,7 @@ static rapid_status segment_impl(rapid_ctx *ctx, const rapid_image *imgs, int32_
     Batch b;
     rapid_status r = prepare_batch(ctx, imgs, n, params, gate_dev, false, b, tiles);
     if (r) return r;
-    if ((r = run_jobs(ctx, b.jobs, b.sc, 0, b.sc.n_stages, FLAG_INIT | FLAG_OUT, b.Kmax, b.nbF_max, b.max_nb)))
+    if ((r = run_jobs(ctx, b.jobs, b.sc, 0, b.sc.n_stages, FLAG_INIT | FLAG_OUT, b.Kmax, b.nbF_max)))
         return r;
     if (reports) return fetch_reports(ctx, b.jobs, b.sc, 0, b.sc.n_stages, reports);
     return RAPID_OK;
@@ -732,8 +741,7 @@ static rapid_status gated_impl(rapid_ctx *ctx, const rapid_image *imgs, int32_t 
     // then the finer levels under the gate (Eq. (7))
     b.sc.mlp_w = model->w_bf16_dev;
     b.sc.mlp_thresh = model->thresh;
-    if ((r = run_jobs(ctx, b.jobs, b.sc, 0, b.sc.n_stages, FLAG_INIT | FLAG_OUT | FLAG_GATE, b.Kmax, b.nbF_max,
-                      b.max_nb)))
+    if ((r = run_jobs(ctx, b.jobs, b.sc, 0, b.sc.n_stages, FLAG_INIT | FLAG_OUT | FLAG_GATE, b.Kmax, b.nbF_max)))
         return r;
     if (features_dev)
         HIPCHK(hipMemcpyAsync(features_dev, b.X, 4 * 16 * (size_t)b.Ktot, hipMemcpyDeviceToDevice, ctx->stream));
@@ -846,13 +854,12 @@ rapid_status rapid_state_create(rapid_ctx *ctx, const rapid_image *img, const ra
     im.label_stride = img->W;
     fill_job(st->job, st->mem, L, &im, gx, gy, nullptr);
     std::vector<Job> jobs(1, st->job);
-    int64_t max_nb[MAXST] = {};
-    for (int s = 0; s < st->sc.n_stages; s++)
-        max_nb[s] = (int64_t)((img->W + st->sc.B[s] - 1) / st->sc.B[s]) * ((img->H + st->sc.B[s] - 1) / st->sc.B[s]);
-    // grid labels and statistics, no stage yet
+    const int Bf = st->sc.B[st->sc.n_stages - 1];
+    const int64_t nbF = (int64_t)((img->W + Bf - 1) / Bf) * ((img->H + Bf - 1) / Bf);
+    // block-sum pyramid, grid labels and statistics, no stage yet
     Sched sc = st->sc;
     sc.gate_stage = sc.n_stages;
-    r = run_jobs(ctx, jobs, sc, 0, 0, FLAG_INIT, gx * gy, max_nb[st->sc.n_stages - 1], max_nb);
+    r = run_jobs(ctx, jobs, sc, 0, 0, FLAG_INIT, gx * gy, nbF);
     if (r == RAPID_OK) r = dev_err(hipStreamSynchronize(ctx->stream));
     if (r) {
         (void)hipFree(st->mem);
@@ -879,10 +886,9 @@ rapid_status rapid_refine_level(rapid_ctx *ctx, rapid_state *st, int32_t level, 
     sc.gate_stage = gate_dev ? s0 : sc.n_stages;
     st->job.gate = gate_dev;
     std::vector<Job> jobs(1, st->job);
-    int64_t max_nb[MAXST] = {};
     int Bf = sc.B[sc.n_stages - 1];
     int64_t nbF = (int64_t)((st->W + Bf - 1) / Bf) * ((st->H + Bf - 1) / Bf);
-    rapid_status r = run_jobs(ctx, jobs, sc, s0, s1, 0, st->job.K, nbF, max_nb);
+    rapid_status r = run_jobs(ctx, jobs, sc, s0, s1, 0, st->job.K, nbF);
     if (r) return r;
     st->next_level = level + 1;
     st->map_stage = s1 - 1;

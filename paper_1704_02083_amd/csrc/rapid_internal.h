@@ -14,8 +14,13 @@ constexpr int MAX_GATE_WORDS = 8192;
 
 // FLAG_INIT: grid labels and statistics first; FLAG_OUT: write the pixel
 // labels; FLAG_GATE: evaluate the gate in place at the first gated stage
-// (features, network, gate bits) and track moved pixels before it.
-enum { FLAG_INIT = 1, FLAG_OUT = 2, FLAG_GATE = 4 };
+// (features, network, gate bits) and track moved pixels before it;
+// FLAG_PYRAMID: with FLAG_INIT, each workgroup builds its job's block-sum
+// pyramid (else separate launches have).
+enum { FLAG_INIT = 1, FLAG_OUT = 2, FLAG_GATE = 4, FLAG_PYRAMID = 8 };
+
+// jobs from which the refinement launch builds the block-sum pyramids itself
+constexpr int PYRAMID_MIN_JOBS = 128;
 
 // The schedule, flattened: effective block size of every stage.
 struct Sched {
@@ -84,7 +89,7 @@ struct Job {
     float *xrow;
     uint8_t *gate_out;
     // per-block pixel second moments (3 x uint32 per block) of stage
-    // moms_stage, written by the block-sum pass for the gate's features
+    // moms_stage, written with the block-sum pyramid for the gate's features
     uint32_t *moms;
     int32_t moms_stage, pad4;
     // slide tiles: only the core [core_x0, +core_w) x [core_y0, +core_h) of
@@ -94,8 +99,7 @@ struct Job {
     int64_t gid_x0, gid_y0, gid_w;
 };
 
-hipError_t launch_block_sums(const Job *jobs_dev, int n_jobs, int s, int B, int64_t max_nb,
-                             hipStream_t stream);
+hipError_t launch_block_sums(const Job *jobs_dev, int n_jobs, int s, int B, int64_t max_nb, hipStream_t stream);
 hipError_t launch_expand(const int32_t *L, int W, int H, int B, int32_t *out, int64_t stride,
                          hipStream_t stream);
 hipError_t launch_refine(const Job *jobs_dev, int n_jobs, const Sched &sc, const LdsPlan &lp,

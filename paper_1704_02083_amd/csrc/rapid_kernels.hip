@@ -220,21 +220,20 @@ __device__ __forceinline__ void wg_sync()
     __syncthreads();
 }
 
-// --------------------------------------------------------------- k_sums
-// Packed per-block RGB sums (21 bits per channel) for a stage of block size
-// B; for the stage the gate's features read (J.moms_stage) also the pixel
-// second moments per channel (at most 64^2 * 255^2 < 2^32).
-template <bool MOMS>
-__device__ __forceinline__ void block_sums_of(const Job &J, int s, int B)
+// ------------------------------------------------------- block-sum pyramid
+// Packed per-block RGB sums (21 bits per channel; B <= 64 keeps every
+// channel below 2^21) of one stage of block size B straight from the
+// pixels, by the whole workgroup; with MOMS also the pixel second moments
+// per channel (at most 64^2 * 255^2 < 2^32) that the gate's features read.
+template <bool SUMS, bool MOMS>
+__device__ __forceinline__ void sums_from_pixels(const Job &J, int s, int B, int tid, int nt)
 {
-    int nbx = (J.W + B - 1) / B, nby = (J.H + B - 1) / B;
-    int64_t nb = (int64_t)nbx * nby;
-    uint64_t *out = J.sums[s];
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nb;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        int bx = (int)(i % nbx), by = (int)(i / nbx);
-        int x0 = bx * B, y0 = by * B;
-        int x1 = min(x0 + B, J.W), y1 = min(y0 + B, J.H);
+    const int nbx = (J.W + B - 1) / B, nby = (J.H + B - 1) / B;
+    const int64_t nb = (int64_t)nbx * nby;
+    for (int64_t i = tid; i < nb; i += nt) {
+        const int bx = (int)(i % nbx), by = (int)(i / nbx);
+        const int x0 = bx * B, y0 = by * B;
+        const int x1 = min(x0 + B, J.W), y1 = min(y0 + B, J.H);
         uint32_t r = 0, g = 0, b = 0, qr = 0, qg = 0, qb = 0;
         for (int y = y0; y < y1; y++) {
             const uint8_t *row = J.rgb + (int64_t)y * J.rgb_stride + 3 * (int64_t)x0;
@@ -250,7 +249,7 @@ __device__ __forceinline__ void block_sums_of(const Job &J, int s, int B)
                 }
             }
         }
-        out[i] = (uint64_t)r | ((uint64_t)g << 21) | ((uint64_t)b << 42);
+        if (SUMS) J.sums[s][i] = (uint64_t)r | ((uint64_t)g << 21) | ((uint64_t)b << 42);
         if (MOMS) {
             J.moms[3 * i] = qr;
             J.moms[3 * i + 1] = qg;
@@ -259,11 +258,49 @@ __device__ __forceinline__ void block_sums_of(const Job &J, int s, int B)
     }
 }
 
+// Block sums of stage s for every job by a separate launch (grid-stride
+// over blockIdx.x, one job per blockIdx.y): used when the jobs are too few
+// to fill the chip with the refinement kernel's workgroups.
 __global__ void k_block_sums(const Job *__restrict__ jobs, int s, int B)
 {
     const Job &J = jobs[blockIdx.y];
-    if (J.moms && s == J.moms_stage) block_sums_of<true>(J, s, B);
-    else block_sums_of<false>(J, s, B);
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
+    if (J.moms && s == J.moms_stage) sums_from_pixels<true, true>(J, s, B, tid, nt);
+    else sums_from_pixels<true, false>(J, s, B, tid, nt);
+}
+
+// The pyramid of the schedule (Sec. 3.2's levels as exact box sums) for
+// every stage with B >= 2: the finest such stage from the pixels, each
+// coarser one as the sum of its children in the next finer stage (block
+// sizes divide each other; packed fields add without carries).  Ends with a
+// workgroup barrier.
+__device__ void build_pyramid(const Job &J, const Sched &sc, int tid, int nt)
+{
+    int sf = -1;
+    for (int s = 0; s < sc.n_stages; s++)
+        if (sc.B[s] >= 2) sf = s;
+    if (sf >= 0) {
+        if (J.moms && J.moms_stage == sf) sums_from_pixels<true, true>(J, sf, sc.B[sf], tid, nt);
+        else sums_from_pixels<true, false>(J, sf, sc.B[sf], tid, nt);
+        for (int s = sf - 1; s >= 0; s--) {
+            __syncthreads();
+            const int B = sc.B[s], Bc = sc.B[s + 1], r = B / Bc;
+            const int nbx = (J.W + B - 1) / B, nby = (J.H + B - 1) / B;
+            const int nbxc = (J.W + Bc - 1) / Bc, nbyc = (J.H + Bc - 1) / Bc;
+            const uint64_t *child = J.sums[s + 1];
+            for (int64_t i = tid; i < (int64_t)nbx * nby; i += nt) {
+                const int bx = (int)(i % nbx), by = (int)(i / nbx);
+                const int cx1 = min((bx + 1) * r, nbxc), cy1 = min((by + 1) * r, nbyc);
+                uint64_t acc = 0;
+                for (int cy = by * r; cy < cy1; cy++)
+                    for (int cx = bx * r; cx < cx1; cx++) acc += child[(int64_t)cy * nbxc + cx];
+                J.sums[s][i] = acc;
+            }
+        }
+        if (J.moms && J.moms_stage >= 0 && J.moms_stage < sf)
+            sums_from_pixels<false, true>(J, J.moms_stage, sc.B[J.moms_stage], tid, nt);
+    }
+    __syncthreads();
 }
 
 // ------------------------------------------------------------- k_expand
@@ -526,10 +563,12 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
     for (int i = tid; i < lp.bm_words; i += nt) l_bm[i] = 0;
 
     if (flags & FLAG_INIT) {
-        // grid initialisation (Algorithm RAPID, first step) and the
-        // statistics, computed once for all levels (Sec. 3.2)
+        // the block-sum pyramid, grid initialisation (Algorithm RAPID,
+        // first step) and the statistics, computed once for all levels
+        // (Sec. 3.2)
         for (int64_t i = tid; i < 6 * (int64_t)K; i += nt) st[i] = 0;
-        wg_sync();
+        if (flags & FLAG_PYRAMID) build_pyramid(J, sc, tid, nt);
+        else wg_sync();
         const int B0 = sc.B[0];
         const int nbx = (W + B0 - 1) / B0, nby = (H + B0 - 1) / B0;
         int32_t *L = J.lab[0];
@@ -938,14 +977,13 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
 
 // ------------------------------------------------------------ launchers
 
-hipError_t launch_block_sums(const Job *jobs_dev, int n_jobs, int s, int B, int64_t max_nb,
-                             hipStream_t stream)
+hipError_t launch_block_sums(const Job *jobs_dev, int n_jobs, int s, int B, int64_t max_nb, hipStream_t stream)
 {
     int64_t blocks = (max_nb + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_block_sums, dim3((unsigned)blocks, (unsigned)n_jobs), dim3(256), 0, stream,
-                       jobs_dev, s, B);
+    hipLaunchKernelGGL(k_block_sums, dim3((unsigned)blocks, (unsigned)n_jobs), dim3(256), 0, stream, jobs_dev, s,
+                       B);
     return hipGetLastError();
 }
 

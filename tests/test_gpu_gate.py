@@ -289,3 +289,34 @@ def test_roi_gate_matches_oracle_and_finds_tissue(ctx):
     sc = gate.roi_scores(gate.roi_mask(labs[0], g), synth_gpu.tissue_mask(512, 512, seed=699, background=0.4))
     _say("ROI %s" % sc)
     assert sc["f1"] >= 0.9
+
+
+def test_gated_batch_of_128_matches_oracle(ctx):
+    """128 images in one gated launch: the refinement kernel builds the
+    block-sum pyramids (and the gate's second moments) itself from this many
+    jobs.  Every image's labels equal the oracle run with the GPU's gate
+    bits, and the features of a sample of images equal the oracle's."""
+    import torch
+    imgs = [synth.he_tile(160, 128, seed=700 + i) for i in range(128)]
+    p = params.default_params(160, 128, 20, levels=params.THREE_LEVEL, gate_level=1)
+    gx, gy = oracle.grid(160, 128, 20)
+    K = gx * gy
+    theta, wb = _rand_model(31)
+    _say("case: gated batch of 128 images 160x128")
+    labs, _, X, g = ctx.segment_gated([_dev(im) for im in imgs], p, _dev(wb), 0.0, features=True,
+                                      report=False)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    X = X.cpu().numpy()
+    assert 0 < g.sum() < len(g)
+    bad = []
+    for i, im in enumerate(imgs):
+        ref, _, _ = oracle.segment(im, p, gate=g[i * K:(i + 1) * K])
+        if not (labs[i].cpu().numpy() == ref).all():
+            bad.append(i)
+    assert not bad, "images differ: %s" % bad[:10]
+    p0 = dict(p, levels=p["levels"][:1], gate_level=-1)
+    for i in (0, 63, 127):
+        lab0, s0, _, _, mov0 = oracle.segment(imgs[i], p0, track=True)
+        Xo = oracle.features(imgs[i], lab0, 16, s0, mov0, gx, gy)
+        assert np.abs(X[i * K:(i + 1) * K] - Xo).max() <= 1e-6
