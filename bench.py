@@ -296,34 +296,46 @@ def bench_gated(args, ctx, rgb, labels, plain, W, H, dt_plain):
     from 'nothing refined past the gate point' to 'everything', and the one
     calibrated on held-out tiles for boundary recall >= 0.99."""
     import torch
-    from paper_1704_02083_amd import gate, metrics, params, synth_gpu
+    from paper_1704_02083_amd import gate, metrics, params, rapid, synth_gpu
     w, info = train_gate(ctx, args.gate_rule, args.train_tiles)
     print("bench: gate trained (%s)" % info, file=sys.stderr, flush=True)
     if args.workload in ("slide", "slide65k"):
         pg = params.gated(2048, 2048, 4096, rule=args.gate_rule)
+        lay = rapid.tile_layout(W, H, 2048, 64, 32)
 
-        def run(th):
-            ctx.segment_slide(rgb, pg, tile=2048, halo=64, cell=32, labels=labels, w_bf16=w, thresh=th)
+        def run(th, report=False):
+            _, reps = ctx.segment_slide(rgb, pg, tile=2048, halo=64, cell=32, labels=labels, w_bf16=w, thresh=th,
+                                        report=report)
+            return tiles_alg_bytes(W, H, lay, reps) if report else None
     else:
         pg = params.gated(W, H, 16384, rule=args.gate_rule)
 
-        def run(th):
-            ctx.segment_gated([rgb], pg, w, th, labels=[labels], report=False)
+        def run(th, report=False):
+            _, reps, _, _ = ctx.segment_gated([rgb], pg, w, th, labels=[labels], report=report)
+            return refine_alg_bytes([rgb], reps) if report else None
     hold = [synth_gpu.he_slide(2048, 2048, seed=7100 + i, background=0.4, device="cuda") for i in range(4)]
     crops = [(0, 0)] if args.workload == "he4096" else [(1000, 3000), (9000, 17000), (20000, 7000), (28000, 28000)]
 
     def point(th):
-        run(th)
+        alg = run(th, report=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(3):
             run(th)
         torch.cuda.synchronize()
         dtg = (time.perf_counter() - t0) / 3
+        kms = []
+        for _ in range(3):
+            run(th)
+            kms.append(ctx.last_timings()["refine_ms"])
+        achieved = alg / (sum(kms) / len(kms) * 1e-3) / 1e9
         ue = [metrics.undersegmentation_error(plain[y:y + 4096, x:x + 4096].cpu().numpy(),
                                               labels[y:y + 4096, x:x + 4096].cpu().numpy()) for y, x in crops]
         return {"thresh": th, "MPixel/s": round(W * H / dtg / 1e6, 3), "ms": round(dtg * 1e3, 3),
-                "speedup": round(dt_plain / dtg, 4), "br": round(gate.boundary_recall(ctx, plain, labels), 6),
+                "speedup": round(dt_plain / dtg, 4),
+                "k_refine_ms": round(sum(kms) / len(kms), 3), "alg_bytes_per_launch": alg,
+                "achieved_GBps": round(achieved, 3), "hbm_frac": round(achieved / HBM_PEAK_GBS, 6),
+                "br": round(gate.boundary_recall(ctx, plain, labels), 6),
                 "disagreement": round(float((plain != labels).float().mean().item()), 6),
                 "ue": round(float(sum(ue) / len(ue)), 6)}
 
