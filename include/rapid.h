@@ -176,6 +176,21 @@ rapid_status rapid_state_export(rapid_ctx *ctx, rapid_state *st, int32_t *labels
                                 int64_t *stats_dev);
 void rapid_state_destroy(rapid_state *st);   /* NULL-safe */
 
+/* Checkpoint resume: restore into st (created with the same image and
+ * params) the point after next_level levels (0 .. n_levels) of Algorithm
+ * RAPID.  labels_dev: W*H int32 pixel labels (row-major, stride W), as
+ * rapid_state_export wrote them at that point; they must be constant on
+ * every block of that point's block size (the last stage of level
+ * next_level - 1, the first stage when next_level is 0) and lie in
+ * [0, gx*gy).  stats_dev: gx*gy*6 int64 statistics as exported, or NULL to
+ * recompute them exactly from the image and labels (Sec. 3.2 sums).  The
+ * next rapid_refine_level call then takes level next_level.  Moved-pixel
+ * tracking is not part of a checkpoint.  Labels that break the block or
+ * range rule give RAPID_EINVAL and leave st unusable (RAPID_ESTATE) until a
+ * later import succeeds.  Synchronous. */
+rapid_status rapid_state_import(rapid_ctx *ctx, rapid_state *st, int32_t next_level, const int32_t *labels_dev,
+                                const int64_t *stats_dev);
+
 /* Waits for the last segmentation call and returns its kernel durations;
  * RAPID_ESTATE when the context does not time or nothing ran yet. */
 rapid_status rapid_last_timings(rapid_ctx *ctx, rapid_timings *out);
@@ -223,6 +238,18 @@ rapid_status rapid_state_track(rapid_state *st, uint8_t *involved_dev, int64_t *
  * (X_dev: gx*gy rows of 16 float32).  Feature 13 uses the moved counts
  * tracked so far (zero when not tracked). */
 rapid_status rapid_state_features(rapid_ctx *ctx, rapid_state *st, float *X_dev);
+
+/* The prediction step of Algorithm RAPID on a level-by-level state
+ * (Eq. (6)): the features of its superpixels at the current stage as in
+ * rapid_state_features, then gate_dev[k] = [h(x_k) >= model->thresh]
+ * (gx*gy bytes), to pass to the following rapid_refine_level calls
+ * (Eq. (7)).  features_dev (nullable): the gx*gy feature rows.  With
+ * rapid_state_track's moved counts on from the first level, the bits equal
+ * those rapid_segment_gated decides for the same image.  A model with
+ * non-finite weights is refused: every byte of gate_dev is set to 1 (refine
+ * all) and RAPID_EGATE is returned. */
+rapid_status rapid_gate(rapid_ctx *ctx, rapid_state *st, const rapid_gate_model *model, float *features_dev,
+                        uint8_t *gate_dev);
 
 /* Misses of the boundary recall (Sec. 4.2) of test against ref, two W x H
  * int32 label maps on the device with the same row stride (in elements):

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "rapid_internal.h"
+#include "rapid_state_kernels.h"
 
 using namespace rapid;
 
@@ -40,10 +41,13 @@ struct rapid_state {
     Job job{};
     Job *job_dev = nullptr;
     int64_t *zero_dev = nullptr;   // a device 0 (row offset of the state's features)
+    uint32_t *err_dev = nullptr;   // import: violation flag
+    float *xbuf = nullptr;         // rapid_gate: feature rows when the caller passes none
     char *mem = nullptr;
     Sched sc{};
     int32_t level_first[RAPID_MAX_LEVELS + 1] = {};
-    int32_t next_level = 0;
+    int32_t n_levels = 0;
+    int32_t next_level = 0;  // -1: a failed import left the labels undefined
     int32_t map_stage = 0;   // stage whose block size the current label map uses
     int32_t W = 0, H = 0;
 };
@@ -867,6 +871,7 @@ rapid_status rapid_state_create(rapid_ctx *ctx, const rapid_image *img, const ra
         delete st;
         return r;
     }
+    st->n_levels = params->n_levels;
     st->next_level = 0;
     st->map_stage = 0;
     *out = st;
@@ -899,6 +904,7 @@ rapid_status rapid_refine_level(rapid_ctx *ctx, rapid_state *st, int32_t level, 
 rapid_status rapid_state_export(rapid_ctx *ctx, rapid_state *st, int32_t *labels_dev, int64_t *stats_dev)
 {
     if (!ctx || !st || st->ctx != ctx) return RAPID_EINVAL;
+    if (st->next_level < 0) return RAPID_ESTATE;
     std::lock_guard<std::mutex> lock(ctx->mu);
     if (hipSetDevice(ctx->device) != hipSuccess) return RAPID_EDEVICE;
     if (labels_dev) {
@@ -922,6 +928,8 @@ void rapid_state_destroy(rapid_state *st)
     (void)hipFree(st->mem);
     (void)hipFree(st->job_dev);
     (void)hipFree(st->zero_dev);
+    (void)hipFree(st->err_dev);
+    (void)hipFree(st->xbuf);
     delete st;
 }
 
@@ -937,6 +945,7 @@ rapid_status rapid_state_track(rapid_state *st, uint8_t *involved_dev, int64_t *
 rapid_status rapid_state_features(rapid_ctx *ctx, rapid_state *st, float *X_dev)
 {
     if (!ctx || !st || st->ctx != ctx || !X_dev) return RAPID_EINVAL;
+    if (st->next_level < 0) return RAPID_ESTATE;
     std::lock_guard<std::mutex> lock(ctx->mu);
     if (hipSetDevice(ctx->device) != hipSuccess) return RAPID_EDEVICE;
     if (!st->zero_dev) {
@@ -949,6 +958,67 @@ rapid_status rapid_state_features(rapid_ctx *ctx, rapid_state *st, float *X_dev)
     HIPCHK(launch_features(st->job_dev, 1, B, s & 1, st->sc.F, st->job.K, nb, st->zero_dev, X_dev, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return RAPID_OK;
+}
+
+rapid_status rapid_state_import(rapid_ctx *ctx, rapid_state *st, int32_t next_level, const int32_t *labels_dev,
+                                const int64_t *stats_dev)
+{
+    if (!ctx || !st || st->ctx != ctx || !labels_dev || next_level < 0 || next_level > st->n_levels)
+        return RAPID_EINVAL;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return RAPID_EDEVICE;
+    if (!st->err_dev && hipMalloc(&st->err_dev, 4) != hipSuccess) return RAPID_ENOMEM;
+    // the label map of a state that has refined next_level levels: the last
+    // stage's block size (the first stage's before any level)
+    const int s = next_level == 0 ? 0 : st->level_first[next_level] - 1;
+    const int B = st->sc.B[s];
+    int32_t *L = st->job.lab[s & 1];
+    HIPCHK(hipMemsetAsync(st->err_dev, 0, 4, ctx->stream));
+    HIPCHK(launch_import_labels(labels_dev, st->W, st->W, st->H, B, st->job.K, L, st->err_dev, ctx->stream));
+    if (stats_dev) {
+        HIPCHK(hipMemcpyAsync(st->job.stats, stats_dev, sizeof(int64_t) * 6 * st->job.K, hipMemcpyDeviceToDevice,
+                              ctx->stream));
+    } else {
+        HIPCHK(hipMemsetAsync(st->job.stats, 0, sizeof(int64_t) * 6 * st->job.K, ctx->stream));
+        HIPCHK(launch_import_stats(st->job.rgb, st->job.rgb_stride, st->W, st->H, B, L, st->job.stats,
+                                   ctx->stream));
+    }
+    uint32_t err = 0;
+    HIPCHK(hipMemcpyAsync(&err, st->err_dev, 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (err) {
+        st->next_level = -1;
+        return RAPID_EINVAL;
+    }
+    st->next_level = next_level;
+    st->map_stage = s;
+    return RAPID_OK;
+}
+
+rapid_status rapid_gate(rapid_ctx *ctx, rapid_state *st, const rapid_gate_model *model, float *features_dev,
+                        uint8_t *gate_dev)
+{
+    if (!ctx || !st || st->ctx != ctx || !model || !model->w_bf16_dev || !gate_dev) return RAPID_EINVAL;
+    if (st->next_level < 0) return RAPID_ESTATE;
+    const int64_t K = st->job.K;
+    if (!model_finite(model->w_bf16_dev, ctx->stream)) {
+        // refuse the model: every superpixel stays marked (refine all)
+        std::lock_guard<std::mutex> lock(ctx->mu);
+        if (hipSetDevice(ctx->device) != hipSuccess) return RAPID_EDEVICE;
+        HIPCHK(hipMemsetAsync(gate_dev, 1, (size_t)K, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        return RAPID_EGATE;
+    }
+    float *X = features_dev;
+    if (!X) {
+        std::lock_guard<std::mutex> lock(ctx->mu);
+        if (hipSetDevice(ctx->device) != hipSuccess) return RAPID_EDEVICE;
+        if (!st->xbuf && hipMalloc(&st->xbuf, sizeof(float) * 16 * (size_t)K) != hipSuccess) return RAPID_ENOMEM;
+        X = st->xbuf;
+    }
+    rapid_status r = rapid_state_features(ctx, st, X);
+    if (r) return r;
+    return rapid_mlp_forward(ctx, X, K, model->w_bf16_dev, model->thresh, nullptr, gate_dev);
 }
 
 rapid_status rapid_boundary_miss(rapid_ctx *ctx, const int32_t *ref_dev, const int32_t *test_dev, int32_t W,

@@ -121,6 +121,8 @@ _lib.rapid_segment_gated.argtypes = [_P, C.POINTER(Image), C.c_int32, C.POINTER(
                                      C.POINTER(GateModel), _P, _P, C.POINTER(Report)]
 _lib.rapid_state_track.argtypes = [_P, _P, _P]
 _lib.rapid_state_features.argtypes = [_P, _P, _P]
+_lib.rapid_state_import.argtypes = [_P, _P, C.c_int32, _P, _P]
+_lib.rapid_gate.argtypes = [_P, _P, C.POINTER(GateModel), _P, _P]
 _lib.rapid_boundary_miss.argtypes = [_P, _P, _P, C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_int32,
                                      _P, _P]
 _lib.rapid_mlp_forward.argtypes = [_P, _P, C.c_int64, _P, C.c_float, _P, _P]
@@ -135,7 +137,8 @@ EXPORTED = ["rapid_init", "rapid_destroy", "rapid_segment", "rapid_segment_batch
             "rapid_state_destroy", "rapid_grid", "rapid_status_str", "rapid_simple_lut",
             "rapid_check_params", "rapid_last_timings", "rapid_segment_gated",
             "rapid_state_track", "rapid_state_features", "rapid_mlp_forward", "rapid_mlp_grad",
-            "rapid_gate_train", "rapid_slide_tiles", "rapid_segment_slide", "rapid_boundary_miss"]
+            "rapid_gate_train", "rapid_slide_tiles", "rapid_segment_slide", "rapid_boundary_miss",
+            "rapid_state_import", "rapid_gate"]
 
 
 def _check(rc: int, where: str):
@@ -384,7 +387,8 @@ class Context:
 
 
 class State:
-    """rapid_state_create / rapid_refine_level / rapid_state_export."""
+    """rapid_state_create / rapid_refine_level / rapid_gate / rapid_state_export /
+    rapid_state_import."""
 
     def __init__(self, ctx: Context, rgb, params: dict):
         self.ctx = ctx
@@ -417,6 +421,33 @@ class State:
         _check(_lib.rapid_state_features(self.ctx._h, self._h, C.c_void_p(X.data_ptr())),
                "rapid_state_features")
         return X
+
+    def gate(self, w_bf16, thresh: float = 0.0, features: bool = False, out=None):
+        """rapid_gate: (gate bytes (K,), features (K, 16) or None); out: an
+        optional (K,) uint8 tensor for the gate bytes."""
+        import torch
+        g = torch.empty(self.K, dtype=torch.uint8, device=self.rgb.device) if out is None else out
+        assert g.is_cuda and g.dtype == torch.uint8 and g.numel() == self.K and g.is_contiguous()
+        X = torch.empty((self.K, N_FEATURES), dtype=torch.float32, device=self.rgb.device) if features else None
+        model = GateModel(w_bf16.data_ptr(), thresh)
+        _check(_lib.rapid_gate(self.ctx._h, self._h, C.byref(model),
+                               C.c_void_p(X.data_ptr()) if X is not None else None, C.c_void_p(g.data_ptr())),
+               "rapid_gate")
+        return g, X
+
+    def import_(self, next_level: int, labels, stats=None):
+        """rapid_state_import: labels (H, W) int32 and stats (K, 6) int64 or
+        None, both contiguous on the state's device."""
+        import torch
+        H, W = int(self.rgb.shape[0]), int(self.rgb.shape[1])
+        assert labels.is_cuda and labels.dtype == torch.int32 and tuple(labels.shape) == (H, W)
+        assert labels.is_contiguous()
+        if stats is not None:
+            assert stats.is_cuda and stats.dtype == torch.int64 and tuple(stats.shape) == (self.K, 6)
+            assert stats.is_contiguous()
+        _check(_lib.rapid_state_import(self.ctx._h, self._h, next_level, C.c_void_p(labels.data_ptr()),
+                                       C.c_void_p(stats.data_ptr()) if stats is not None else None),
+               "rapid_state_import")
 
     def export(self):
         import torch

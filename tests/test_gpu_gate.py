@@ -320,3 +320,50 @@ def test_gated_batch_of_128_matches_oracle(ctx):
         lab0, s0, _, _, mov0 = oracle.segment(imgs[i], p0, track=True)
         Xo = oracle.features(imgs[i], lab0, 16, s0, mov0, gx, gy)
         assert np.abs(X[i * K:(i + 1) * K] - Xo).max() <= 1e-6
+
+
+def test_state_gate_matches_oracle_and_fused(ctx):
+    """rapid_gate on a level-by-level state (moved pixels tracked from the
+    first level) decides the same bits as the oracle's features and network
+    and as the single-launch gated path; the levels refined under those bits
+    match both."""
+    import torch
+    img, p = _he_case()
+    theta, wb = _rand_model(21)
+    thresh, bits, ref, ref_rep, Xo = _oracle_gated(img, p, theta)
+    K = len(bits)
+    _say("case: rapid_gate level by level 256x192, marked %d of %d" % (bits.sum(), K))
+    st = ctx.state(_dev(img), p)
+    moved = torch.zeros(K, dtype=torch.int64, device="cuda")
+    st.track(None, moved)
+    reps = st.refine_level(0)
+    g, X = st.gate(_dev(wb), thresh, features=True)
+    assert np.abs(X.cpu().numpy() - Xo).max() <= 1e-6
+    assert (g.cpu().numpy() == bits).all()
+    st.track(None, None)
+    reps += st.refine_level(1, gate=g)
+    reps += st.refine_level(2, gate=g)
+    lab, _ = st.export()
+    assert (lab.cpu().numpy() == ref).all()
+    assert reps == ref_rep
+    st.close()
+    labs, _, Xf, gf = ctx.segment_gated([_dev(img)], p, _dev(wb), thresh, features=True)
+    assert (gf.cpu().numpy() == bits).all()
+    assert (Xf.cpu().numpy() == X.cpu().numpy()).all()
+    assert (labs[0].cpu().numpy() == ref).all()
+
+
+def test_state_gate_refuses_non_finite_model(ctx, gpu_lib):
+    import torch
+    img, p = _he_case()
+    _, wb = _rand_model(2)
+    wb = wb.copy()
+    wb[7] = np.int16(0x7F80)   # +inf
+    st = ctx.state(_dev(img), p)
+    st.refine_level(0)
+    g = torch.zeros(st.K, dtype=torch.uint8, device="cuda")
+    with pytest.raises(gpu_lib.RapidError) as e:
+        st.gate(_dev(wb), 0.0, out=g)
+    assert e.value.code == -5
+    assert (g.cpu().numpy() == 1).all()
+    st.close()

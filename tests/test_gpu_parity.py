@@ -141,6 +141,74 @@ def test_state_api_level_by_level(ctx):
     st.close()
 
 
+@pytest.mark.parametrize("with_stats", [True, False])
+def test_state_checkpoint_resume(ctx, with_stats):
+    """Export after level 1 of three, import into a fresh state (statistics
+    given, or rebuilt from the image), refine the remaining levels: labels,
+    statistics and stage counters equal the uninterrupted oracle run."""
+    import torch
+    img = synth.voronoi_blur(192, 160, regions=12, seed=33)
+    p = params.default_params(192, 160, 30, levels=params.THREE_LEVEL)
+    _say("case: checkpoint after level 1, stats given %s" % with_stats)
+    rgb = torch.from_numpy(img).cuda()
+    a = ctx.state(rgb, p)
+    reps = a.refine_level(0)
+    lab1, stats1 = a.export()
+    a.close()
+    b = ctx.state(rgb, p)
+    b.import_(1, lab1, stats1 if with_stats else None)
+    lab_b, stats_b = b.export()
+    torch.cuda.synchronize()
+    assert (lab_b.cpu().numpy() == lab1.cpu().numpy()).all()
+    assert (stats_b.cpu().numpy() == stats1.cpu().numpy()).all()
+    reps += b.refine_level(1)
+    reps += b.refine_level(2)
+    lab, stats = b.export()
+    torch.cuda.synchronize()
+    ref, ref_stats, ref_rep = oracle.segment(img, p)
+    _assert_same(lab.cpu().numpy(), reps, ref, ref_rep, "checkpoint resume")
+    assert (stats.cpu().numpy() == ref_stats).all()
+    # a finished state restores too: export of the import is the input
+    c = ctx.state(rgb, p)
+    c.import_(3, lab, None)
+    lab_c, stats_c = c.export()
+    torch.cuda.synchronize()
+    assert (lab_c.cpu().numpy() == ref).all() and (stats_c.cpu().numpy() == ref_stats).all()
+    c.close()
+    b.close()
+
+
+def test_state_import_rejects_bad_labels(ctx, gpu_lib):
+    """Labels that are not constant on the point's blocks, or out of range,
+    are refused; the state is unusable until a valid import."""
+    import torch
+    img = synth.voronoi_blur(128, 96, regions=8, seed=34)
+    p = params.default_params(128, 96, 12, levels=params.THREE_LEVEL)
+    rgb = torch.from_numpy(img).cuda()
+    st = ctx.state(rgb, p)
+    st.refine_level(0)
+    lab1, stats1 = st.export()
+    bad = lab1.clone()
+    bad[17, 21] = (int(bad[17, 21]) + 1) % st.K     # inside a 16 x 16 block
+    with pytest.raises(gpu_lib.RapidError) as e:
+        st.import_(1, bad)
+    assert e.value.code == -1
+    with pytest.raises(gpu_lib.RapidError) as e:
+        st.refine_level(1)
+    assert e.value.code == -4
+    neg = lab1.clone()
+    neg[:16, :16] = st.K                             # a whole block out of range
+    with pytest.raises(gpu_lib.RapidError) as e:
+        st.import_(1, neg)
+    assert e.value.code == -1
+    with pytest.raises(gpu_lib.RapidError) as e:
+        st.import_(4, lab1)                          # beyond the last level
+    assert e.value.code == -1
+    st.import_(1, lab1, stats1)
+    st.refine_level(1)
+    st.close()
+
+
 def test_state_api_rejects_out_of_order(ctx, gpu_lib):
     import torch
     img = synth.voronoi_blur(64, 64, regions=5, seed=2)
