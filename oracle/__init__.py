@@ -57,6 +57,7 @@ class OrcParams(C.Structure):
         ("stages", (C.c_int32 * MAX_STAGES) * MAX_LEVELS),
         ("gate_level", C.c_int32), ("frac_bits", C.c_int32),
         ("max_sweeps", C.c_int32), ("shuffle_seed", C.c_int32), ("gate_rule", C.c_int32),
+        ("merge", C.c_int32), ("pad_", C.c_int32),
         ("min_size", C.c_int64), ("max_size", C.c_int64),
         ("w_col", C.c_int64), ("w_pos", C.c_int64), ("w_bnd", C.c_int64),
     ]
@@ -67,6 +68,7 @@ class OrcStageReport(C.Structure):
         ("level", C.c_int32), ("block", C.c_int32), ("sweeps", C.c_int32),
         ("converged", C.c_int32), ("active", C.c_int64), ("proposals", C.c_int64),
         ("commits", C.c_int64), ("skip_min", C.c_int64), ("skip_topo", C.c_int64),
+        ("merges", C.c_int64),
     ]
 
     def as_dict(self):
@@ -94,6 +96,9 @@ def lib():
         L.orc_block_energy.restype = C.c_int64
         L.orc_segment_ex.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, C.POINTER(OrcParams), P,
                                      P, P, P, C.c_int32, C.c_int32, P, P]
+        L.orc_merge_cost.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, C.POINTER(OrcParams), P,
+                                     C.c_int32, C.c_int32, C.c_int32]
+        L.orc_merge_cost.restype = C.c_int64
         L.orc_features.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, P, C.c_int32, P, P,
                                    C.c_int32, C.c_int32, C.c_int32, P]
     return _lib
@@ -116,6 +121,7 @@ def make_params(d: dict, shuffle_seed: int = 0) -> OrcParams:
     p.max_sweeps = int(d.get("max_sweeps", 64))
     p.shuffle_seed = int(shuffle_seed)
     p.gate_rule = GATE_RULES[d.get("gate_rule", "either")]
+    p.merge = int(bool(d.get("merge", False)))
     p.min_size = int(d["min_size"])
     p.max_size = int(d["max_size"])
     p.w_col = int(d["w_col"])
@@ -182,6 +188,16 @@ def segment(rgb: np.ndarray, d: dict, gate: np.ndarray | None = None,
         raise RuntimeError("orc_segment failed rc=%d" % rc)
     out = (labels, stats, [reps[i].as_dict() for i in range(rc)])
     return out + (inv, mov) if track else out
+
+
+def merge_cost(rgb: np.ndarray, d: dict, labels: np.ndarray, K: int, m: int, k: int) -> int:
+    """Energy change of Eq. (1) when superpixel m is merged into k, for
+    pixel labels labels (see orc_merge_cost)."""
+    rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    H, W, _ = rgb.shape
+    p = make_params(d)
+    return int(lib().orc_merge_cost(_ptr(rgb), W, H, 3 * W, C.byref(p), _ptr(labels), K, m, k))
 
 
 def features(rgb: np.ndarray, labels: np.ndarray, B: int, stats: np.ndarray,

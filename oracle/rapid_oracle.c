@@ -14,8 +14,11 @@
  *     energy difference that involves the block is evaluated (Sec. 3.1, last
  *     paragraph);
  *   - the size regularity of Sec. 3.1 read as a hard lower/upper bound on
- *     superpixel size (Eqs. (4)-(5) supply the upper bound; the merge that
- *     would change the label count is not part of this path);
+ *     superpixel size (Eqs. (4)-(5) supply the upper bound); with merge on,
+ *     a superpixel that a block could not leave without falling below the
+ *     lower bound is instead merged into the neighbour of least merged
+ *     energy (Eq. (4)) whose merged size stays within the upper bound
+ *     (Eq. (5)), which lowers the label count;
  *   - the stage loop of Algorithm RAPID: grid initialisation, blocks that
  *     shrink stage by stage, a boundary set that is processed until no block
  *     changes, statistics kept up to date after moves;
@@ -41,7 +44,10 @@
  *     and the means are refreshed after the class;  after a sweep only
  *     eligible blocks within one block of a changed block stay active;
  *   - the grid of K superpixels follows a block-centre rule (orc_grid and
- *     orc_init_labels).
+ *     orc_init_labels);
+ *   - merges are collected and applied in a synchronous pass too (see
+ *     merge_pass): the energy of a merge is Eq. (1) after minus before, with
+ *     the fixed-point means of the union.
  */
 #include "rapid_oracle.h"
 #include <math.h>
@@ -183,6 +189,7 @@ typedef struct {
     const uint8_t *gate;       /* NULL: every pair active */
     uint8_t *involved;         /* optional: superpixels in a proposal        */
     int64_t *moved;            /* optional: pixels moved in or out, per label */
+    uint8_t *req;              /* merge on: asked to merge since the last pass */
 } state;
 
 static inline int64_t div_round(int64_t num, int64_t n, int F)
@@ -197,6 +204,11 @@ static inline int64_t div_round(int64_t num, int64_t n, int F)
 static void refresh_means(state *s, int32_t k)
 {
     int F = s->p->frac_bits;
+    if (s->n[k] == 0) {   /* merged away: no pixels, means 0 */
+        for (int ch = 0; ch < 3; ch++) s->c[3 * k + ch] = 0;
+        for (int ax = 0; ax < 2; ax++) s->mu[2 * k + ax] = 0;
+        return;
+    }
     for (int ch = 0; ch < 3; ch++) s->c[3 * k + ch] = div_round(s->S[3 * k + ch], s->n[k], F);
     for (int ax = 0; ax < 2; ax++) s->mu[2 * k + ax] = div_round(s->T[2 * k + ax], s->n[k], F);
 }
@@ -345,8 +357,9 @@ static i128 global_energy(const state *s)
     return (i128)p->w_col * ec + (i128)p->w_pos * ep + (i128)p->w_bnd * (eb << (2 * F));
 }
 
-/* Debug invariants: every superpixel non-empty and 4-connected, statistics
- * equal to a from-scratch recount, means equal to f(statistics). */
+/* Debug invariants: every superpixel 4-connected and non-empty unless
+ * merged away (then its sums are 0 as well), statistics equal to a
+ * from-scratch recount, means equal to f(statistics). */
 static int check_invariants(state *s)
 {
     int32_t W = s->W, H = s->H, K = s->K;
@@ -364,9 +377,14 @@ static int check_invariants(state *s)
         ok = stats_from_labels(s->rgb, W, H, s->stride, lab, K, n, S, T) == ORC_OK;
     }
     for (int32_t k = 0; ok && k < K; k++) {
-        if (n[k] == 0 || n[k] != s->n[k]) ok = 0;
+        if ((n[k] == 0 && !s->p->merge) || n[k] != s->n[k]) ok = 0;
         for (int ch = 0; ch < 3; ch++) if (S[3 * k + ch] != s->S[3 * k + ch]) ok = 0;
         for (int ax = 0; ax < 2; ax++) if (T[2 * k + ax] != s->T[2 * k + ax]) ok = 0;
+        if (n[k] == 0) {
+            for (int ch = 0; ch < 3; ch++) if (s->c[3 * k + ch] != 0) ok = 0;
+            for (int ax = 0; ax < 2; ax++) if (s->mu[2 * k + ax] != 0) ok = 0;
+            continue;
+        }
         int F = s->p->frac_bits;
         for (int ch = 0; ch < 3; ch++) if (s->c[3 * k + ch] != div_round(S[3 * k + ch], n[k], F)) ok = 0;
         for (int ax = 0; ax < 2; ax++) if (s->mu[2 * k + ax] != div_round(T[2 * k + ax], n[k], F)) ok = 0;
@@ -459,7 +477,11 @@ static int64_t propose(state *s, int32_t cls, const uint8_t *active,
         if (active && !active[bi]) continue;
         blk b = block_geom(s, bx, by);
         int32_t a = s->bl[bi];
-        if (s->n[a] - b.m < p->min_size) { (*skip_min)++; continue; }
+        if (s->n[a] - b.m < p->min_size) {
+            (*skip_min)++;
+            if (s->req) s->req[a] = 1;   /* underflow: a merge candidate */
+            continue;
+        }
         if (!is_simple_block(s, bx, by)) { (*skip_topo)++; continue; }
         /* candidate labels: distinct in-image 4-neighbour labels != a, ascending */
         int32_t cand[4]; int nc = 0;
@@ -493,6 +515,154 @@ static int64_t propose(state *s, int32_t cls, const uint8_t *active,
         }
     }
     return np;
+}
+
+/* ----------------------------------------------------- merge on underflow */
+
+/* n |c|^2 - 2^(F+1) <c, S> over d components: the part of
+ * sum_p |2^F v(p) - c|^2 over a superpixel's pixels that depends on c (the
+ * sum of |2^F v(p)|^2 is the same before and after a merge and cancels). */
+static i128 fit_term(const int64_t *c, const int64_t *S, int64_t n, int d, int F)
+{
+    i128 r = 0;
+    for (int i = 0; i < d; i++)
+        r += (i128)n * c[i] * c[i] - ((i128)2 << F) * c[i] * S[i];
+    return r;
+}
+
+/* Energy change of Eq. (1) when superpixel m is merged into k (Eq. (4)):
+ * the colour and position terms of both, re-fitted to the union's
+ * fixed-point means, and the len shared boundary pixel pairs that stop
+ * being boundary. */
+static i128 merge_cost(const state *s, int32_t m, int32_t k, int64_t len)
+{
+    const orc_params *p = s->p;
+    int F = p->frac_bits;
+    int64_t nm = s->n[m], nk = s->n[k], nu = nm + nk;
+    int64_t Su[3], cu[3], Tu[2], mu_u[2];
+    for (int ch = 0; ch < 3; ch++) {
+        Su[ch] = s->S[3 * (int64_t)m + ch] + s->S[3 * (int64_t)k + ch];
+        cu[ch] = div_round(Su[ch], nu, F);
+    }
+    for (int ax = 0; ax < 2; ax++) {
+        Tu[ax] = s->T[2 * (int64_t)m + ax] + s->T[2 * (int64_t)k + ax];
+        mu_u[ax] = div_round(Tu[ax], nu, F);
+    }
+    i128 dc = fit_term(cu, Su, nu, 3, F) - fit_term(s->c + 3 * (int64_t)m, s->S + 3 * (int64_t)m, nm, 3, F) -
+              fit_term(s->c + 3 * (int64_t)k, s->S + 3 * (int64_t)k, nk, 3, F);
+    i128 dp = fit_term(mu_u, Tu, nu, 2, F) - fit_term(s->mu + 2 * (int64_t)m, s->T + 2 * (int64_t)m, nm, 2, F) -
+              fit_term(s->mu + 2 * (int64_t)k, s->T + 2 * (int64_t)k, nk, 2, F);
+    return (i128)p->w_col * dc + (i128)p->w_pos * dp - (i128)p->w_bnd * ((i128)len << (2 * F));
+}
+
+/* One merge pass (Sec. 3.1, Eqs. (4)-(5)), run when a sweep commits nothing.
+ * Candidates: superpixels that asked since the last pass (a block of theirs
+ * could not leave without going below min_size) and still hold fewer than
+ * min_size + B^2 pixels.  Each candidate m picks, among the labels of
+ * blocks 4-adjacent to its blocks (at most ORC_MERGE_MAX_NB distinct ones,
+ * else no pick), those k with an active pair (m, k) and
+ * n_m + n_k <= max_size, the one of least merge_cost, ties to the smaller
+ * label.  A pick m -> t makes m leave when t picked nothing itself, or
+ * when t picked m back and m > t (a mutual pair merges into its smaller
+ * label); of the leaving superpixels that picked t, the smallest merges.
+ * No target leaves and every target absorbs at most one superpixel, so the
+ * applied merges are disjoint pairs whose energy changes add up.  Merged
+ * blocks are marked in changed.  Returns the number of merges. */
+static int64_t merge_pass(state *s, uint8_t *changed, int debug, int *rc)
+{
+    const orc_params *p = s->p;
+    int32_t K = s->K;
+    int64_t nb = (int64_t)s->nbx * s->nby, B2 = (int64_t)s->B * s->B, merged = 0;
+    int32_t *key = malloc(sizeof(int32_t) * ORC_MERGE_MAX_NB * (int64_t)K);
+    int64_t *len = malloc(sizeof(int64_t) * ORC_MERGE_MAX_NB * (int64_t)K);
+    int32_t *cnt = malloc(sizeof(int32_t) * K), *tgt = malloc(sizeof(int32_t) * K);
+    int32_t *win = malloc(sizeof(int32_t) * K);
+    uint8_t *cand = calloc(K, 1), *com = calloc(K, 1);
+    i128 *cost = malloc(sizeof(i128) * K);
+    *rc = ORC_OK;
+    if (!key || !len || !cnt || !tgt || !win || !cand || !com || !cost) { *rc = ORC_ENOMEM; goto done; }
+    int any = 0;
+    for (int32_t m = 0; m < K; m++) {
+        cand[m] = s->req[m] && s->n[m] > 0 && s->n[m] < p->min_size + B2;
+        any |= cand[m];
+        cnt[m] = 0;
+        tgt[m] = -1;
+        win[m] = INT32_MAX;
+    }
+    if (!any) goto done;
+    /* shared boundary length with every neighbour label, in pixel pairs */
+    for (int32_t by = 0; by < s->nby; by++)
+        for (int32_t bx = 0; bx < s->nbx; bx++) {
+            int32_t a = blabel(s, bx, by);
+            if (!cand[a]) continue;
+            blk b = block_geom(s, bx, by);
+            int32_t nl[4] = {blabel(s, bx - 1, by), blabel(s, bx + 1, by), blabel(s, bx, by - 1),
+                             blabel(s, bx, by + 1)};
+            int64_t el[4] = {b.h, b.h, b.w, b.w};
+            for (int d = 0; d < 4; d++) {
+                int32_t k = nl[d];
+                if (k < 0 || k == a || cnt[a] > ORC_MERGE_MAX_NB) continue;
+                int j = 0;
+                while (j < cnt[a] && key[ORC_MERGE_MAX_NB * a + j] != k) j++;
+                if (j == cnt[a]) {
+                    if (cnt[a] == ORC_MERGE_MAX_NB) { cnt[a] = ORC_MERGE_MAX_NB + 1; continue; }
+                    key[ORC_MERGE_MAX_NB * a + j] = k;
+                    len[ORC_MERGE_MAX_NB * a + j] = 0;
+                    cnt[a]++;
+                }
+                len[ORC_MERGE_MAX_NB * a + j] += el[d];
+            }
+        }
+    /* picks (Eq. (4) under the size bound of Eq. (5)) */
+    for (int32_t m = 0; m < K; m++) {
+        if (!cand[m] || cnt[m] > ORC_MERGE_MAX_NB) continue;
+        for (int j = 0; j < cnt[m]; j++) {
+            int32_t k = key[ORC_MERGE_MAX_NB * m + j];
+            if (s->n[m] + s->n[k] > p->max_size || !pair_active(s, m, k)) continue;
+            i128 c = merge_cost(s, m, k, len[ORC_MERGE_MAX_NB * m + j]);
+            if (tgt[m] < 0 || c < cost[m] || (c == cost[m] && k < tgt[m])) { tgt[m] = k; cost[m] = c; }
+        }
+    }
+    for (int32_t m = 0; m < K; m++) {
+        int32_t t = tgt[m];
+        com[m] = t >= 0 && (tgt[t] < 0 || (tgt[t] == m && m > t));   /* leaves */
+        if (com[m] && m < win[t]) win[t] = m;
+    }
+    for (int32_t m = 0; m < K; m++)
+        if (com[m] && win[tgt[m]] != m) com[m] = 0;
+    /* apply */
+    i128 e_before = 0, de_sum = 0;
+    if (debug) e_before = global_energy(s);
+    for (int64_t i = 0; i < nb; i++) {
+        int32_t a = s->bl[i];
+        if (com[a]) { s->bl[i] = tgt[a]; changed[i] = 1; }
+    }
+    for (int32_t m = 0; m < K; m++) {
+        if (!com[m]) continue;
+        int32_t t = tgt[m];
+        de_sum += cost[m];
+        s->n[t] += s->n[m]; s->n[m] = 0;
+        for (int ch = 0; ch < 3; ch++) {
+            s->S[3 * (int64_t)t + ch] += s->S[3 * (int64_t)m + ch];
+            s->S[3 * (int64_t)m + ch] = 0;
+        }
+        for (int ax = 0; ax < 2; ax++) {
+            s->T[2 * (int64_t)t + ax] += s->T[2 * (int64_t)m + ax];
+            s->T[2 * (int64_t)m + ax] = 0;
+        }
+        refresh_means(s, t);
+        refresh_means(s, m);
+        merged++;
+    }
+    if (debug) {
+        /* the picks' energies add up to the change of Eq. (1) exactly */
+        if (global_energy(s) - e_before != de_sum) { *rc = ORC_EINVAR; goto done; }
+        if ((*rc = check_invariants(s)) != ORC_OK) goto done;
+    }
+done:
+    memset(s->req, 0, K);
+    free(key); free(len); free(cnt); free(tgt); free(win); free(cand); free(com); free(cost);
+    return merged;
 }
 
 static int run_stage(state *s, int32_t level, int32_t B, int32_t *lab,
@@ -585,6 +755,7 @@ static int run_stage(state *s, int32_t level, int32_t B, int32_t *lab,
                 /* an undersized superpixel cannot shrink, an oversized one
                  * cannot grow */
                 for (int32_t k = 0; k < K && s->n0; k++) {
+                    if (s->n[k] == 0 && p->merge) continue;   /* merged away */
                     int64_t lo = p->min_size < s->n0[k] ? p->min_size : s->n0[k];
                     int64_t hi = p->max_size > s->n0[k] ? p->max_size : s->n0[k];
                     if (s->n[k] < lo || s->n[k] > hi || s->n[k] < 1) { rc = ORC_EINVAR; goto done; }
@@ -593,7 +764,17 @@ static int run_stage(state *s, int32_t level, int32_t B, int32_t *lab,
             }
         }
         rep->sweeps = t + 1;
-        if (sweep_commits == 0) { rep->converged = 1; break; }
+        if (sweep_commits == 0) {
+            /* a quiet sweep: pending merges go now, and the merged blocks
+             * seed the next sweep like committed moves */
+            int64_t merged = 0;
+            if (p->merge) {
+                merged = merge_pass(s, changed, debug, &rc);
+                if (rc) goto done;
+            }
+            if (merged == 0) { rep->converged = 1; break; }
+            rep->merges += merged;
+        }
         /* next active set: eligible blocks within one block of a changed one */
         memset(active, 0, nb);
         for (int32_t by = 0; by < s->nby; by++)
@@ -612,6 +793,7 @@ static int run_stage(state *s, int32_t level, int32_t B, int32_t *lab,
                 if (active[bi]) active[bi] = (uint8_t)eligible(s, bx, by);
             }
     }
+    if (s->req) memset(s->req, 0, K);   /* requests do not outlive the stage */
     /* write the block labels back to the pixels */
     for (int32_t y = 0; y < s->H; y++)
         for (int32_t x = 0; x < s->W; x++)
@@ -630,6 +812,7 @@ static int check_params(const orc_params *p, int32_t W, int32_t H)
     if (p->n_levels < 1 || p->n_levels > ORC_MAX_LEVELS) return ORC_EINVAL;
     if (p->frac_bits < 0 || p->frac_bits > 8 || p->max_sweeps < 1) return ORC_EINVAL;
     if (p->gate_rule < ORC_GATE_EITHER || p->gate_rule > ORC_GATE_DIFFER) return ORC_EINVAL;
+    if (p->merge != 0 && p->merge != 1) return ORC_EINVAL;
     if (p->w_col < 0 || p->w_pos < 0 || p->w_bnd < 0) return ORC_EINVAL;
     int32_t prev = 0;
     for (int l = 0; l < p->n_levels; l++) {
@@ -691,7 +874,8 @@ int orc_segment_ex(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
     s.T = calloc(2 * (int64_t)K, sizeof(int64_t));
     s.c = calloc(3 * (int64_t)K, sizeof(int64_t)); s.mu = calloc(2 * (int64_t)K, sizeof(int64_t));
     s.n0 = calloc(K, sizeof(int64_t));
-    if (!s.n || !s.S || !s.T || !s.c || !s.mu || !s.n0) { rc = ORC_ENOMEM; goto done; }
+    if (p->merge) s.req = calloc(K, 1);
+    if (!s.n || !s.S || !s.T || !s.c || !s.mu || !s.n0 || (p->merge && !s.req)) { rc = ORC_ENOMEM; goto done; }
     /* statistics are computed once (first level) and reused afterwards */
     if ((rc = stats_from_labels(rgb, W, H, stride, labels, K, s.n, s.S, s.T))) goto done;
     for (int32_t k = 0; k < K; k++) {
@@ -724,6 +908,7 @@ int orc_segment_ex(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
     rc = nrep;
 done:
     free(s.n); free(s.S); free(s.T); free(s.c); free(s.mu); free(s.n0); free(s.bl); free(s.bs);
+    free(s.req);
     return rc;
 }
 
@@ -793,6 +978,44 @@ int64_t orc_block_energy(const uint8_t *rgb, int32_t W, int32_t H, int64_t strid
 }
 
 
+/* Energy change of merging superpixel m into k (merge_cost) for a state
+ * given by pixel labels constant on blocks of size B (statistics recounted,
+ * shared boundary counted over pixel pairs).  Saturates to INT64 range;
+ * INT64_MIN on a bad argument. */
+int64_t orc_merge_cost(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
+                       const orc_params *p, const int32_t *labels, int32_t K, int32_t m, int32_t k)
+{
+    state s;
+    memset(&s, 0, sizeof s);
+    s.rgb = rgb; s.W = W; s.H = H; s.stride = stride; s.p = p; s.K = K;
+    int64_t r = INT64_MIN;
+    if (m < 0 || k < 0 || m >= K || k >= K || m == k) return r;
+    s.n = calloc(K, sizeof(int64_t)); s.S = calloc(3 * (int64_t)K, sizeof(int64_t));
+    s.T = calloc(2 * (int64_t)K, sizeof(int64_t));
+    s.c = calloc(3 * (int64_t)K, sizeof(int64_t)); s.mu = calloc(2 * (int64_t)K, sizeof(int64_t));
+    if (s.n && s.S && s.T && s.c && s.mu &&
+        stats_from_labels(rgb, W, H, stride, labels, K, s.n, s.S, s.T) == ORC_OK && s.n[m] && s.n[k]) {
+        for (int32_t j = 0; j < K; j++) refresh_means(&s, j);
+        int64_t len = 0;
+        for (int32_t y = 0; y < H; y++)
+            for (int32_t x = 0; x < W; x++) {
+                int32_t a = labels[(int64_t)y * W + x];
+                if (x + 1 < W) {
+                    int32_t b = labels[(int64_t)y * W + x + 1];
+                    len += (a == m && b == k) || (a == k && b == m);
+                }
+                if (y + 1 < H) {
+                    int32_t b = labels[(int64_t)(y + 1) * W + x];
+                    len += (a == m && b == k) || (a == k && b == m);
+                }
+            }
+        i128 e = merge_cost(&s, m, k, len);
+        r = e > (i128)INT64_MAX ? INT64_MAX : (e < -(i128)INT64_MAX ? -INT64_MAX : (int64_t)e);
+    }
+    free(s.n); free(s.S); free(s.T); free(s.c); free(s.mu);
+    return r;
+}
+
 /* ------------------------------------------------------- gate features */
 
 /* Sixteen features of every superpixel at the gate point (Eq. (6) needs a
@@ -810,6 +1033,7 @@ int64_t orc_block_energy(const uint8_t *rgb, int32_t W, int32_t H, int64_t strid
  *   13   pixels moved in or out so far / size
  *   14   max of features 3-5
  *   15   1
+ * (a superpixel merged away has all 16 features 0)
  * labels: pixel labels constant on blocks of size B (the last stage before
  * the gate); stats: K x 6 (n, S, T); moved: K (may be NULL: zeros). */
 int orc_features(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
@@ -828,7 +1052,7 @@ int orc_features(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
     for (int32_t k = 0; k < K; k++) {
         cmin[k] = -1;
         for (int ch = 0; ch < 3; ch++)
-            cm[3 * k + ch] = div_round(stats[6 * (int64_t)k + 1 + ch], stats[6 * (int64_t)k], F);
+            cm[3 * k + ch] = stats[6 * (int64_t)k] ? div_round(stats[6 * (int64_t)k + 1 + ch], stats[6 * (int64_t)k], F) : 0;
     }
     for (int32_t y = 0; y < H; y++)
         for (int32_t x = 0; x < W; x++) {
@@ -864,6 +1088,10 @@ int orc_features(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
         const int64_t *r = stats + 6 * (int64_t)k;
         double n = (double)r[0];
         float *f = out + 16 * (int64_t)k;
+        if (r[0] == 0) {   /* merged away: all features 0 */
+            for (int i = 0; i < 16; i++) f[i] = 0.0f;
+            continue;
+        }
         double sd[3];
         for (int ch = 0; ch < 3; ch++) {
             double mu = (double)r[1 + ch] / n;

@@ -33,6 +33,8 @@ typedef struct {
     int32_t max_sweeps;
     int32_t shuffle_seed;      /* 0: natural block order; else a permutation    */
     int32_t gate_rule;         /* ORC_GATE_*: pairs a gate lets move            */
+    int32_t merge;             /* 1: merge on underflow (Sec. 3.1, Eqs. (4)-(5)) */
+    int32_t pad_;
     int64_t min_size, max_size;
     int64_t w_col, w_pos, w_bnd;
 } orc_params;
@@ -40,7 +42,12 @@ typedef struct {
 typedef struct {
     int32_t level, block, sweeps, converged;
     int64_t active, proposals, commits, skip_min, skip_topo;
+    int64_t merges;            /* superpixels merged away in the stage          */
 } orc_stage_report;
+
+/* merge on underflow: a superpixel with more distinct neighbour labels than
+ * this does not merge */
+#define ORC_MERGE_MAX_NB 8
 
 /* gate rules (which pairs (a, k) may move past the gate level) */
 #define ORC_GATE_EITHER 0      /* g_a or g_k                                    */
@@ -67,6 +74,8 @@ int orc_segment_ex(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
                    int32_t *labels, int64_t *stats_out,
                    orc_stage_report *rep, int32_t max_rep, int32_t debug,
                    uint8_t *involved, int64_t *moved);
+int64_t orc_merge_cost(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
+                       const orc_params *p, const int32_t *labels, int32_t K, int32_t m, int32_t k);
 int orc_features(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
                  const int32_t *labels, int32_t B, const int64_t *stats, const int64_t *moved,
                  int32_t gx, int32_t gy, int32_t F, float *out);
