@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define RAPID_ABI_VERSION 1
+#define RAPID_ABI_VERSION 2
 #define RAPID_MAX_LEVELS 4
 #define RAPID_MAX_STAGES 8
 #define RAPID_MAX_DIM 8192
@@ -97,6 +97,21 @@ typedef struct {
  *             RAPID_GATE_DIFFER  g_a != g_k: g holds a predicted class and
  *                                only pairs across a class border refine,
  *                                as the paper's boundary superpixels.
+ *  merge      0: plain size bounds.  1: merge on underflow (Sec. 3.1,
+ *             Eqs. (4)-(5)): a superpixel that one of its blocks could not
+ *             leave without going below min_size asks to merge; when a
+ *             sweep commits nothing, every asker still below
+ *             min_size + B^2 pixels picks the 4-adjacent superpixel of least
+ *             merged energy (Eq. (1) after minus before, means of the
+ *             union) among those with an active pair and a merged size
+ *             within max_size (at most 8 distinct neighbour labels, else no
+ *             pick; ties to the smaller label); an asker leaves when its
+ *             pick picked nothing, or picked it back and has the smaller
+ *             label; the smallest leaving label per target merges into it,
+ *             then sweeping resumes around the merged blocks.  Merged
+ *             labels end up empty (n = 0) and absent from the output.
+ *             Per label 4-connected input is assumed (a state import
+ *             with disconnected labels may merge differently).
  *  min_size, max_size  hard size bounds in pixels (Sec. 3.1, Eq. (5)).
  *  w_col, w_pos, w_bnd integer weights of colour, position and boundary
  *             terms (Eq. (1)); rejected when the worst-case block energy
@@ -111,6 +126,8 @@ typedef struct {
     int32_t frac_bits;
     int32_t max_sweeps;
     int32_t gate_rule;     /* RAPID_GATE_*: which pairs a gate lets move */
+    int32_t merge;         /* 1: merge on underflow */
+    int32_t reserved;      /* 0 */
     int64_t min_size, max_size;
     int64_t w_col, w_pos, w_bnd;
 } rapid_params;
@@ -134,6 +151,7 @@ typedef struct {
     int64_t commits;     /* proposals admitted by the size filter     */
     int64_t skip_min;    /* visits skipped: source would fall below min */
     int64_t skip_topo;   /* visits skipped: not a simple point        */
+    int64_t merges;      /* superpixels merged away (merge on)         */
 } rapid_stage_report;
 
 typedef struct {

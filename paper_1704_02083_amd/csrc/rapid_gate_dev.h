@@ -109,7 +109,8 @@ __device__ __forceinline__ void feat_init_sp(const int64_t *st, int32_t *fmean, 
 {
     const int64_t *r = st + 6 * (int64_t)k;
     const int64_t n = r[0];
-    for (int ch = 0; ch < 3; ch++) fmean[3 * k + ch] = (int32_t)(((r[1 + ch] << (F + 1)) + n) / (2 * n));
+    // a superpixel merged away (n = 0) has mean 0
+    for (int ch = 0; ch < 3; ch++) fmean[3 * k + ch] = n ? (int32_t)(((r[1 + ch] << (F + 1)) + n) / (2 * n)) : 0;
     int64_t *a = facc + FACC * (int64_t)k;
     for (int q = 0; q < FACC; q++) a[q] = 0;
     a[7] = INT64_MAX;   // min contrast
@@ -241,6 +242,10 @@ __device__ __forceinline__ void feat_final_sp(const Job &J, const int64_t *st, c
     const double cs = 255.0 * (double)(1 << F);
     const int64_t *r = st + 6 * (int64_t)k;
     const int64_t *a = facc + FACC * (int64_t)k;
+    if (r[0] == 0) {   // merged away: all features 0
+        for (int i = 0; i < 16; i++) f[i] = 0.0f;
+        return;
+    }
     const double n = (double)r[0];
     double sd[3];
     for (int ch = 0; ch < 3; ch++) {

@@ -157,6 +157,8 @@ rapid_status make_sched(const rapid_params *p, Sched *sc, int32_t level_first[RA
     if (p->frac_bits < 0 || p->frac_bits > 4 || p->max_sweeps < 1 || p->max_sweeps > (1 << 20)) return RAPID_EINVAL;
     if (p->gate_rule < RAPID_GATE_EITHER || p->gate_rule > RAPID_GATE_DIFFER) return RAPID_EINVAL;
     sc->gate_rule = p->gate_rule;
+    if ((p->merge != 0 && p->merge != 1) || p->reserved != 0) return RAPID_EINVAL;
+    sc->merge = p->merge;
     if (p->w_col < 0 || p->w_pos < 0 || p->w_bnd < 0 || p->min_size < 0 || p->max_size < 1)
         return RAPID_EINVAL;
     sc->F = p->frac_bits;
@@ -253,6 +255,7 @@ struct Layout {
     size_t off_lab[2], off_sums[MAXST], off_lists, off_props, off_changed, off_stamp;
     size_t off_stats, off_means, off_flow, off_rep;
     size_t off_fmean, off_facc, off_moved, off_moms;
+    size_t off_merge[8];   // merge on: mreq mlist mbox mkey mlen mstate mpick mwin
     int64_t capc = 0;
 };
 
@@ -291,6 +294,13 @@ Layout plan(int32_t W, int32_t H, int32_t K, const Sched &sc, int moms_stage = -
         const int B = sc.B[moms_stage];
         L.off_moms = take(12 * (size_t)((W + B - 1) / B) * ((H + B - 1) / B));
     }
+    for (int i = 0; i < 8; i++) L.off_merge[i] = (size_t)-1;
+    if (sc.merge) {
+        const size_t Kz = (size_t)K;
+        const size_t bytes[8] = {4 * ((Kz + 31) / 32), 4 * Kz, 16 * Kz, 4 * MERGE_NB * Kz,
+                                 4 * MERGE_NB * Kz, 4 * Kz, 4 * Kz, 4 * Kz};
+        for (int i = 0; i < 8; i++) L.off_merge[i] = take(bytes[i]);
+    }
     L.bytes = o;
     return L;
 }
@@ -326,6 +336,16 @@ void fill_job(Job &J, char *base, const Layout &L, const rapid_image *img, int32
     J.facc = reinterpret_cast<int64_t *>(base + L.off_facc);
     J.moms = L.off_moms == (size_t)-1 ? nullptr : reinterpret_cast<uint32_t *>(base + L.off_moms);
     J.moms_stage = -1;
+    if (L.off_merge[0] != (size_t)-1) {
+        J.mreq = reinterpret_cast<uint32_t *>(base + L.off_merge[0]);
+        J.mlist = reinterpret_cast<int32_t *>(base + L.off_merge[1]);
+        J.mbox = reinterpret_cast<int4 *>(base + L.off_merge[2]);
+        J.mkey = reinterpret_cast<int32_t *>(base + L.off_merge[3]);
+        J.mlen = reinterpret_cast<int32_t *>(base + L.off_merge[4]);
+        J.mstate = reinterpret_cast<int32_t *>(base + L.off_merge[5]);
+        J.mpick = reinterpret_cast<int32_t *>(base + L.off_merge[6]);
+        J.mwin = reinterpret_cast<int32_t *>(base + L.off_merge[7]);
+    }
 }
 
 rapid_status dev_err(hipError_t e) { return e == hipSuccess ? RAPID_OK : RAPID_EDEVICE; }

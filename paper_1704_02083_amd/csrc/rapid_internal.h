@@ -31,6 +31,7 @@ struct Sched {
                              // integer below 2^53, so fp64 evaluates it exactly
     int32_t gate_stage;      // first stage refined under the gate
     int32_t gate_rule;       // RAPID_GATE_*
+    int32_t merge;           // 1: merge on underflow
     int32_t F, max_sweeps;
     int64_t min_size, max_size, w_col, w_pos, w_bnd;
     double d_wc, d_wp, d_wb, d_fs;   // w_col, w_pos, w_bnd 2^(2F), 2^(F+1) as doubles
@@ -97,7 +98,19 @@ struct Job {
     // (gid_y0 + k / gx) * gid_w + gid_x0 + k % gx
     int32_t tile, core_x0, core_y0, core_w, core_h, pad3;
     int64_t gid_x0, gid_y0, gid_w;
+    // merge on underflow (null when off): ask bits (K bits), askers in
+    // order of asking (K), per asker its window of blocks and MERGE_NB
+    // neighbour slots (label, shared length) with a state word, per label
+    // its pick and the smallest leaving label that picked it
+    uint32_t *mreq;
+    int32_t *mlist;
+    int4 *mbox;
+    int32_t *mkey, *mlen, *mstate;
+    int32_t *mpick, *mwin;
 };
+
+// merge on underflow: neighbour slots per asker
+constexpr int MERGE_NB = 8;
 
 hipError_t launch_block_sums(const Job *jobs_dev, int n_jobs, int s, int B, int64_t max_nb, hipStream_t stream);
 hipError_t launch_expand(const int32_t *L, int W, int H, int B, int32_t *out, int64_t stride,

@@ -114,7 +114,8 @@ __device__ __forceinline__ void refresh_sp(const int64_t *st, int32_t *mn, int k
 {
     const int64_t *r = st + 6 * (int64_t)k;
     const int64_t n = r[0];
-    const double dd = (double)(2 * n), dn0 = (double)n;
+    // a superpixel merged away (n = 0, sums 0) gets means 0
+    const double dd = (double)(2 * max(n, (int64_t)1)), dn0 = (double)n;
     const double rcp = 1.0 / dd;
     int32_t *o = mn + MN_STRIDE * k;
     double q[5];
@@ -349,6 +350,206 @@ __device__ __forceinline__ void class_push(int32_t *cnt, int32_t *lds, int capl,
     list_put(lds + cls * capl, capl, glob, cls * capg, slot, v);
 }
 
+// ------------------------------------------------------ merge on underflow
+// Sec. 3.1, Eqs. (4)-(5).  A superpixel asks to merge when one of its
+// blocks cannot leave it without going below min_size (P1); the askers of a
+// stage are a bit per label plus a list in order of asking.  When a sweep
+// commits nothing, merge_pass settles them all at once.
+
+__device__ __forceinline__ void merge_ask(const Job &J, int32_t a, int32_t *s_nreq)
+{
+    const uint32_t bit = 1u << (a & 31);
+    if (!(atomicOr(&J.mreq[a >> 5], bit) & bit)) J.mlist[atomicAdd(s_nreq, 1)] = a;
+}
+
+// n |c|^2 - 2^(F+1) c S for one component: the part of the sum over a
+// superpixel's pixels of (2^F v - c)^2 that depends on the mean c.
+__device__ __forceinline__ __int128 fit_term(int64_t c, int64_t S, int64_t n, int F)
+{
+    return (__int128)n * c * c - ((__int128)2 << F) * c * S;
+}
+
+// Energy change of Eq. (1) when m is merged into k: colour and position
+// terms re-fitted to the union's fixed-point means (rounded half up), and
+// len shared boundary pixel pairs that stop being boundary.  Exact.
+__device__ __forceinline__ __int128 merge_cost(const int64_t *st, const int32_t *mn, int m, int k, int64_t len, const Sched &sc)
+{
+    const int F = sc.F;
+    const int64_t *rm = st + 6 * (int64_t)m, *rk = st + 6 * (int64_t)k;
+    const int64_t nm = rm[0], nk = rk[0], nu = nm + nk;
+    __int128 dc = 0, dp = 0;
+#pragma unroll
+    for (int j = 0; j < 5; j++) {
+        const int64_t Su = rm[1 + j] + rk[1 + j];
+        const int64_t cu = ((Su << (F + 1)) + nu) / (2 * nu);
+        const __int128 d = fit_term(cu, Su, nu, F) - fit_term(mn[MN_STRIDE * m + j], rm[1 + j], nm, F) -
+                           fit_term(mn[MN_STRIDE * k + j], rk[1 + j], nk, F);
+        if (j < 3) dc += d;
+        else dp += d;
+    }
+    return (__int128)sc.w_col * dc + (__int128)sc.w_pos * dp - (__int128)sc.w_bnd * ((__int128)len << (2 * F));
+}
+
+// One merge pass, by the whole workgroup; returns the number of merges.
+// Askers still below min_size + B^2 pixels are candidates.  A candidate's
+// blocks lie within n - 1 pixels of its centroid (a 4-connected set of n
+// pixels), so its window of blocks is scanned for the labels 4-adjacent to
+// it and their shared lengths (MERGE_NB slots per candidate filled with
+// atomic compare-and-swap; a full set means no pick).  Each candidate picks
+// the adjacent label of least merge_cost with an active pair and a merged
+// size within max_size (ties to the smaller label); it leaves when its pick
+// picked nothing or picked it back with a smaller label; per target the
+// smallest leaving label merges.  Merges are then disjoint pairs: the sums
+// move in parallel and the merged blocks go to the changed list.  mstate
+// bits: 1 not a candidate, 2 slots full, 4 leaves, 8 merges.
+__device__ __forceinline__ int merge_pass(const Job &J, int64_t *st, int32_t *mn, int32_t *L, int B,
+                                                    int nbx, int nby, const Sched &sc, const GateView &gv,
+                                                    int32_t *s_nreq, int32_t *s_nchg, int32_t *s_merged,
+                                                    int32_t *l_chg, int capx, int tid, int nt)
+{
+    const int nreq = *s_nreq;
+    // candidates, their windows, empty slots
+    for (int r = tid; r < nreq; r += nt) {
+        const int32_t m = J.mlist[r];
+        const int64_t *rm = st + 6 * (int64_t)m;
+        const int64_t n = rm[0];
+        bool cand = n > 0 && n < sc.min_size + (int64_t)B * B;
+        for (int j = 0; j < MERGE_NB; j++) {
+            J.mkey[MERGE_NB * r + j] = -1;
+            J.mlen[MERGE_NB * r + j] = 0;
+        }
+        if (cand) {
+            const int64_t x0 = max((int64_t)0, rm[4] / n - (n - 1));
+            const int64_t x1 = min((int64_t)J.W - 1, (rm[4] + n - 1) / n + (n - 1));
+            const int64_t y0 = max((int64_t)0, rm[5] / n - (n - 1));
+            const int64_t y1 = min((int64_t)J.H - 1, (rm[5] + n - 1) / n + (n - 1));
+            // sums consistent with the labels always give a non-empty window
+            cand = x0 <= x1 && y0 <= y1;
+            J.mbox[r] = make_int4((int)(x0 / B), (int)(y0 / B), (int)(x1 / B), (int)(y1 / B));
+        }
+        J.mstate[r] = cand ? 0 : 1;
+    }
+    if (tid == 0) *s_merged = 0;
+    wg_sync();
+    // shared boundary lengths with the adjacent labels
+    for (int r = 0; r < nreq; r++) {
+        if (J.mstate[r] != 0) continue;   // uniform
+        const int32_t m = J.mlist[r];
+        const int4 bb = J.mbox[r];
+        const int ww = bb.z - bb.x + 1;
+        const int64_t cnt = (int64_t)ww * (bb.w - bb.y + 1);
+        int32_t *keys = J.mkey + MERGE_NB * r;
+        int32_t *lens = J.mlen + MERGE_NB * r;
+        for (int64_t i = tid; i < cnt; i += nt) {
+            const int bx = bb.x + (int)(i % ww), by = bb.y + (int)(i / ww);
+            const int64_t bi = (int64_t)by * nbx + bx;
+            if (L[bi] != m) continue;
+            const Geo g = block_geo(bx, by, B, J.W, J.H);
+            const int32_t nl[4] = {bx > 0 ? L[bi - 1] : -1, bx + 1 < nbx ? L[bi + 1] : -1,
+                                   by > 0 ? L[bi - nbx] : -1, by + 1 < nby ? L[bi + nbx] : -1};
+            const int el[4] = {g.h, g.h, g.w, g.w};
+            for (int d = 0; d < 4; d++) {
+                const int32_t k = nl[d];
+                if (k < 0 || k == m) continue;
+                int j = 0;
+                for (; j < MERGE_NB; j++) {
+                    const int32_t old = atomicCAS(&keys[j], -1, k);
+                    if (old == -1 || old == k) {
+                        atomicAdd(&lens[j], el[d]);
+                        break;
+                    }
+                }
+                if (j == MERGE_NB) atomicOr(&J.mstate[r], 2);
+            }
+        }
+    }
+    wg_sync();
+    // picks (Eq. (4) under the size bound of Eq. (5))
+    for (int r = tid; r < nreq; r += nt) {
+        if (J.mstate[r] != 0) continue;
+        const int32_t m = J.mlist[r];
+        const int64_t nm = st[6 * (int64_t)m];
+        int32_t best = -1;
+        __int128 bc = 0;
+        for (int j = 0; j < MERGE_NB; j++) {
+            const int32_t k = J.mkey[MERGE_NB * r + j];
+            if (k < 0) break;
+            if (nm + st[6 * (int64_t)k] > sc.max_size || !pair_on(gv, m, k)) continue;
+            const __int128 c = merge_cost(st, mn, m, k, J.mlen[MERGE_NB * r + j], sc);
+            if (best < 0 || c < bc || (c == bc && k < best)) {
+                best = k;
+                bc = c;
+            }
+        }
+        J.mpick[m] = best;
+    }
+    wg_sync();
+    // who leaves, and the smallest leaving label per target
+    for (int r = tid; r < nreq; r += nt) {
+        const int32_t m = J.mlist[r];
+        const int32_t t = J.mstate[r] == 0 ? J.mpick[m] : -1;
+        if (t < 0) continue;
+        const int32_t tt = J.mpick[t];
+        if (tt < 0 || (tt == m && m > t)) {
+            atomicMin(&J.mwin[t], m);
+            J.mstate[r] = 4;
+        }
+    }
+    wg_sync();
+    // merges: each target absorbs one superpixel and none leaves, so the
+    // rows touched here are distinct
+    for (int r = tid; r < nreq; r += nt) {
+        if (J.mstate[r] != 4) continue;
+        const int32_t m = J.mlist[r], t = J.mpick[m];
+        if (J.mwin[t] != m) continue;
+        J.mstate[r] = 8;
+        int64_t *rt = st + 6 * (int64_t)t, *rm = st + 6 * (int64_t)m;
+        for (int j = 0; j < 6; j++) {
+            rt[j] += rm[j];
+            rm[j] = 0;
+        }
+        refresh_sp(st, mn, t, sc);
+        refresh_sp(st, mn, m, sc);
+        atomicAdd(s_merged, 1);
+    }
+    wg_sync();
+    // relabel the merged blocks; they seed the next sweep
+    for (int r = 0; r < nreq; r++) {
+        if (J.mstate[r] != 8) continue;   // uniform
+        const int32_t m = J.mlist[r], t = J.mpick[m];
+        const int4 bb = J.mbox[r];
+        const int ww = bb.z - bb.x + 1;
+        const int64_t cnt = (int64_t)ww * (bb.w - bb.y + 1);
+        for (int64_t i0 = 0; i0 < cnt; i0 += nt) {
+            const int64_t i = i0 + tid;
+            bool hit = false;
+            int32_t bi = 0;
+            if (i < cnt) {
+                bi = (bb.y + (int)(i / ww)) * nbx + bb.x + (int)(i % ww);
+                hit = L[bi] == m;
+                if (hit) L[bi] = t;
+            }
+            const int slot = wave_append(s_nchg, hit);
+            if (slot >= 0) list_put(l_chg, capx, J.changed, 0, slot, bi);
+        }
+    }
+    wg_sync();
+    // clear the askers and the per-label pick state
+    for (int r = tid; r < nreq; r += nt) {
+        const int32_t m = J.mlist[r];
+        atomicAnd(&J.mreq[m >> 5], ~(1u << (m & 31)));
+        const int32_t t = J.mpick[m];
+        if (t >= 0) J.mwin[t] = INT32_MAX;
+    }
+    wg_sync();
+    for (int r = tid; r < nreq; r += nt) J.mpick[J.mlist[r]] = -1;
+    const int merged = *s_merged;
+    wg_sync();
+    if (tid == 0) *s_nreq = 0;
+    wg_sync();
+    return merged;
+}
+
 // Accumulators of one superpixel in the LDS window of the gate point.
 struct WinAcc {
     unsigned long long q[3], ed2;
@@ -503,7 +704,7 @@ __device__ __attribute__((noinline)) void gate_point(const Job &J, const int64_t
     wg_sync();
 }
 
-template <bool LDS, int GM>
+template <bool LDS, int GM, bool MERGE>
 __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, Sched sc, LdsPlan lp,
                                                   int s_begin, int s_end, int flags,
                                                   const uint32_t *__restrict__ lut_g)
@@ -511,8 +712,8 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
     extern __shared__ __align__(16) char smem[];
     __shared__ uint32_t s_lut[8];
     __shared__ int32_t s_cnt[9];
-    __shared__ int32_t s_nprop, s_nchg;
-    __shared__ unsigned long long s_ctr[5];   // active proposals commits skip_min skip_topo
+    __shared__ int32_t s_nprop, s_nchg, s_nreq, s_merged;
+    __shared__ unsigned long long s_ctr[6];   // active proposals commits skip_min skip_topo merges
 
     const Job &J = jobs[blockIdx.x];
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -548,8 +749,16 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
     if (tid == 0) {
         s_nprop = 0;
         s_nchg = 0;
+        s_nreq = 0;
     }
     for (int64_t i = tid; i < 2 * (int64_t)K; i += nt) fl[i] = 0;
+    if (MERGE) {
+        for (int64_t i = tid; i < K; i += nt) {
+            J.mpick[i] = -1;
+            J.mwin[i] = INT32_MAX;
+        }
+        for (int i = tid; i < (K + 31) / 32; i += nt) J.mreq[i] = 0;
+    }
     if (s_end > s_begin) {
         // visit stamps are unique per (stage, sweep) of this launch: cleared
         // once, for the largest stage whose blocks the LDS bitmap cannot cover
@@ -629,7 +838,7 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
         const bool use_bm = (int64_t)lp.bm_words * 32 >= nb;
         const bool use_f64 = sc.f64[s] != 0;
         if (tid < 9) s_cnt[tid] = 0;
-        if (tid < 5) s_ctr[tid] = 0;
+        if (tid < 6) s_ctr[tid] = 0;
         wg_sync();
         if (s > 0) {
             // split: each block inherits the label of the block that holds it.
@@ -731,6 +940,7 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                         m = g.m;
                         if ((int64_t)mn[MN_STRIDE * a + 5] - g.m < sc.min_size) {
                             smin = true;
+                            if (MERGE) merge_ask(J, a, &s_nreq);
                         } else {
                             uint32_t mask = 0;
 #pragma unroll
@@ -888,8 +1098,17 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
             const int commits = s_nchg;
             if (tid == 0) s_ctr[2] += (unsigned long long)commits;
             if (commits == 0) {
-                converged = 1;
-                break;
+                // a quiet sweep: pending merges go now, and the merged
+                // blocks seed the next sweep like committed moves
+                int merged = 0;
+                if (MERGE && s_nreq > 0)
+                    merged = merge_pass(J, st, mn, L, B, nbx, nby, sc, gv, &s_nreq, &s_nchg, &s_merged, l_chg, capx,
+                                        tid, nt);
+                if (merged == 0) {
+                    converged = 1;
+                    break;
+                }
+                if (tid == 0) s_ctr[5] += (unsigned long long)merged;
             }
             // next boundary set: eligible blocks within one block of a change
             const int nchg = s_nchg;
@@ -931,6 +1150,14 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
         }
         if (n_smin) atomicAdd(&s_ctr[3], (unsigned long long)n_smin);
         if (n_stopo) atomicAdd(&s_ctr[4], (unsigned long long)n_stopo);
+        if (MERGE) {
+            // asks do not outlive the stage
+            const int nreq = s_nreq;
+            for (int r = tid; r < nreq; r += nt) {
+                const int32_t m = J.mlist[r];
+                atomicAnd(&J.mreq[m >> 5], ~(1u << (m & 31)));
+            }
+        }
         wg_sync();
         if (tid == 0) {
             rapid_stage_report r;
@@ -943,8 +1170,10 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
             r.commits = (int64_t)s_ctr[2];
             r.skip_min = (int64_t)s_ctr[3];
             r.skip_topo = (int64_t)s_ctr[4];
+            r.merges = (int64_t)s_ctr[5];
             J.rep[s] = r;
             s_nchg = 0;
+            s_nreq = 0;
         }
         wg_sync();
     }
@@ -1002,10 +1231,16 @@ hipError_t launch_refine(const Job *jobs_dev, int n_jobs, const Sched &sc, const
                          hipStream_t stream)
 {
     typedef void (*Kern)(const Job *, Sched, LdsPlan, int, int, int, const uint32_t *);
-    static const Kern table[2][3] = {{k_refine<false, GM_NONE>, k_refine<false, GM_BITS>, k_refine<false, GM_FUSED>},
-                                     {k_refine<true, GM_NONE>, k_refine<true, GM_BITS>, k_refine<true, GM_FUSED>}};
+    // instantiations: statistics in LDS or not, gate mode, merge on underflow
+    static const Kern table[2][3][2] = {
+        {{k_refine<false, GM_NONE, false>, k_refine<false, GM_NONE, true>},
+         {k_refine<false, GM_BITS, false>, k_refine<false, GM_BITS, true>},
+         {k_refine<false, GM_FUSED, false>, k_refine<false, GM_FUSED, true>}},
+        {{k_refine<true, GM_NONE, false>, k_refine<true, GM_NONE, true>},
+         {k_refine<true, GM_BITS, false>, k_refine<true, GM_BITS, true>},
+         {k_refine<true, GM_FUSED, false>, k_refine<true, GM_FUSED, true>}}};
     const int gm = (flags & FLAG_GATE) ? GM_FUSED : lp.gate_words > 0 ? GM_BITS : GM_NONE;
-    const Kern fn = table[lp.stats_lds ? 1 : 0][gm];
+    const Kern fn = table[lp.stats_lds ? 1 : 0][gm][sc.merge ? 1 : 0];
     hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp.total);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fn, dim3((unsigned)n_jobs), dim3(threads), lp.total, stream, jobs_dev, sc, lp, s_begin,

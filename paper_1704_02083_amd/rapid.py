@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # RAPID_LIB selects another build of the same C-ABI (e.g. an instrumented one)
 LIB_PATH = os.environ.get("RAPID_LIB") or os.path.join(_HERE, "librapid.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 MAX_LEVELS = 4
 MAX_STAGES = 8
 
@@ -49,7 +49,7 @@ class Params(C.Structure):
         ("factor", C.c_int32 * MAX_LEVELS), ("n_stages", C.c_int32 * MAX_LEVELS),
         ("stages", (C.c_int32 * MAX_STAGES) * MAX_LEVELS),
         ("gate_level", C.c_int32), ("frac_bits", C.c_int32), ("max_sweeps", C.c_int32),
-        ("gate_rule", C.c_int32),
+        ("gate_rule", C.c_int32), ("merge", C.c_int32), ("reserved", C.c_int32),
         ("min_size", C.c_int64), ("max_size", C.c_int64),
         ("w_col", C.c_int64), ("w_pos", C.c_int64), ("w_bnd", C.c_int64),
     ]
@@ -64,7 +64,8 @@ class Image(C.Structure):
 class StageReport(C.Structure):
     _fields_ = [("level", C.c_int32), ("block", C.c_int32), ("sweeps", C.c_int32),
                 ("converged", C.c_int32), ("active", C.c_int64), ("proposals", C.c_int64),
-                ("commits", C.c_int64), ("skip_min", C.c_int64), ("skip_topo", C.c_int64)]
+                ("commits", C.c_int64), ("skip_min", C.c_int64), ("skip_topo", C.c_int64),
+                ("merges", C.c_int64)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -165,6 +166,7 @@ def make_params(d: dict) -> Params:
     p.frac_bits = int(d.get("frac_bits", 4))
     p.max_sweeps = int(d.get("max_sweeps", 64))
     p.gate_rule = GATE_RULES[d.get("gate_rule", "either")]
+    p.merge = int(bool(d.get("merge", False)))
     p.min_size = int(d["min_size"])
     p.max_size = int(d["max_size"])
     p.w_col = int(d["w_col"])
