@@ -150,6 +150,13 @@ def main():
     ap.add_argument("--grain", type=int, default=1,
                     help="H&E workloads: stop the schedule at this effective block size (the paper's "
                          "'grain'; 4 = its 4x4 setting)")
+    ap.add_argument("--merge", action="store_true",
+                    help="batch and single256: merge on underflow (Sec. 3.1, Eqs. (4)-(5)); the "
+                         "line also reports the merges and the boundary recall against the plain labels")
+    ap.add_argument("--reuse-baseline", action="store_true",
+                    help="he4096: also time the level-by-level path with the statistics carried "
+                         "across levels (Sec. 3.2) against recounting them from the pixels at "
+                         "every level (multi-scale CTFTPS without reuse)")
     ap.add_argument("--cpu-sample", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -191,6 +198,9 @@ def main():
         return bench_roi(args)
 
     imgs, p, desc = workload(args.workload)
+    if args.merge:
+        p = dict(p, merge=True)
+        desc += ", merge on underflow"
     print("bench: workload %s, %d images generated" % (args.workload, len(imgs)), file=sys.stderr,
           flush=True)
     rgbs = [torch.from_numpy(im).cuda() for im in imgs]
@@ -232,7 +242,7 @@ def main():
     alg = refine_alg_bytes(imgs, reps)
     achieved = alg / (avg_refine * 1e-3) / 1e9
     src_hash = kernel_source_hash()
-    traffic = profile_traffic("k_refine", args.workload, src_hash)
+    traffic = profile_traffic("k_refine", args.workload + ("_merge" if args.merge else ""), src_hash)
     out = {
         "metric": METRIC,
         "value": round(pixels * args.steps / dt / 1e6, 3),
@@ -247,7 +257,7 @@ def main():
         "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": desc, "images": len(imgs), "pixels": pixels,
-                   "superpixels_per_image": p["K"], "path": "plain"},
+                   "superpixels_per_image": p["K"], "path": "plain+merge" if args.merge else "plain"},
         "roofline": {
             "bound": "hbm",
             "kernel": "k_refine",
@@ -261,6 +271,23 @@ def main():
             "source_hash": src_hash,
         },
     }
+    if args.merge:
+        # what the merges did: superpixels merged away, and how many of the
+        # plain segmentation's boundary pixels the merged one still has
+        # within 2 px (boundary recall, Sec. 4.2)
+        merges = sum(r["merges"] for rep in reps for r in rep)
+        plain = [torch.empty_like(l) for l in labels]
+        if len(rgbs) == 1:
+            ctx.segment(rgbs[0], dict(p, merge=False), labels=plain[0], report=False)
+        else:
+            ctx.segment_batch(rgbs, dict(p, merge=False), labels=plain, report=False)
+        nb = nm = 0
+        for a, b in zip(plain, labels):
+            _, x, y = ctx.boundary_miss(a, b, radius=2, counts=False)
+            nb += x
+            nm += y
+        out["merge"] = {"merges": int(merges), "merges_per_image": round(merges / len(imgs), 2),
+                        "boundary_recall_vs_plain": round(1.0 - nm / max(nb, 1), 5)}
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(imgs, p, args.cpu_sample)
@@ -513,8 +540,46 @@ def bench_he(args):
     }
     if args.gated:
         out["gated"] = bench_gated(args, ctx, rgb, labels, plain, W, H, dt)
+    if args.reuse_baseline:
+        if args.workload != "he4096":
+            raise SystemExit("--reuse-baseline applies to he4096")
+        out["reuse"] = bench_reuse(ctx, rgb, p, plain)
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def bench_reuse(ctx, rgb, p, plain, reps: int = 3):
+    """Level by level through the state API: statistics carried from level
+    to level (Sec. 3.2) against the same run with the statistics recounted
+    from the pixels at every level (labels mapped to pixels and back), as
+    multi-scale CTFTPS recomputes them.  The sums are exact either way, so
+    both must give the plain labels."""
+    import torch
+    n_levels = len(p["levels"])
+
+    def run(recount):
+        st = ctx.state(rgb, p)
+        for l in range(n_levels):
+            if recount and l > 0:
+                lab, _ = st.export()
+                st.import_(l, lab, None)
+            st.refine_level(l, report=False)
+        lab, _ = st.export()
+        st.close()
+        return lab
+
+    out = {}
+    for name, recount in (("reuse", False), ("recount", True)):
+        run(recount)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            lab = run(recount)
+        torch.cuda.synchronize()
+        out[name + "_ms"] = round((time.perf_counter() - t0) * 1e3 / reps, 3)
+        out[name + "_identical_to_plain"] = bool((lab == plain).all().item())
+    out["recount_over_reuse"] = round(out["recount_ms"] / out["reuse_ms"], 4)
+    return out
 
 
 if __name__ == "__main__":
