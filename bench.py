@@ -157,6 +157,9 @@ def main():
                     help="he4096: also time the level-by-level path with the statistics carried "
                          "across levels (Sec. 3.2) against recounting them from the pixels at "
                          "every level (multi-scale CTFTPS without reuse)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the default launch shape instead of the autotuned one (the first "
+                         "warm-up step tunes)")
     ap.add_argument("--cpu-sample", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -205,7 +208,7 @@ def main():
           flush=True)
     rgbs = [torch.from_numpy(im).cuda() for im in imgs]
     labels = [torch.empty(im.shape[:2], dtype=torch.int32, device="cuda") for im in imgs]
-    ctx = rapid.Context(0, timing=True)
+    ctx = rapid.Context(0, timing=True, autotune=not args.no_autotune)
     pixels = sum(im.shape[0] * im.shape[1] for im in imgs)
 
     def step():
@@ -214,7 +217,8 @@ def main():
         else:
             ctx.segment_batch(rgbs, p, labels=labels, report=False)
 
-    for _ in range(args.warmup):
+    # with the autotuner on, the first call of a shape tunes: never timed
+    for _ in range(max(args.warmup, 0 if args.no_autotune else 1)):
         step()
     torch.cuda.synchronize()
     # the timed steps run back to back (launches queue while the GPU works)
@@ -230,6 +234,9 @@ def main():
     for _ in range(args.steps):
         step()
         refine_ms.append(ctx.last_timings()["refine_ms"])
+    tm = ctx.last_timings()
+    shape = {"threads": tm["threads"], "stats_lds": tm["stats_lds"], "pyramid_in_launch": tm["pyramid"],
+             "autotuned": not args.no_autotune}
 
     # counters of the same (deterministic) work, from one untimed call
     if len(rgbs) == 1:
@@ -270,6 +277,7 @@ def main():
             "avg_launch_ms": round(avg_refine, 4),
             "source_hash": src_hash,
         },
+        "launch_shape": shape,
     }
     if args.merge:
         # what the merges did: superpixels merged away, and how many of the
@@ -479,7 +487,7 @@ def bench_he(args):
         desc += ", grain %d (stages of effective block size >= %d only)" % (args.grain, args.grain)
         if args.gated:
             raise SystemExit("--grain applies to the plain path only")
-    ctx = rapid.Context(0, timing=True)
+    ctx = rapid.Context(0, timing=True, autotune=not args.no_autotune)
     if args.workload in ("slide", "slide65k"):
         W, H, seed = (32768, 32768, 4) if args.workload == "slide" else (65536, 49152, 5)
         rgb = synth_gpu.he_slide(W, H, seed=seed, background=0.4, device="cuda", band=1024)
@@ -515,8 +523,11 @@ def bench_he(args):
             ref_ms.append(ctx.last_timings()["refine_ms"])
         return dt, ref_ms
 
-    steps, warm = max(1, min(args.steps, 5)), max(0, min(args.warmup, 2))
+    steps, warm = max(1, min(args.steps, 5)), max(0 if args.no_autotune else 1, min(args.warmup, 2))
     dt, ref_ms = timed(lambda: run(), steps, warm)
+    tm = ctx.last_timings()
+    shape = {"threads": tm["threads"], "stats_lds": tm["stats_lds"], "pyramid_in_launch": tm["pyramid"],
+             "autotuned": not args.no_autotune}
     plain = labels.clone()
     # per-stage counters of the same deterministic work, from one untimed call
     if args.workload in ("slide", "slide65k"):
@@ -537,6 +548,7 @@ def bench_he(args):
                      "frac": round(achieved / HBM_PEAK_GBS, 6),
                      "traffic": profile_traffic("k_refine", args.workload, kernel_source_hash()),
                      "alg_bytes_per_launch": alg},
+        "launch_shape": shape,
     }
     if args.gated:
         out["gated"] = bench_gated(args, ctx, rgb, labels, plain, W, H, dt)

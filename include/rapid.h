@@ -52,6 +52,7 @@ typedef struct rapid_ctx rapid_ctx;       /* opaque, library-owned */
 typedef struct rapid_state rapid_state;   /* opaque, library-owned */
 
 #define RAPID_CFG_TIMING 1   /* record HIP events around every kernel launch */
+#define RAPID_CFG_AUTOTUNE 2 /* tune the launch shape per problem shape (below) */
 
 /* rapid_params.gate_rule values */
 #define RAPID_GATE_EITHER 0
@@ -63,7 +64,20 @@ typedef struct {
     int32_t device;        /* HIP device ordinal */
     void *hip_stream;      /* hipStream_t to queue on; NULL = the null stream */
     int32_t flags;         /* RAPID_CFG_* bits */
-    int32_t reserved;
+    int32_t reserved;      /* 0 */
+    /* Autotuning (RAPID_CFG_AUTOTUNE): the first segmentation call of each
+     * problem shape (images, largest W, H and superpixel count, schedule,
+     * gate and merge modes) runs its launch once per candidate shape --
+     * workgroup size 256, 512 or 1024; statistics in LDS or in global
+     * memory when both fit; block-sum pyramid inside the launch or in
+     * separate launches -- and keeps the fastest; later calls of that
+     * shape use it.  Every candidate computes the same labels (the result
+     * never depends on the shape), so tuning costs time only.  Only calls
+     * that start from the image tune (not rapid_refine_level).
+     * autotune_cache: NULL, or a file that holds the choices across
+     * processes: read by rapid_init when present (ignored when written for
+     * another device architecture), rewritten after every new choice. */
+    const char *autotune_cache;
 } rapid_config;
 
 /* Kernel durations of the last segmentation call (context created with
@@ -71,8 +85,12 @@ typedef struct {
 typedef struct {
     float block_sums_ms;   /* block-sum launches before the refinement
                               kernel (0 when that kernel builds the
-                              pyramids itself: 128 jobs or more)      */
+                              pyramids itself)                        */
     float refine_ms;       /* the refinement kernel (all stages)   */
+    int32_t threads;       /* launch shape of that call: workgroup size, */
+    int32_t stats_lds;     /* statistics in LDS (1) or global (0),       */
+    int32_t pyramid;       /* pyramid inside the refinement launch (1)   */
+    int32_t tuned;         /* 1 when this call ran the autotuner         */
 } rapid_timings;
 
 /* Method parameters, all integers (the paper gives no values for the
@@ -162,7 +180,10 @@ typedef struct {
 
 /* Create a context on cfg->device: builds the 256-entry simple-point table
  * of the topology term (Eq. (1), E_topo) and uploads it.  *out receives the
- * context; rapid_destroy releases it. */
+ * context; rapid_destroy releases it.  Environment: RAPID_THREADS=n (64 ..
+ * 1024, a multiple of 64) fixes the workgroup size; RAPID_SHAPE=t,l,p fixes
+ * the whole launch shape (workgroup size, statistics in LDS when they fit,
+ * pyramid inside the launch) and bypasses the autotuner. */
 rapid_status rapid_init(const rapid_config *cfg, rapid_ctx **out);
 void rapid_destroy(rapid_ctx *ctx);   /* NULL-safe; waits for queued work */
 

@@ -6,8 +6,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "rapid_internal.h"
@@ -15,13 +17,33 @@
 
 using namespace rapid;
 
+// Launch shape of the refinement: workgroup size, statistics in LDS (when
+// they fit) or in global memory, block-sum pyramid inside the launch or in
+// separate launches.  The labels never depend on it.
+struct LaunchShape {
+    int threads = 1024;
+    int stats_lds = 1;
+    int pyramid = 1;
+    float ms = 0.0f;   // autotuner: time of the choice
+};
+
 struct rapid_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     uint32_t *lut_dev = nullptr;
     size_t lds_limit = 0;
     int threads = 1024;
+    bool threads_forced = false;   // RAPID_THREADS fixes the workgroup size
     bool verbose = false;
+    // autotuner: chosen shape per problem shape, optional cache file
+    bool autotune = false;
+    std::string cache_path, arch;
+    std::map<std::string, LaunchShape> tuned;
+    hipEvent_t tev[2] = {nullptr, nullptr};
+    LaunchShape last;              // shape of the last refinement launch
+    int last_tuned = 0;
+    bool shape_forced = false;     // RAPID_SHAPE=threads,stats_lds,pyramid fixes the shape
+    LaunchShape forced;
     // scratch pool for rapid_segment / rapid_segment_batch
     char *pool = nullptr;
     size_t pool_size = 0;
@@ -359,7 +381,14 @@ rapid_status dev_err(hipError_t e) { return e == hipSuccess ? RAPID_OK : RAPID_E
 // Carve the LDS of the refinement kernel: statistics first (when they fit
 // with room to spare), then the class lists, proposals, the frontier visit
 // bitmap and the changed list, each within a share of what remains.
-LdsPlan plan_lds(size_t limit, int32_t Kmax, int64_t nbF, bool gated)
+// Whether the statistics of Kmax superpixels fit LDS beside the work space.
+bool stats_fit_lds(size_t limit, int32_t Kmax, bool gated)
+{
+    const size_t gwords = gated ? ((size_t)Kmax + 31) / 32 : 0;
+    return (size_t)Kmax * LDS_PER_SP + 48 * 1024 + 4 * gwords <= limit;
+}
+
+LdsPlan plan_lds(size_t limit, int32_t Kmax, int64_t nbF, bool gated, bool stats_lds)
 {
     LdsPlan p;
     std::memset(&p, 0, sizeof p);
@@ -367,7 +396,7 @@ LdsPlan plan_lds(size_t limit, int32_t Kmax, int64_t nbF, bool gated)
     size_t off = 0;
     const size_t gwords = gated ? ((size_t)Kmax + 31) / 32 : 0;   // at most MAX_GATE_WORDS (run_jobs)
     size_t stats = (size_t)Kmax * LDS_PER_SP;
-    if (stats + 48 * 1024 + 4 * gwords <= limit) {
+    if (stats_lds && stats_fit_lds(limit, Kmax, gated)) {
         p.stats_lds = 1;
         off = a16(stats);
     }
@@ -392,6 +421,108 @@ LdsPlan plan_lds(size_t limit, int32_t Kmax, int64_t nbF, bool gated)
     return p;
 }
 
+// ---------------------------------------------------------- autotuner
+
+// Problem shape: jobs, largest image and superpixel count, schedule, gate
+// and merge modes, which stages run.
+std::string shape_key(const std::vector<Job> &jobs, const Sched &sc, int s_begin, int s_end, int flags,
+                      int32_t Kmax, bool gated)
+{
+    int Wm = 0, Hm = 0;
+    for (const Job &J : jobs) {
+        Wm = std::max(Wm, J.W);
+        Hm = std::max(Hm, J.H);
+    }
+    std::string k = "n" + std::to_string(jobs.size()) + "_W" + std::to_string(Wm) + "_H" + std::to_string(Hm) +
+                    "_K" + std::to_string(Kmax) + "_B";
+    for (int s = 0; s < sc.n_stages; s++) k += (s ? "." : "") + std::to_string(sc.B[s]);
+    k += "_s" + std::to_string(s_begin) + "-" + std::to_string(s_end) + "_f" + std::to_string(flags) + "_g" +
+         std::to_string(gated ? 1 : 0) + "_m" + std::to_string(sc.merge) + "_r" + std::to_string(sc.gate_rule);
+    return k;
+}
+
+// Cache file: one JSON object, one entry per line:
+//   {"rapid_autotune": 1, "arch": "<gcnArchName>", "entries": {
+//   "<key>": [threads, stats_lds, pyramid, ms],
+//   ...
+//   }}
+void cache_load(rapid_ctx *ctx)
+{
+    if (ctx->cache_path.empty()) return;
+    FILE *f = std::fopen(ctx->cache_path.c_str(), "r");
+    if (!f) return;
+    char line[2048];
+    bool arch_ok = false;
+    while (std::fgets(line, sizeof line, f)) {
+        if (std::strstr(line, "\"rapid_autotune\"")) {
+            const char *a = std::strstr(line, "\"arch\": \"");
+            arch_ok = a && std::strncmp(a + 9, ctx->arch.c_str(), ctx->arch.size()) == 0 &&
+                      a[9 + ctx->arch.size()] == '"';
+            continue;
+        }
+        if (!arch_ok) break;
+        char key[1024];
+        LaunchShape sh;
+        if (std::sscanf(line, " \"%1023[^\"]\": [%d, %d, %d, %f]", key, &sh.threads, &sh.stats_lds, &sh.pyramid,
+                        &sh.ms) == 5 &&
+            sh.threads >= 64 && sh.threads <= 1024 && sh.threads % 64 == 0)
+            ctx->tuned[key] = sh;
+    }
+    std::fclose(f);
+}
+
+void cache_save(const rapid_ctx *ctx)
+{
+    if (ctx->cache_path.empty()) return;
+    const std::string tmp = ctx->cache_path + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "{\"rapid_autotune\": 1, \"arch\": \"%s\", \"entries\": {\n", ctx->arch.c_str());
+    size_t i = 0;
+    for (const auto &e : ctx->tuned)
+        std::fprintf(f, "\"%s\": [%d, %d, %d, %.4f]%s\n", e.first.c_str(), e.second.threads, e.second.stats_lds,
+                     e.second.pyramid, e.second.ms, ++i < ctx->tuned.size() ? "," : "");
+    std::fprintf(f, "}}\n");
+    std::fclose(f);
+    std::rename(tmp.c_str(), ctx->cache_path.c_str());
+}
+
+// Block sums (when the launch does not build the pyramid) and the
+// refinement launch with shape sh; jobs are on the device already.
+rapid_status launch_shape(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched &sc, int s_begin, int s_end,
+                          int flags, int32_t Kmax, int64_t nbF_max, bool gated, const LaunchShape &sh,
+                          hipEvent_t e0, hipEvent_t e1, hipEvent_t e2)
+{
+    const size_t n = jobs.size();
+    if (e0) HIPCHK(hipEventRecord(e0, ctx->stream));
+    if (flags & FLAG_INIT) {
+        if (sh.pyramid) {
+            flags |= FLAG_PYRAMID;
+        } else {
+            // chip-wide launches, one per stage with B >= 2
+            for (int s = 0; s < sc.n_stages; s++) {
+                const int B = sc.B[s];
+                if (B < 2) continue;
+                int64_t nb = 0;
+                for (const Job &J : jobs) nb = std::max<int64_t>(nb, (int64_t)((J.W + B - 1) / B) * ((J.H + B - 1) / B));
+                HIPCHK(launch_block_sums(ctx->jobs_dev, (int)n, s, B, nb, ctx->stream));
+            }
+        }
+    }
+    LdsPlan lp = plan_lds(ctx->lds_limit, Kmax, nbF_max, gated, sh.stats_lds != 0);
+    if (ctx->verbose)
+        std::fprintf(stderr,
+                     "rapid: threads %d, lds limit %zu, stats_lds %d, capl %d capp %d capx %d bm_words %d "
+                     "gate_words %d total %u\n",
+                     sh.threads, ctx->lds_limit, lp.stats_lds, lp.capl, lp.capp, lp.capx, lp.bm_words,
+                     lp.gate_words, lp.total);
+    if (e1) HIPCHK(hipEventRecord(e1, ctx->stream));
+    HIPCHK(launch_refine(ctx->jobs_dev, (int)n, sc, lp, s_begin, s_end, flags, ctx->lut_dev, sh.threads,
+                         ctx->stream));
+    if (e2) HIPCHK(hipEventRecord(e2, ctx->stream));
+    return RAPID_OK;
+}
+
 rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched &sc, int s_begin,
                       int s_end, int flags, int32_t Kmax, int64_t nbF_max)
 {
@@ -410,46 +541,72 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
         if (hipHostMalloc(&ctx->jobs_pinned, cap * sizeof(Job)) != hipSuccess) return RAPID_ENOMEM;
         ctx->jobs_cap = cap;
     }
+    // the gate bits live in LDS during the gated stages
+    bool gated = (flags & FLAG_GATE) != 0;
+    if (s_end > sc.gate_stage)
+        for (const Job &J : jobs) gated |= J.gate != nullptr;
+    if (gated && ((int64_t)Kmax + 31) / 32 > MAX_GATE_WORDS) return RAPID_EINVAL;
     // the previous upload from the staging buffer must have completed
     HIPCHK(hipEventSynchronize(ctx->jobs_copied));
     std::memcpy(ctx->jobs_pinned, jobs.data(), n * sizeof(Job));
     HIPCHK(hipMemcpyAsync(ctx->jobs_dev, ctx->jobs_pinned, n * sizeof(Job), hipMemcpyHostToDevice,
                           ctx->stream));
     HIPCHK(hipEventRecord(ctx->jobs_copied, ctx->stream));
-    if (ctx->timing) HIPCHK(hipEventRecord(ctx->ev[0], ctx->stream));
-    if (flags & FLAG_INIT) {
-        if ((int)n >= PYRAMID_MIN_JOBS) {
-            flags |= FLAG_PYRAMID;   // enough workgroups to fill the chip
-        } else {
-            // few jobs: chip-wide launches, one per stage with B >= 2
-            for (int s = 0; s < sc.n_stages; s++) {
-                const int B = sc.B[s];
-                if (B < 2) continue;
-                int64_t nb = 0;
-                for (const Job &J : jobs) nb = std::max<int64_t>(nb, (int64_t)((J.W + B - 1) / B) * ((J.H + B - 1) / B));
-                HIPCHK(launch_block_sums(ctx->jobs_dev, (int)n, s, B, nb, ctx->stream));
-            }
+
+    // launch shape: the tuned one for this problem shape, else the default
+    // (enough jobs to fill the chip: the pyramid inside the launch)
+    const bool fits = stats_fit_lds(ctx->lds_limit, Kmax, gated);
+    LaunchShape sh;
+    sh.threads = ctx->threads;
+    sh.stats_lds = fits ? 1 : 0;
+    sh.pyramid = (int)n >= PYRAMID_MIN_JOBS ? 1 : 0;
+    const std::string key = shape_key(jobs, sc, s_begin, s_end, flags, Kmax, gated);
+    auto it = ctx->tuned.find(key);
+    ctx->last_tuned = 0;
+    if (ctx->shape_forced) {
+        sh = ctx->forced;
+    } else if (it != ctx->tuned.end()) {
+        sh = it->second;
+        if (ctx->threads_forced) sh.threads = ctx->threads;
+    } else if (ctx->autotune && (flags & FLAG_INIT)) {
+        // a call that starts from the image can be repeated: time it once
+        // per candidate shape (the labels are the same for all of them)
+        for (int i = 0; i < 2; i++)
+            if (!ctx->tev[i]) HIPCHK(hipEventCreate(&ctx->tev[i]));
+        const int thr_all[3] = {256, 512, 1024};
+        LaunchShape best;
+        best.ms = -1.0f;
+        for (int t = 0; t < 3; t++) {
+            if (ctx->threads_forced && thr_all[t] != ctx->threads) continue;
+            for (int l = fits ? 1 : 0; l >= 0; l--)
+                for (int py = 1; py >= 0; py--) {
+                    LaunchShape c;
+                    c.threads = thr_all[t];
+                    c.stats_lds = l;
+                    c.pyramid = py;
+                    rapid_status r = launch_shape(ctx, jobs, sc, s_begin, s_end, flags, Kmax, nbF_max, gated, c,
+                                                  ctx->tev[0], nullptr, ctx->tev[1]);
+                    if (r) return r;
+                    HIPCHK(hipEventSynchronize(ctx->tev[1]));
+                    HIPCHK(hipEventElapsedTime(&c.ms, ctx->tev[0], ctx->tev[1]));
+                    if (best.ms < 0.0f || c.ms < best.ms) best = c;
+                }
         }
+        sh = best;
+        ctx->tuned[key] = best;
+        ctx->last_tuned = 1;
+        cache_save(ctx);
+        if (ctx->verbose)
+            std::fprintf(stderr, "rapid: tuned %s -> threads %d stats_lds %d pyramid %d (%.3f ms)\n", key.c_str(),
+                         best.threads, best.stats_lds, best.pyramid, best.ms);
     }
-    // the gate bits live in LDS during the gated stages
-    bool gated = (flags & FLAG_GATE) != 0;
-    if (s_end > sc.gate_stage)
-        for (const Job &J : jobs) gated |= J.gate != nullptr;
-    if (gated && ((int64_t)Kmax + 31) / 32 > MAX_GATE_WORDS) return RAPID_EINVAL;
-    LdsPlan lp = plan_lds(ctx->lds_limit, Kmax, nbF_max, gated);
-    if (ctx->verbose)
-        std::fprintf(stderr,
-                     "rapid: lds limit %zu, stats_lds %d, capl %d capp %d capx %d bm_words %d gate_words %d "
-                     "total %u\n",
-                     ctx->lds_limit, lp.stats_lds, lp.capl, lp.capp, lp.capx, lp.bm_words, lp.gate_words,
-                     lp.total);
-    if (ctx->timing) HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
-    HIPCHK(launch_refine(ctx->jobs_dev, (int)n, sc, lp, s_begin, s_end, flags, ctx->lut_dev,
-                         ctx->threads, ctx->stream));
-    if (ctx->timing) {
-        HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
-        ctx->timed = true;
-    }
+    if (!fits) sh.stats_lds = 0;
+    ctx->last = sh;
+    rapid_status r = launch_shape(ctx, jobs, sc, s_begin, s_end, flags, Kmax, nbF_max, gated, sh,
+                                  ctx->timing ? ctx->ev[0] : nullptr, ctx->timing ? ctx->ev[1] : nullptr,
+                                  ctx->timing ? ctx->ev[2] : nullptr);
+    if (r) return r;
+    if (ctx->timing) ctx->timed = true;
     return RAPID_OK;
 }
 
@@ -537,9 +694,26 @@ rapid_status rapid_init(const rapid_config *cfg, rapid_ctx **out)
     ctx->verbose = std::getenv("RAPID_VERBOSE") != nullptr;
     if (const char *t = std::getenv("RAPID_THREADS")) {
         int v = std::atoi(t);
-        if (v >= 64 && v <= 1024 && v % 64 == 0) ctx->threads = v;
+        if (v >= 64 && v <= 1024 && v % 64 == 0) {
+            ctx->threads = v;
+            ctx->threads_forced = true;
+        }
+    }
+    if (const char *t = std::getenv("RAPID_SHAPE")) {
+        LaunchShape f;
+        if (std::sscanf(t, "%d,%d,%d", &f.threads, &f.stats_lds, &f.pyramid) == 3 && f.threads >= 64 &&
+            f.threads <= 1024 && f.threads % 64 == 0) {
+            ctx->forced = f;
+            ctx->shape_forced = true;
+        }
     }
     ctx->timing = (cfg->flags & RAPID_CFG_TIMING) != 0;
+    ctx->autotune = (cfg->flags & RAPID_CFG_AUTOTUNE) != 0;
+    ctx->arch = prop.gcnArchName;
+    if (cfg->autotune_cache) {
+        ctx->cache_path = cfg->autotune_cache;
+        cache_load(ctx);
+    }
     if (ctx->timing)
         for (int i = 0; i < 3; i++)
             if (hipEventCreate(&ctx->ev[i]) != hipSuccess) { delete ctx; return RAPID_EDEVICE; }
@@ -569,6 +743,8 @@ void rapid_destroy(rapid_ctx *ctx)
     if (ctx->jobs_copied) (void)hipEventDestroy(ctx->jobs_copied);
     for (int i = 0; i < 3; i++)
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+    for (int i = 0; i < 2; i++)
+        if (ctx->tev[i]) (void)hipEventDestroy(ctx->tev[i]);
     delete ctx;
 }
 
@@ -580,6 +756,10 @@ rapid_status rapid_last_timings(rapid_ctx *ctx, rapid_timings *out)
     HIPCHK(hipEventSynchronize(ctx->ev[2]));
     HIPCHK(hipEventElapsedTime(&out->block_sums_ms, ctx->ev[0], ctx->ev[1]));
     HIPCHK(hipEventElapsedTime(&out->refine_ms, ctx->ev[1], ctx->ev[2]));
+    out->threads = ctx->last.threads;
+    out->stats_lds = ctx->last.stats_lds;
+    out->pyramid = ctx->last.pyramid;
+    out->tuned = ctx->last_tuned;
     return RAPID_OK;
 }
 

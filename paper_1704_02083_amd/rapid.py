@@ -32,15 +32,17 @@ class RapidError(RuntimeError):
 
 
 CFG_TIMING = 1
+CFG_AUTOTUNE = 2
 
 
 class Config(C.Structure):
     _fields_ = [("abi_version", C.c_int32), ("device", C.c_int32), ("hip_stream", C.c_void_p),
-                ("flags", C.c_int32), ("reserved", C.c_int32)]
+                ("flags", C.c_int32), ("reserved", C.c_int32), ("autotune_cache", C.c_char_p)]
 
 
 class Timings(C.Structure):
-    _fields_ = [("block_sums_ms", C.c_float), ("refine_ms", C.c_float)]
+    _fields_ = [("block_sums_ms", C.c_float), ("refine_ms", C.c_float), ("threads", C.c_int32),
+                ("stats_lds", C.c_int32), ("pyramid", C.c_int32), ("tuned", C.c_int32)]
 
 
 class Params(C.Structure):
@@ -240,14 +242,16 @@ def _image(rgb, labels) -> Image:
 class Context:
     """rapid_init / rapid_destroy around one device and stream."""
 
-    def __init__(self, device: int = 0, stream=None, timing: bool = False):
+    def __init__(self, device: int = 0, stream=None, timing: bool = False, autotune: bool = False,
+                 autotune_cache: str | None = None):
         import torch
         self.device = device
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.stream = stream
+        self._cache = autotune_cache.encode() if autotune_cache else None
         cfg = Config(ABI_VERSION, device, C.c_void_p(stream.cuda_stream),
-                     CFG_TIMING if timing else 0, 0)
+                     (CFG_TIMING if timing else 0) | (CFG_AUTOTUNE if autotune else 0), 0, self._cache)
         h = _P()
         _check(_lib.rapid_init(C.byref(cfg), C.byref(h)), "rapid_init")
         self._h = h
@@ -382,7 +386,9 @@ class Context:
     def last_timings(self) -> dict:
         t = Timings()
         _check(_lib.rapid_last_timings(self._h, C.byref(t)), "rapid_last_timings")
-        return {"block_sums_ms": float(t.block_sums_ms), "refine_ms": float(t.refine_ms)}
+        return {"block_sums_ms": float(t.block_sums_ms), "refine_ms": float(t.refine_ms),
+                "threads": int(t.threads), "stats_lds": int(t.stats_lds), "pyramid": int(t.pyramid),
+                "tuned": int(t.tuned)}
 
     def state(self, rgb, params: dict) -> "State":
         return State(self, rgb, params)
