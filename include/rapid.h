@@ -68,8 +68,9 @@ typedef struct {
     /* Autotuning (RAPID_CFG_AUTOTUNE): the first segmentation call of each
      * problem shape (images, largest W, H and superpixel count, schedule,
      * gate and merge modes) runs its launch once per candidate shape --
-     * workgroup size 256, 512 or 1024; statistics in LDS or in global
-     * memory when both fit; block-sum pyramid inside the launch or in
+     * workgroup size 256, 512 or 1024; per-superpixel state all in LDS,
+     * only the means records in LDS, or all in global memory (as far as
+     * they fit); block-sum pyramid inside the launch or in
      * separate launches -- and keeps the fastest; later calls of that
      * shape use it.  Every candidate computes the same labels (the result
      * never depends on the shape), so tuning costs time only.  Only calls
@@ -88,7 +89,8 @@ typedef struct {
                               pyramids itself)                        */
     float refine_ms;       /* the refinement kernel (all stages)   */
     int32_t threads;       /* launch shape of that call: workgroup size, */
-    int32_t stats_lds;     /* statistics in LDS (1) or global (0),       */
+    int32_t stats_lds;     /* per-superpixel state: 1 all in LDS, 2 the
+                              means records in LDS, 0 all global,       */
     int32_t pyramid;       /* pyramid inside the refinement launch (1)   */
     int32_t tuned;         /* 1 when this call ran the autotuner         */
 } rapid_timings;
@@ -182,8 +184,9 @@ typedef struct {
  * of the topology term (Eq. (1), E_topo) and uploads it.  *out receives the
  * context; rapid_destroy releases it.  Environment: RAPID_THREADS=n (64 ..
  * 1024, a multiple of 64) fixes the workgroup size; RAPID_SHAPE=t,l,p fixes
- * the whole launch shape (workgroup size, statistics in LDS when they fit,
- * pyramid inside the launch) and bypasses the autotuner. */
+ * the whole launch shape (workgroup size, residency l as in
+ * rapid_timings.stats_lds when it fits, pyramid inside the launch) and
+ * bypasses the autotuner. */
 rapid_status rapid_init(const rapid_config *cfg, rapid_ctx **out);
 void rapid_destroy(rapid_ctx *ctx);   /* NULL-safe; waits for queued work */
 

@@ -381,25 +381,28 @@ rapid_status dev_err(hipError_t e) { return e == hipSuccess ? RAPID_OK : RAPID_E
 // Carve the LDS of the refinement kernel: statistics first (when they fit
 // with room to spare), then the class lists, proposals, the frontier visit
 // bitmap and the changed list, each within a share of what remains.
-// Whether the statistics of Kmax superpixels fit LDS beside the work space.
-bool stats_fit_lds(size_t limit, int32_t Kmax, bool gated)
+// Residency of the per-superpixel state that fits LDS beside the work
+// space, given the one asked for: 1 (statistics, means, flow), else 2 (the
+// means records), else 0 (all in global memory).
+int lds_residency(size_t limit, int32_t Kmax, bool gated, int want)
 {
     const size_t gwords = gated ? ((size_t)Kmax + 31) / 32 : 0;
-    return (size_t)Kmax * LDS_PER_SP + 48 * 1024 + 4 * gwords <= limit;
+    const size_t base = 48 * 1024 + 4 * gwords;
+    if (want == 1 && (size_t)Kmax * LDS_PER_SP + base <= limit) return 1;
+    if (want >= 1 && (size_t)Kmax * LDS_MEANS_PER_SP + base <= limit) return 2;
+    return 0;
 }
 
-LdsPlan plan_lds(size_t limit, int32_t Kmax, int64_t nbF, bool gated, bool stats_lds)
+LdsPlan plan_lds(size_t limit, int32_t Kmax, int64_t nbF, bool gated, int want)
 {
     LdsPlan p;
     std::memset(&p, 0, sizeof p);
     auto a16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
     size_t off = 0;
     const size_t gwords = gated ? ((size_t)Kmax + 31) / 32 : 0;   // at most MAX_GATE_WORDS (run_jobs)
-    size_t stats = (size_t)Kmax * LDS_PER_SP;
-    if (stats_lds && stats_fit_lds(limit, Kmax, gated)) {
-        p.stats_lds = 1;
-        off = a16(stats);
-    }
+    p.stats_lds = lds_residency(limit, Kmax, gated, want);
+    if (p.stats_lds == 1) off = a16((size_t)Kmax * LDS_PER_SP);
+    else if (p.stats_lds == 2) off = a16((size_t)Kmax * LDS_MEANS_PER_SP);
     p.gate_words = (int32_t)gwords;
     p.off_gate = (uint32_t)off;
     off = a16(off + 4 * gwords);
@@ -509,7 +512,7 @@ rapid_status launch_shape(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sc
             }
         }
     }
-    LdsPlan lp = plan_lds(ctx->lds_limit, Kmax, nbF_max, gated, sh.stats_lds != 0);
+    LdsPlan lp = plan_lds(ctx->lds_limit, Kmax, nbF_max, gated, sh.stats_lds);
     if (ctx->verbose)
         std::fprintf(stderr,
                      "rapid: threads %d, lds limit %zu, stats_lds %d, capl %d capp %d capx %d bm_words %d "
@@ -555,10 +558,9 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
 
     // launch shape: the tuned one for this problem shape, else the default
     // (enough jobs to fill the chip: the pyramid inside the launch)
-    const bool fits = stats_fit_lds(ctx->lds_limit, Kmax, gated);
     LaunchShape sh;
     sh.threads = ctx->threads;
-    sh.stats_lds = fits ? 1 : 0;
+    sh.stats_lds = lds_residency(ctx->lds_limit, Kmax, gated, 1);
     sh.pyramid = (int)n >= PYRAMID_MIN_JOBS ? 1 : 0;
     const std::string key = shape_key(jobs, sc, s_begin, s_end, flags, Kmax, gated);
     auto it = ctx->tuned.find(key);
@@ -576,9 +578,12 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
         const int thr_all[3] = {256, 512, 1024};
         LaunchShape best;
         best.ms = -1.0f;
+        const int res_all[3] = {1, 2, 0};
         for (int t = 0; t < 3; t++) {
             if (ctx->threads_forced && thr_all[t] != ctx->threads) continue;
-            for (int l = fits ? 1 : 0; l >= 0; l--)
+            for (int li = 0; li < 3; li++) {
+                const int l = res_all[li];
+                if (lds_residency(ctx->lds_limit, Kmax, gated, l) != l) continue;   // does not fit
                 for (int py = 1; py >= 0; py--) {
                     LaunchShape c;
                     c.threads = thr_all[t];
@@ -591,6 +596,7 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
                     HIPCHK(hipEventElapsedTime(&c.ms, ctx->tev[0], ctx->tev[1]));
                     if (best.ms < 0.0f || c.ms < best.ms) best = c;
                 }
+            }
         }
         sh = best;
         ctx->tuned[key] = best;
@@ -600,7 +606,7 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
             std::fprintf(stderr, "rapid: tuned %s -> threads %d stats_lds %d pyramid %d (%.3f ms)\n", key.c_str(),
                          best.threads, best.stats_lds, best.pyramid, best.ms);
     }
-    if (!fits) sh.stats_lds = 0;
+    sh.stats_lds = lds_residency(ctx->lds_limit, Kmax, gated, sh.stats_lds);
     ctx->last = sh;
     rapid_status r = launch_shape(ctx, jobs, sc, s_begin, s_end, flags, Kmax, nbF_max, gated, sh,
                                   ctx->timing ? ctx->ev[0] : nullptr, ctx->timing ? ctx->ev[1] : nullptr,

@@ -52,7 +52,7 @@ struct Prop {
 // cap* entries in LDS and spill to global scratch; the visit bitmap of the
 // frontier rebuild is used when it covers the stage's blocks.
 struct LdsPlan {
-    int32_t stats_lds;
+    int32_t stats_lds;       // 0 global, 1 statistics, means, flow in LDS, 2 means in LDS
     int32_t capl, capp, capx, bm_words;
     int32_t gate_words;      // LDS bitmap of the gate bits (0: no gate in this launch)
     uint32_t off_lists, off_props, off_chg, off_bm, off_gate;
@@ -74,7 +74,7 @@ struct Job {
     int32_t *changed;        // changed blocks of a sweep
     int32_t *stamp;          // per block visit stamp (when the LDS bitmap is too small)
     int64_t *stats;          // K x 6 int64: n, S_r, S_g, S_b, T_x, T_y
-    int32_t *means;          // K x MN_STRIDE (global working set)
+    int32_t *means;          // K records of MN_STRIDE words (global working set)
     int32_t *flow;           // K x 2 out/in (global working set)
     rapid_stage_report *rep; // per stage
     const uint8_t *gate;     // K bytes or null
@@ -123,9 +123,9 @@ hipError_t launch_refine(const Job *jobs_dev, int n_jobs, const Sched &sc, const
 constexpr int MLP_PARAMS = 5313;
 constexpr int FACC = 8;
 
-// per-superpixel means record: c_r c_g c_b mu_x mu_y n and two pad words
-// (int32; 32 bytes, one aligned sector per superpixel)
-constexpr int MN_STRIDE = 8;
+// per-superpixel means record: c_r c_g c_b mu_x mu_y n packed into four
+// 32-bit words (16 bytes; two records per 32-byte sector)
+constexpr int MN_STRIDE = 4;
 
 hipError_t launch_features(const Job *jobs_dev, int n_jobs, int B, int lab_buf, int F, int32_t Kmax,
                            int64_t max_nb, const int64_t *xoff_dev, float *X, hipStream_t stream);
@@ -144,5 +144,7 @@ hipError_t launch_boundary_miss(const int32_t *ref, const int32_t *test, int W, 
 // bytes of LDS per superpixel when the statistics live in LDS: sums, means
 // record, flow counters
 constexpr size_t LDS_PER_SP = 6 * 8 + MN_STRIDE * 4 + 2 * 4;
+// bytes of LDS per superpixel when only the means records live in LDS
+constexpr size_t LDS_MEANS_PER_SP = MN_STRIDE * 4;
 
 }  // namespace rapid

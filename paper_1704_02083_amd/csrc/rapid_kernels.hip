@@ -88,13 +88,40 @@ __device__ __forceinline__ void block_rgb(const Job &J, int s, int B, int64_t bi
     }
 }
 
-// E'(beta, k) of the block with the means of k held fixed (Eq. (1) minus
-// the terms that do not depend on k; difference form of Sec. 3.1).
-__device__ __forceinline__ int64_t block_energy(const int32_t *mn, int k, const Geo &g,
+// Means record of a superpixel, 16 bytes (4 words):
+//   c_r | c_g << 16,  c_b | (n & 0xFFFF) << 16,  mu_x | (n >> 16) << 17,  mu_y
+// with the fixed-point means c <= 255 * 2^4 < 2^16 and mu_x <= 8191 * 2^4 <
+// 2^17 (F <= 4, W, H <= 8192) and the size n <= 2^26.  Unpacked to
+// lo = (c_r, c_g, c_b, mu_x) and hi = (mu_y, n).
+__device__ __forceinline__ void unpack_mn(const uint4 &w, int4 &lo, int2 &hi)
+{
+    lo.x = (int)(w.x & 0xFFFFu);
+    lo.y = (int)(w.x >> 16);
+    lo.z = (int)(w.y & 0xFFFFu);
+    lo.w = (int)(w.z & 0x1FFFFu);
+    hi.x = (int)w.w;
+    hi.y = (int)((w.y >> 16) | ((w.z >> 17) << 16));
+}
+
+__device__ __forceinline__ void load_mn(const int32_t *mn, int k, int4 &lo, int2 &hi)
+{
+    unpack_mn(reinterpret_cast<const uint4 *>(mn)[k], lo, hi);
+}
+
+// size n of superpixel k from its means record
+__device__ __forceinline__ int64_t mn_size(const int32_t *mn, int k)
+{
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(mn) + MN_STRIDE * (int64_t)k;
+    return (int64_t)((w[1] >> 16) | ((w[2] >> 17) << 16));
+}
+
+// E'(beta, k) of the block with the means of k (record lo, hi) held fixed
+// (Eq. (1) minus the terms that do not depend on k; difference form of
+// Sec. 3.1).
+__device__ __forceinline__ int64_t block_energy(const int4 &lo, const int2 &hi, const Geo &g,
                                                 const int64_t I[3], int bnd, const Sched &sc)
 {
-    const int32_t *c = mn + MN_STRIDE * (int64_t)k;
-    int64_t c0 = c[0], c1 = c[1], c2 = c[2], mx = c[3], my = c[4];
+    int64_t c0 = lo.x, c1 = lo.y, c2 = lo.z, mx = lo.w, my = hi.x;
     int64_t col = c0 * c0 + c1 * c1 + c2 * c2;
     int64_t dot = c0 * I[0] + c1 * I[1] + c2 * I[2];
     int64_t e_col = g.m * col - (dot << (sc.F + 1));
@@ -117,27 +144,18 @@ __device__ __forceinline__ void refresh_sp(const int64_t *st, int32_t *mn, int k
     // a superpixel merged away (n = 0, sums 0) gets means 0
     const double dd = (double)(2 * max(n, (int64_t)1)), dn0 = (double)n;
     const double rcp = 1.0 / dd;
-    int32_t *o = mn + MN_STRIDE * k;
-    double q[5];
+    uint32_t q[5];
 #pragma unroll
     for (int j = 0; j < 5; j++) {
         const double dn = fma((double)r[1 + j], sc.d_fs, dn0);   // 2^(F+1) S + n, exact
         double v = floor(dn * rcp);
         if (v * dd > dn) v -= 1.0;
         else if ((v + 1.0) * dd <= dn) v += 1.0;
-        q[j] = v;
-        o[j] = (int32_t)v;
+        q[j] = (uint32_t)v;
     }
-    o[5] = (int32_t)n;
-}
-
-// Superpixel k's means record as two vector loads: (c_r, c_g, c_b, mu_x)
-// and (mu_y, n).
-__device__ __forceinline__ void load_mn(const int32_t *mn, int k, int4 &lo, int2 &hi)
-{
-    const int4 *p = reinterpret_cast<const int4 *>(mn + MN_STRIDE * (int64_t)k);
-    lo = p[0];
-    hi = *reinterpret_cast<const int2 *>(p + 1);
+    const uint32_t un = (uint32_t)n;
+    reinterpret_cast<uint4 *>(mn)[k] =
+        make_uint4(q[0] | (q[1] << 16), q[2] | ((un & 0xFFFFu) << 16), q[3] | ((un >> 16) << 17), q[4]);
 }
 
 // E' in fp64 from a means record: m A - <c', I> - <mu', P> + w_bnd 2^(2F) bnd
@@ -377,13 +395,18 @@ __device__ __forceinline__ __int128 merge_cost(const int64_t *st, const int32_t 
     const int F = sc.F;
     const int64_t *rm = st + 6 * (int64_t)m, *rk = st + 6 * (int64_t)k;
     const int64_t nm = rm[0], nk = rk[0], nu = nm + nk;
+    int4 lm, lk;
+    int2 hm, hk;
+    load_mn(mn, m, lm, hm);
+    load_mn(mn, k, lk, hk);
+    const int32_t cm[5] = {lm.x, lm.y, lm.z, lm.w, hm.x}, ck[5] = {lk.x, lk.y, lk.z, lk.w, hk.x};
     __int128 dc = 0, dp = 0;
 #pragma unroll
     for (int j = 0; j < 5; j++) {
         const int64_t Su = rm[1 + j] + rk[1 + j];
         const int64_t cu = ((Su << (F + 1)) + nu) / (2 * nu);
-        const __int128 d = fit_term(cu, Su, nu, F) - fit_term(mn[MN_STRIDE * m + j], rm[1 + j], nm, F) -
-                           fit_term(mn[MN_STRIDE * k + j], rk[1 + j], nk, F);
+        const __int128 d = fit_term(cu, Su, nu, F) - fit_term(cm[j], rm[1 + j], nm, F) -
+                           fit_term(ck[j], rk[1 + j], nk, F);
         if (j < 3) dc += d;
         else dp += d;
     }
@@ -704,7 +727,10 @@ __device__ __attribute__((noinline)) void gate_point(const Job &J, const int64_t
     wg_sync();
 }
 
-template <bool LDS, int GM, bool MERGE>
+// SL: where the per-superpixel state lives -- 0 all in global memory, 1
+// statistics, means records and flow counters in LDS, 2 the means records
+// in LDS (the hot reads of P1) and the rest in global memory.
+template <int SL, int GM, bool MERGE>
 __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, Sched sc, LdsPlan lp,
                                                   int s_begin, int s_end, int flags,
                                                   const uint32_t *__restrict__ lut_g)
@@ -720,10 +746,14 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
     const int W = J.W, H = J.H, K = J.K;
     int64_t *st;
     int32_t *mn, *fl;
-    if (LDS) {
+    if (SL == 1) {
         st = reinterpret_cast<int64_t *>(smem);
-        mn = reinterpret_cast<int32_t *>(st + 6 * (int64_t)K);   // K x MN_STRIDE, 16-byte aligned
+        mn = reinterpret_cast<int32_t *>(st + 6 * (int64_t)K);   // K records of 16 bytes, 16-byte aligned
         fl = mn + MN_STRIDE * (int64_t)K;
+    } else if (SL == 2) {
+        st = J.stats;
+        mn = reinterpret_cast<int32_t *>(smem);
+        fl = J.flow;
     } else {
         st = J.stats;
         mn = J.means;
@@ -798,7 +828,7 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
             add64(r + 4, g.px);
             add64(r + 5, g.py);
         }
-    } else if (LDS) {
+    } else if (SL == 1) {
         for (int64_t i = tid; i < 6 * (int64_t)K; i += nt) st[i] = J.stats[i];
     }
     wg_sync();
@@ -938,7 +968,10 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                         Ipk = pack_rgb(I[0], I[1], I[2]);
                         Geo g = block_geo(bx, by, B, W, H);
                         m = g.m;
-                        if ((int64_t)mn[MN_STRIDE * a + 5] - g.m < sc.min_size) {
+                        int4 ra;
+                        int2 rb;
+                        load_mn(mn, a, ra, rb);
+                        if ((int64_t)rb.y - g.m < sc.min_size) {
                             smin = true;
                             if (MERGE) merge_ask(J, a, &s_nreq);
                         } else {
@@ -968,9 +1001,6 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                                 if (use_f64) {
                                     const double dm = (double)g.m, dI0 = (double)I[0], dI1 = (double)I[1],
                                                  dI2 = (double)I[2], dpx = (double)g.px, dpy = (double)g.py;
-                                    int4 ra;
-                                    int2 rb;
-                                    load_mn(mn, a, ra, rb);
                                     double estar = energy_f64(ra, rb, sc, dm, dI0, dI1, dI2, dpx, dpy, sc.d_wb * (double)bnd_a);
 #pragma unroll
                                     for (int u = 0; u < 4; u++) {
@@ -990,16 +1020,19 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                                         }
                                     }
                                 } else {
-                                    int64_t estar = block_energy(mn, a, g, I, bnd_a, sc);
+                                    int64_t estar = block_energy(ra, rb, g, I, bnd_a, sc);
 #pragma unroll
                                     for (int u = 0; u < 4; u++) {
                                         const int32_t k = cs[u];
                                         if (k == INT32_MAX || (u > 0 && k == cs[u - 1])) continue;
-                                        if ((int64_t)mn[MN_STRIDE * k + 5] + g.m > sc.max_size) continue;
+                                        int4 ka;
+                                        int2 kb;
+                                        load_mn(mn, k, ka, kb);
+                                        if ((int64_t)kb.y + g.m > sc.max_size) continue;
                                         int bnd = 0;
 #pragma unroll
                                         for (int d = 0; d < 4; d++) bnd += (nl[d] >= 0 && nl[d] != k) ? el[d] : 0;
-                                        int64_t ek = block_energy(mn, k, g, I, bnd, sc);
+                                        int64_t ek = block_energy(ka, kb, g, I, bnd, sc);
                                         if (ek < estar) {
                                             estar = ek;
                                             best = k;
@@ -1046,8 +1079,8 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                         const int32_t a = rec.a, k = rec.k;
                         // sizes from the class-start snapshot: the atomics of
                         // this phase are already moving the live counts
-                        com = (int64_t)mn[MN_STRIDE * a + 5] - fl[2 * a] >= sc.min_size &&
-                              (int64_t)mn[MN_STRIDE * k + 5] + fl[2 * k + 1] <= sc.max_size;
+                        com = mn_size(mn, a) - fl[2 * a] >= sc.min_size &&
+                              mn_size(mn, k) + fl[2 * k + 1] <= sc.max_size;
                         if (com) {
                             const int bx = bi % nbx, by = bi / nbx;
                             const Geo g = block_geo(bx, by, B, W, H);
@@ -1177,7 +1210,7 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
         }
         wg_sync();
     }
-    if (LDS)
+    if (SL == 1)
         for (int64_t i = tid; i < 6 * (int64_t)K; i += nt) J.stats[i] = st[i];
     if ((flags & FLAG_OUT) && s_end > 0 && J.tile) {
         // slide tile: core pixels only, labels as slide-wide cell ids
@@ -1231,16 +1264,16 @@ hipError_t launch_refine(const Job *jobs_dev, int n_jobs, const Sched &sc, const
                          hipStream_t stream)
 {
     typedef void (*Kern)(const Job *, Sched, LdsPlan, int, int, int, const uint32_t *);
-    // instantiations: statistics in LDS or not, gate mode, merge on underflow
-    static const Kern table[2][3][2] = {
-        {{k_refine<false, GM_NONE, false>, k_refine<false, GM_NONE, true>},
-         {k_refine<false, GM_BITS, false>, k_refine<false, GM_BITS, true>},
-         {k_refine<false, GM_FUSED, false>, k_refine<false, GM_FUSED, true>}},
-        {{k_refine<true, GM_NONE, false>, k_refine<true, GM_NONE, true>},
-         {k_refine<true, GM_BITS, false>, k_refine<true, GM_BITS, true>},
-         {k_refine<true, GM_FUSED, false>, k_refine<true, GM_FUSED, true>}}};
+    // instantiations: where the per-superpixel state lives, gate mode, merge
+    // on underflow
+#define RAPID_K(sl, gm) {k_refine<sl, gm, false>, k_refine<sl, gm, true>}
+    static const Kern table[3][3][2] = {
+        {RAPID_K(0, GM_NONE), RAPID_K(0, GM_BITS), RAPID_K(0, GM_FUSED)},
+        {RAPID_K(1, GM_NONE), RAPID_K(1, GM_BITS), RAPID_K(1, GM_FUSED)},
+        {RAPID_K(2, GM_NONE), RAPID_K(2, GM_BITS), RAPID_K(2, GM_FUSED)}};
+#undef RAPID_K
     const int gm = (flags & FLAG_GATE) ? GM_FUSED : lp.gate_words > 0 ? GM_BITS : GM_NONE;
-    const Kern fn = table[lp.stats_lds ? 1 : 0][gm][sc.merge ? 1 : 0];
+    const Kern fn = table[lp.stats_lds][gm][sc.merge ? 1 : 0];
     hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp.total);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fn, dim3((unsigned)n_jobs), dim3(threads), lp.total, stream, jobs_dev, sc, lp, s_begin,
