@@ -546,7 +546,8 @@ def bench_he(args):
         "roofline": {"bound": "hbm", "kernel": "k_refine", "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "avg_launch_ms": round(avg_refine, 3), "achieved": round(achieved, 3),
                      "frac": round(achieved / HBM_PEAK_GBS, 6),
-                     "traffic": profile_traffic("k_refine", args.workload, kernel_source_hash()),
+                     "traffic": profile_traffic("k_refine", args.workload + ("_grain%d" % args.grain if args.grain > 1
+                                                                           else ""), kernel_source_hash()),
                      "alg_bytes_per_launch": alg},
         "launch_shape": shape,
     }
