@@ -133,8 +133,16 @@ def cpu_baseline(imgs, p, sample: int):
         oracle.segment(img, p)
         px += img.shape[0] * img.shape[1]
     dt = time.perf_counter() - t0
-    return {"value": round(px / dt / 1e6, 4), "unit": "MPixel/s", "cores": 1, "kind": "oracle",
-            "sample": "%d of the %d images (%d px), single-threaded, %.1f s" % (n, len(imgs), px, dt)}
+    out = {"value": round(px / dt / 1e6, 4), "unit": "MPixel/s", "cores": 1, "kind": "oracle",
+           "sample": "%d of the %d images (%d px), single-threaded, %.1f s" % (n, len(imgs), px, dt)}
+    if not p.get("merge"):
+        # the oracle's sequential FIFO-queue schedule (the paper's queue read
+        # literally) on the same sample: context for the synchronous one
+        t0 = time.perf_counter()
+        for img in imgs[:n]:
+            oracle.segment_fifo(img, p)
+        out["fifo_schedule_value"] = round(px / (time.perf_counter() - t0) / 1e6, 4)
+    return out
 
 
 def main():

@@ -96,6 +96,10 @@ def lib():
         L.orc_block_energy.restype = C.c_int64
         L.orc_segment_ex.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, C.POINTER(OrcParams), P,
                                      P, P, P, C.c_int32, C.c_int32, P, P]
+        L.orc_segment_fifo.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, C.POINTER(OrcParams), P, P, P,
+                                       C.c_int32]
+        L.orc_energy.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, C.POINTER(OrcParams), P, C.c_int32]
+        L.orc_energy.restype = C.c_int64
         L.orc_merge_cost.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, C.POINTER(OrcParams), P,
                                      C.c_int32, C.c_int32, C.c_int32]
         L.orc_merge_cost.restype = C.c_int64
@@ -188,6 +192,31 @@ def segment(rgb: np.ndarray, d: dict, gate: np.ndarray | None = None,
         raise RuntimeError("orc_segment failed rc=%d" % rc)
     out = (labels, stats, [reps[i].as_dict() for i in range(rc)])
     return out + (inv, mov) if track else out
+
+
+def segment_fifo(rgb: np.ndarray, d: dict, debug: bool = False):
+    """Sequential FIFO-queue schedule (see orc_segment_fifo): (labels,
+    stats, moves)."""
+    rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+    H, W, _ = rgb.shape
+    K = n_superpixels(W, H, d)
+    labels = np.empty((H, W), np.int32)
+    stats = np.empty((K, 6), np.int64)
+    moves = C.c_int64(0)
+    rc = lib().orc_segment_fifo(_ptr(rgb), W, H, 3 * W, C.byref(make_params(d)), _ptr(labels), _ptr(stats),
+                                C.byref(moves), int(debug))
+    if rc < 0:
+        raise RuntimeError("orc_segment_fifo failed rc=%d" % rc)
+    return labels, stats, int(moves.value)
+
+
+def energy(rgb: np.ndarray, d: dict, labels: np.ndarray) -> int:
+    """Eq. (1) at pixel level for a label map (see orc_energy)."""
+    rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    H, W, _ = rgb.shape
+    K = n_superpixels(W, H, d)
+    return int(lib().orc_energy(_ptr(rgb), W, H, 3 * W, C.byref(make_params(d)), _ptr(labels), K))
 
 
 def merge_cost(rgb: np.ndarray, d: dict, labels: np.ndarray, K: int, m: int, k: int) -> int:

@@ -912,6 +912,167 @@ done:
     return rc;
 }
 
+/* --------------------------------------------- sequential FIFO baseline */
+
+/* Best label for block (bx, by) under the current means, as in propose():
+ * -1 when the block may not move (size, topology), else the label of least
+ * E' among its own and its 4-neighbours' within max_size (strictly lower
+ * energy, candidates in ascending order). */
+static int32_t fifo_best(const state *s, int32_t bx, int32_t by)
+{
+    const orc_params *p = s->p;
+    blk b = block_geom(s, bx, by);
+    int32_t a = blabel(s, bx, by);
+    if (s->n[a] - b.m < p->min_size || !is_simple_block(s, bx, by)) return -1;
+    int32_t nbl[4] = {blabel(s, bx - 1, by), blabel(s, bx + 1, by), blabel(s, bx, by - 1), blabel(s, bx, by + 1)};
+    int32_t cand[4];
+    int nc = 0;
+    for (int d = 0; d < 4; d++) {
+        int32_t k = nbl[d];
+        int dup = k < 0 || k == a;
+        for (int e = 0; e < nc && !dup; e++) dup = cand[e] == k;
+        if (!dup) cand[nc++] = k;
+    }
+    for (int u = 1; u < nc; u++)
+        for (int v = u; v > 0 && cand[v - 1] > cand[v]; v--) {
+            int32_t t = cand[v]; cand[v] = cand[v - 1]; cand[v - 1] = t;
+        }
+    int32_t best = a;
+    i128 estar = block_energy(s, bx, by, a);
+    for (int e = 0; e < nc; e++) {
+        if (s->n[cand[e]] + b.m > p->max_size) continue;
+        i128 ek = block_energy(s, bx, by, cand[e]);
+        if (ek < estar) { estar = ek; best = cand[e]; }
+    }
+    return best;
+}
+
+/* Sequential CTFTPS with the boundary queue of Algorithm RAPID read
+ * literally, as a baseline for the synchronous class schedule: at every
+ * stage the boundary blocks (Eq. (2)) enter a FIFO in row-major order; a
+ * popped block that is simple and may leave its superpixel takes the label
+ * of least E' (Eq. (3)); a move updates the sums and both superpixels' means
+ * at once and appends the moved block and its 4-neighbours that are
+ * boundary blocks and not queued.  A stage ends when the queue is empty or
+ * after max_sweeps x (blocks of the stage) pops.  Same grid, energy, size
+ * bounds, levels and reuse as orc_segment; no gate and no merge.  labels:
+ * W*H out; stats_out: K'*6 or NULL; moves_out: total moves or NULL.  Returns
+ * the number of stages run, or an error code. */
+int orc_segment_fifo(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride, const orc_params *p,
+                     int32_t *labels, int64_t *stats_out, int64_t *moves_out, int32_t debug)
+{
+    int rc = check_params(p, W, H);
+    if (rc) return rc;
+    if (!rgb || !labels || stride < 3 * (int64_t)W || p->merge) return ORC_EINVAL;
+    int32_t gx = p->gx, gy = p->gy;
+    if (p->K > 0 && (rc = orc_grid(W, H, p->K, &gx, &gy))) return rc;
+    if (gx < 1 || gy < 1) return ORC_EINVAL;
+    int32_t B0 = p->stages[0][0] * p->factor[0];
+    if ((rc = orc_init_labels(W, H, B0, gx, gy, labels))) return rc;
+    state s;
+    memset(&s, 0, sizeof s);
+    s.rgb = rgb; s.W = W; s.H = H; s.stride = stride; s.p = p; s.K = gx * gy;
+    int32_t K = s.K;
+    int64_t moves = 0;
+    int nst = 0;
+    int64_t *q = NULL;
+    uint8_t *inq = NULL;
+    s.n = calloc(K, sizeof(int64_t)); s.S = calloc(3 * (int64_t)K, sizeof(int64_t));
+    s.T = calloc(2 * (int64_t)K, sizeof(int64_t));
+    s.c = calloc(3 * (int64_t)K, sizeof(int64_t)); s.mu = calloc(2 * (int64_t)K, sizeof(int64_t));
+    if (!s.n || !s.S || !s.T || !s.c || !s.mu) { rc = ORC_ENOMEM; goto done; }
+    if ((rc = stats_from_labels(rgb, W, H, stride, labels, K, s.n, s.S, s.T))) goto done;
+    for (int32_t k = 0; k < K; k++) refresh_means(&s, k);
+    for (int l = 0; l < p->n_levels; l++)
+        for (int st = 0; st < p->n_stages[l]; st++) {
+            int32_t B = p->stages[l][st] * p->factor[l];
+            if ((rc = build_blocks(&s, B, labels))) goto done;
+            int64_t nb = (int64_t)s.nbx * s.nby;
+            free(q); free(inq);
+            q = malloc(sizeof(int64_t) * nb);
+            inq = calloc(nb, 1);
+            if (!q || !inq) { rc = ORC_ENOMEM; goto done; }
+            int64_t head = 0, len = 0;
+            for (int64_t i = 0; i < nb; i++)
+                if (eligible(&s, (int32_t)(i % s.nbx), (int32_t)(i / s.nbx))) { q[len++] = i; inq[i] = 1; }
+            int64_t pops = 0, cap = (int64_t)p->max_sweeps * nb;
+            while (len > 0 && pops < cap) {
+                int64_t bi = q[head];
+                head = (head + 1) % nb;
+                len--;
+                inq[bi] = 0;
+                pops++;
+                int32_t bx = (int32_t)(bi % s.nbx), by = (int32_t)(bi / s.nbx);
+                int32_t a = s.bl[bi], k = fifo_best(&s, bx, by);
+                if (k < 0 || k == a) continue;
+                blk b = block_geom(&s, bx, by);
+                s.bl[bi] = k;
+                s.n[a] -= b.m; s.n[k] += b.m;
+                for (int ch = 0; ch < 3; ch++) {
+                    s.S[3 * (int64_t)a + ch] -= s.bs[3 * bi + ch];
+                    s.S[3 * (int64_t)k + ch] += s.bs[3 * bi + ch];
+                }
+                s.T[2 * (int64_t)a] -= b.px_; s.T[2 * (int64_t)k] += b.px_;
+                s.T[2 * (int64_t)a + 1] -= b.py_; s.T[2 * (int64_t)k + 1] += b.py_;
+                refresh_means(&s, a);
+                refresh_means(&s, k);
+                moves++;
+                static const int d5[5][2] = {{0, 0}, {-1, 0}, {1, 0}, {0, -1}, {0, 1}};
+                for (int d = 0; d < 5; d++) {
+                    int32_t x = bx + d5[d][0], y = by + d5[d][1];
+                    if (x < 0 || y < 0 || x >= s.nbx || y >= s.nby) continue;
+                    int64_t ni = (int64_t)y * s.nbx + x;
+                    if (!inq[ni] && eligible(&s, x, y)) {
+                        q[(head + len) % nb] = ni;
+                        len++;
+                        inq[ni] = 1;
+                    }
+                }
+            }
+            for (int32_t y = 0; y < H; y++)
+                for (int32_t x = 0; x < W; x++)
+                    labels[(int64_t)y * W + x] = s.bl[(int64_t)(y / B) * s.nbx + x / B];
+            if (debug && (rc = check_invariants(&s)) != ORC_OK) goto done;
+            nst++;
+        }
+    if (stats_out)
+        for (int32_t k = 0; k < K; k++) {
+            stats_out[6 * (int64_t)k] = s.n[k];
+            for (int ch = 0; ch < 3; ch++) stats_out[6 * (int64_t)k + 1 + ch] = s.S[3 * (int64_t)k + ch];
+            stats_out[6 * (int64_t)k + 4] = s.T[2 * (int64_t)k];
+            stats_out[6 * (int64_t)k + 5] = s.T[2 * (int64_t)k + 1];
+        }
+    if (moves_out) *moves_out = moves;
+    rc = nst;
+done:
+    free(s.n); free(s.S); free(s.T); free(s.c); free(s.mu); free(s.bl); free(s.bs); free(q); free(inq);
+    return rc;
+}
+
+/* Eq. (1) at pixel level for pixel labels (statistics recounted, means
+ * rounded as everywhere), saturated to the int64 range: the measure the
+ * schedule comparison uses. */
+int64_t orc_energy(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride, const orc_params *p,
+                   const int32_t *labels, int32_t K)
+{
+    state s;
+    memset(&s, 0, sizeof s);
+    s.rgb = rgb; s.W = W; s.H = H; s.stride = stride; s.p = p; s.K = K;
+    int64_t r = INT64_MIN;
+    s.n = calloc(K, sizeof(int64_t)); s.S = calloc(3 * (int64_t)K, sizeof(int64_t));
+    s.T = calloc(2 * (int64_t)K, sizeof(int64_t));
+    s.c = calloc(3 * (int64_t)K, sizeof(int64_t)); s.mu = calloc(2 * (int64_t)K, sizeof(int64_t));
+    if (s.n && s.S && s.T && s.c && s.mu &&
+        stats_from_labels(rgb, W, H, stride, labels, K, s.n, s.S, s.T) == ORC_OK &&
+        build_blocks(&s, 1, labels) == ORC_OK) {
+        for (int32_t k = 0; k < K; k++) refresh_means(&s, k);
+        i128 e = global_energy(&s);
+        r = e > (i128)INT64_MAX ? INT64_MAX : (int64_t)e;
+    }
+    free(s.n); free(s.S); free(s.T); free(s.c); free(s.mu); free(s.bl); free(s.bs);
+    return r;
+}
+
 /* Proposals of class cls at block size B for an arbitrary valid state given
  * by pixel labels (all eligible blocks active, statistics recounted from the
  * labels).  props: 3 int32 per proposal (block index, from, to); eprime: the

@@ -74,6 +74,10 @@ int orc_segment_ex(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
                    int32_t *labels, int64_t *stats_out,
                    orc_stage_report *rep, int32_t max_rep, int32_t debug,
                    uint8_t *involved, int64_t *moved);
+int orc_segment_fifo(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride, const orc_params *p,
+                     int32_t *labels, int64_t *stats_out, int64_t *moves_out, int32_t debug);
+int64_t orc_energy(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride, const orc_params *p,
+                   const int32_t *labels, int32_t K);
 int64_t orc_merge_cost(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
                        const orc_params *p, const int32_t *labels, int32_t K, int32_t m, int32_t k);
 int orc_features(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
