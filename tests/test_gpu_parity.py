@@ -122,6 +122,17 @@ def test_gate_beyond_lds_bitmap_refused(ctx, gpu_lib):
     assert e.value.code == -1
 
 
+def test_sweep_cap_not_converged(ctx):
+    """max_sweeps = 1: the stages stop after one sweep, unconverged, exactly
+    as the oracle's."""
+    img = synth.voronoi_blur(128, 96, regions=10, seed=5)
+    p = params.default_params(128, 96, 24, max_sweeps=1)
+    got, rep = _gpu_segment(ctx, img, p)
+    ref, _, ref_rep = oracle.segment(img, p)
+    _assert_same(got, rep, ref, ref_rep, "max_sweeps 1")
+    assert any(r["converged"] == 0 for r in rep)
+
+
 def test_state_api_level_by_level(ctx):
     """state_create + refine_level per level + export equals the oracle, and
     the exported statistics equal the oracle's (reuse across levels)."""

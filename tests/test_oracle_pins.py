@@ -445,3 +445,14 @@ def test_filter_lower_bound_rejects_class_aggregate():
     are rejected; class 3 moves row 1 (16 - 1 = 15) and the rest is skipped."""
     col, rep = _filter_case(15, 1 << 40)
     assert col == [0, 1, 0, 0] and rep["commits"] == 1 and rep["proposals"] == 3
+
+
+def test_sweep_cap_reports_not_converged():
+    """max_sweeps = 1: every stage runs exactly one sweep and reports
+    converged only when that sweep committed nothing."""
+    img = synth.voronoi_blur(128, 96, regions=10, seed=5)
+    p = params.default_params(128, 96, 24, max_sweeps=1)
+    _, _, rep = oracle.segment(img, p, debug=True)
+    assert all(r["sweeps"] == 1 for r in rep)
+    assert all(r["converged"] == (1 if r["commits"] == 0 else 0) for r in rep)
+    assert any(r["converged"] == 0 for r in rep)
