@@ -4,9 +4,10 @@
  * topology-preserving refinement of RAPID (Sulimowicz & Ahmad, ICME 2017):
  * the CTFTPS energy of Eq. (1), block moves of Eq. (3) restricted to
  * boundary blocks (Eq. (2); Eq. (7) under a prediction gate), the size
- * regularity of Sec. 3.1 as hard bounds, and the adaptive multi-level
- * framework of Sec. 3.2 (statistics computed once and reused; Eq. (8) holds
- * by construction because every sum is kept in fine-pixel units).
+ * regularity of Sec. 3.1 as hard bounds (optionally with the merge on
+ * underflow of Eqs. (4)-(5)), and the adaptive multi-level framework of
+ * Sec. 3.2 (statistics computed once and reused; Eq. (8) holds by
+ * construction because every sum is kept in fine-pixel units).
  *
  * Input: one HWC uint8 RGB image (or a batch) and a target superpixel count.
  * Output: one int32 label per pixel in [0, gx*gy).
