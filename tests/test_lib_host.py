@@ -93,3 +93,15 @@ def test_slide_tile_counts():
 def test_slide_rejects(args):
     with pytest.raises(rapid.RapidError):
         rapid.slide_tiles(*args)
+
+
+@pytest.mark.parametrize("field,value", [("merge", 2), ("merge", -1), ("reserved", 1), ("gate_rule", 3)])
+def test_check_params_rejects_bad_mode_fields(field, value):
+    """Mode fields outside their range are refused, merge included."""
+    import ctypes as C
+    p = rapid.make_params(params.config1())
+    setattr(p, field, value)
+    k = C.c_int32(0)
+    assert rapid._lib.rapid_check_params(256, 256, C.byref(p), C.byref(k)) == -1
+    p = rapid.make_params(dict(params.config1(), merge=True))
+    assert rapid._lib.rapid_check_params(256, 256, C.byref(p), C.byref(k)) == 0 and k.value == 64
