@@ -841,8 +841,16 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
         const int64_t nb = (int64_t)nbx * nby;
         int32_t *L = J.lab[s & 1];
         if (GM == GM_FUSED && s == sc.gate_stage && s > 0) {
-            gate_point(J, st, s - 1, sc.B[s - 1], sc.F, sc.mlp_w, sc.mlp_thresh, smem + lp.off_lists,
-                       lp.total - lp.off_lists, tid, nt);
+            // The gate point may use all the LDS that holds no statistics:
+            // the work lists, the gate words (loaded only afterwards) and,
+            // when only the means records live in LDS, their region too (it
+            // keeps its own means; the records are rebuilt afterwards).  A
+            // larger band of the label map per pass means fewer passes.
+            const uint32_t gp_off = SL == 1 ? lp.off_lists : 0u;
+            gate_point(J, st, s - 1, sc.B[s - 1], sc.F, sc.mlp_w, sc.mlp_thresh, smem + gp_off, lp.total - gp_off,
+                       tid, nt);
+            if (SL == 2)
+                for (int k = tid; k < K; k += nt) refresh_sp(st, mn, k, sc);
             // the frontier bitmap shares that LDS and must start the stage clear
             for (int i = tid; i < lp.bm_words; i += nt) l_bm[i] = 0;
         }

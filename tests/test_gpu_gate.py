@@ -367,3 +367,60 @@ def test_state_gate_refuses_non_finite_model(ctx, gpu_lib):
     assert e.value.code == -5
     assert (g.cpu().numpy() == 1).all()
     st.close()
+
+
+@pytest.mark.parametrize("res", [0, 1, 2])
+def test_gated_segment_every_residency(gpu_lib, res):
+    """The single-launch gated path with the per-superpixel state all in
+    global memory (0), all in LDS (1) or only the means records in LDS (2):
+    the gate point borrows the LDS that holds no statistics, so every
+    residency must still give the oracle's features, bits and labels."""
+    import os
+    img, p = _he_case()
+    theta, wb = _rand_model(21)
+    thresh, bits, ref, ref_rep, Xo = _oracle_gated(img, p, theta)
+    old = os.environ.get("RAPID_SHAPE")
+    os.environ["RAPID_SHAPE"] = "1024,%d,1" % res
+    try:
+        c = gpu_lib.Context(0, timing=True)
+        _say("case: gated 256x192, residency %d" % res)
+        labs, reps, X, g = c.segment_gated([_dev(img)], p, _dev(wb), thresh, features=True)
+        assert c.last_timings()["stats_lds"] == res
+        assert np.abs(X.cpu().numpy() - Xo).max() <= 1e-6
+        assert (g.cpu().numpy() == bits).all()
+        assert (labs[0].cpu().numpy() == ref).all()
+        assert reps[0] == ref_rep
+        c.close()
+    finally:
+        if old is None:
+            os.environ.pop("RAPID_SHAPE", None)
+        else:
+            os.environ["RAPID_SHAPE"] = old
+
+
+def test_gated_large_grid_matches_oracle(ctx):
+    """1024 x 768 H&E tile with K = 3072: the state does not fit LDS whole,
+    so the launch keeps only the means records there (the gate point then
+    works in the rest).  Features against the oracle's; bits against the
+    oracle's network wherever its logit is clear of the threshold (bf16
+    rounding moves logits by up to 1e-2); labels against the oracle run
+    under the GPU's own bits."""
+    img = synth.he_tile(1024, 768, seed=31)
+    p = params.default_params(1024, 768, 3072, levels=params.THREE_LEVEL, gate_level=1)
+    theta, wb = _rand_model(22)
+    gx, gy = oracle.grid(1024, 768, 3072)
+    p0 = dict(p, levels=p["levels"][:1], gate_level=-1)
+    lab0, s0, _, _, mov0 = oracle.segment(img, p0, track=True)
+    Xo = oracle.features(img, lab0, 16, s0, mov0, gx, gy)
+    z, _ = mlp.forward(theta.astype(np.float64), Xo.astype(np.float64), bf16=True)
+    thresh = float(np.median(z))
+    _say("case: gated 1024x768 K=%d" % len(z))
+    labs, reps, X, g = ctx.segment_gated([_dev(img)], p, _dev(wb), thresh, features=True)
+    assert np.abs(X.cpu().numpy() - Xo).max() <= 1e-6
+    g = g.cpu().numpy()
+    far = np.abs(z - thresh) > 1e-2
+    assert far.sum() > 0.9 * len(z)
+    assert (g[far] == (z[far] >= thresh)).all()
+    ref, _, ref_rep = oracle.segment(img, p, gate=g)
+    assert (labs[0].cpu().numpy() == ref).all()
+    assert reps[0] == ref_rep
