@@ -190,6 +190,8 @@ def main():
     ap.add_argument("--gated", action="store_true",
                     help="H&E workloads: also train the gate and time the gated path")
     ap.add_argument("--gate-rule", default="both", choices=["either", "both"])
+    ap.add_argument("--gate-level", type=int, default=3, choices=[1, 2, 3],
+                    help="level of the schedule 16 | 8,4 | 2 | 1 from which the gate applies")
     ap.add_argument("--train-tiles", type=int, default=64, help="4096x4096 training tiles of the gate")
     ap.add_argument("--grain", type=int, default=1,
                     help="H&E workloads: stop the schedule at this effective block size (the paper's "
@@ -350,13 +352,13 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def train_gate(ctx, rule: str, n_tiles: int, seed: int = 0):
+def train_gate(ctx, rule: str, n_tiles: int, seed: int = 0, gate_level: int = 3):
     """Gate network trained on n_tiles synthetic 4096x4096 H&E tiles (seeds
     5000...) with 32-px cells: features and targets from plain runs, the
     training itself, all on the GPU through the C-ABI."""
     import torch
     from paper_1704_02083_amd import gate, params, synth_gpu
-    p = params.gated(4096, 4096, 16384, rule=rule)
+    p = params.gated(4096, 4096, 16384, rule=rule, gate_level=gate_level)
     Xs, ts = [], []
     for i in range(n_tiles):
         rgb = synth_gpu.he_slide(4096, 4096, seed=5000 + i, background=0.4, device="cuda")
@@ -379,10 +381,10 @@ def bench_gated(args, ctx, rgb, labels, plain, W, H, dt_plain):
     calibrated on held-out tiles for boundary recall >= 0.99."""
     import torch
     from paper_1704_02083_amd import gate, metrics, params, rapid, synth_gpu
-    w, info = train_gate(ctx, args.gate_rule, args.train_tiles)
+    w, info = train_gate(ctx, args.gate_rule, args.train_tiles, gate_level=args.gate_level)
     print("bench: gate trained (%s)" % info, file=sys.stderr, flush=True)
     if args.workload in ("slide", "slide65k"):
-        pg = params.gated(2048, 2048, 4096, rule=args.gate_rule)
+        pg = params.gated(2048, 2048, 4096, rule=args.gate_rule, gate_level=args.gate_level)
         lay = rapid.tile_layout(W, H, 2048, 64, 32)
 
         def run(th, report=False):
@@ -390,7 +392,7 @@ def bench_gated(args, ctx, rgb, labels, plain, W, H, dt_plain):
                                         report=report)
             return tiles_alg_bytes(W, H, lay, reps) if report else None
     else:
-        pg = params.gated(W, H, 16384, rule=args.gate_rule)
+        pg = params.gated(W, H, 16384, rule=args.gate_rule, gate_level=args.gate_level)
 
         def run(th, report=False):
             _, reps, _, _ = ctx.segment_gated([rgb], pg, w, th, labels=[labels], report=report)
@@ -422,7 +424,10 @@ def bench_gated(args, ctx, rgb, labels, plain, W, H, dt_plain):
                 "ue": round(float(sum(ue) / len(ue)), 6)}
 
     curve = [point(th) for th in (1e9, 2.0, 1.0, 0.0, -1e9)]
-    res = {"train": info, "rule": args.gate_rule, "schedule": "16 | 8,4 | 2 | 1 (gate before the last level)",
+    res = {"train": info, "rule": args.gate_rule,
+           "schedule": "16 | 8,4 | 2 | 1, gate from level %d (%s)" % (
+               args.gate_level, {3: "the 1-px stage", 2: "the 2-px and 1-px stages",
+                                 1: "every stage after the 16-px one"}[args.gate_level]),
            "curve": curve,
            "note": "thresh 1e9 refines nothing past the gate point, -1e9 everything; br and disagreement "
                    "over the whole image against the plain labels, ue on %d 4096x4096 crops" % len(crops)}
@@ -431,7 +436,8 @@ def bench_gated(args, ctx, rgb, labels, plain, W, H, dt_plain):
     # at the stricter 0.995 where refining nothing is no longer enough
     res["calibrated"] = []
     for target in (0.99, 0.995):
-        cal = gate.calibrate(ctx, hold, params.gated(2048, 2048, 4096, rule=args.gate_rule), w, target,
+        cal = gate.calibrate(ctx, hold, params.gated(2048, 2048, 4096, rule=args.gate_rule,
+                                                     gate_level=args.gate_level), w, target,
                              candidates=[1e9, 4.0, 3.0, 2.0, 1.5, 1.0, 0.5, 0.0, -0.5, -1.0, -2.0, -1e9])
         if cal is not None:
             c = point(cal[0])

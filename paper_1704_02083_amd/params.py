@@ -57,9 +57,10 @@ def config3(W: int = 4096, H: int = 4096, K: int = 16384, gate_level: int = -1) 
     return default_params(W, H, K, levels=THREE_LEVEL, gate_level=gate_level)
 
 
-def gated(W: int, H: int, K: int, rule: str = "both") -> dict:
+def gated(W: int, H: int, K: int, rule: str = "both", gate_level: int = GATE_LEVEL) -> dict:
     """H&E tile or slide tile under the learned gate: the schedule of
-    config3 with the single-pixel stage as the gated level."""
-    p = default_params(W, H, K, levels=GATED_LEVELS, gate_level=GATE_LEVEL)
+    config3 with the single-pixel stage as its own level; by default that
+    last level is gated (gate_level 2 gates the 2-px stage too)."""
+    p = default_params(W, H, K, levels=GATED_LEVELS, gate_level=gate_level)
     p["gate_rule"] = rule
     return p
