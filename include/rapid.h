@@ -70,8 +70,9 @@ typedef struct {
      * problem shape (images, largest W, H and superpixel count, schedule,
      * gate and merge modes) runs its launch once per candidate shape --
      * workgroup size 256, 512 or 1024; per-superpixel state all in LDS,
-     * only the means records in LDS, or all in global memory (as far as
-     * they fit); block-sum pyramid inside the launch or in
+     * the means records and flow counters, only the means records, or
+     * nothing in LDS (as far as they fit); block-sum pyramid inside the
+     * launch or in
      * separate launches -- and keeps the fastest; later calls of that
      * shape use it.  Every candidate computes the same labels (the result
      * never depends on the shape), so tuning costs time only.  Only calls
@@ -90,8 +91,9 @@ typedef struct {
                               pyramids itself)                        */
     float refine_ms;       /* the refinement kernel (all stages)   */
     int32_t threads;       /* launch shape of that call: workgroup size, */
-    int32_t stats_lds;     /* per-superpixel state: 1 all in LDS, 2 the
-                              means records in LDS, 0 all global,       */
+    int32_t stats_lds;     /* per-superpixel state: 1 all in LDS, 3 the
+                              means records and flow counters in LDS, 2
+                              the means records in LDS, 0 all global,   */
     int32_t pyramid;       /* pyramid inside the refinement launch (1)   */
     int32_t tuned;         /* 1 when this call ran the autotuner         */
 } rapid_timings;

@@ -382,13 +382,14 @@ rapid_status dev_err(hipError_t e) { return e == hipSuccess ? RAPID_OK : RAPID_E
 // with room to spare), then the class lists, proposals, the frontier visit
 // bitmap and the changed list, each within a share of what remains.
 // Residency of the per-superpixel state that fits LDS beside the work
-// space, given the one asked for: 1 (statistics, means, flow), else 2 (the
-// means records), else 0 (all in global memory).
+// space, given the one asked for, falling back in the order 1 (statistics,
+// means, flow), 3 (means and flow), 2 (means), 0 (all in global memory).
 int lds_residency(size_t limit, int32_t Kmax, bool gated, int want)
 {
     const size_t gwords = gated ? ((size_t)Kmax + 31) / 32 : 0;
     const size_t base = 48 * 1024 + 4 * gwords;
     if (want == 1 && (size_t)Kmax * LDS_PER_SP + base <= limit) return 1;
+    if ((want == 1 || want == 3) && (size_t)Kmax * LDS_MEANS_FLOW_PER_SP + base <= limit) return 3;
     if (want >= 1 && (size_t)Kmax * LDS_MEANS_PER_SP + base <= limit) return 2;
     return 0;
 }
@@ -402,6 +403,7 @@ LdsPlan plan_lds(size_t limit, int32_t Kmax, int64_t nbF, bool gated, int want)
     const size_t gwords = gated ? ((size_t)Kmax + 31) / 32 : 0;   // at most MAX_GATE_WORDS (run_jobs)
     p.stats_lds = lds_residency(limit, Kmax, gated, want);
     if (p.stats_lds == 1) off = a16((size_t)Kmax * LDS_PER_SP);
+    else if (p.stats_lds == 3) off = a16((size_t)Kmax * LDS_MEANS_FLOW_PER_SP);
     else if (p.stats_lds == 2) off = a16((size_t)Kmax * LDS_MEANS_PER_SP);
     p.gate_words = (int32_t)gwords;
     p.off_gate = (uint32_t)off;
@@ -578,10 +580,10 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
         const int thr_all[3] = {256, 512, 1024};
         LaunchShape best;
         best.ms = -1.0f;
-        const int res_all[3] = {1, 2, 0};
+        const int res_all[4] = {1, 3, 2, 0};
         for (int t = 0; t < 3; t++) {
             if (ctx->threads_forced && thr_all[t] != ctx->threads) continue;
-            for (int li = 0; li < 3; li++) {
+            for (int li = 0; li < 4; li++) {
                 const int l = res_all[li];
                 if (lds_residency(ctx->lds_limit, Kmax, gated, l) != l) continue;   // does not fit
                 for (int py = 1; py >= 0; py--) {

@@ -52,7 +52,8 @@ struct Prop {
 // cap* entries in LDS and spill to global scratch; the visit bitmap of the
 // frontier rebuild is used when it covers the stage's blocks.
 struct LdsPlan {
-    int32_t stats_lds;       // 0 global, 1 statistics, means, flow in LDS, 2 means in LDS
+    int32_t stats_lds;       // 0 global, 1 statistics, means, flow in LDS, 2 means in LDS,
+                             // 3 means and flow in LDS
     int32_t capl, capp, capx, bm_words;
     int32_t gate_words;      // LDS bitmap of the gate bits (0: no gate in this launch)
     uint32_t off_lists, off_props, off_chg, off_bm, off_gate;
@@ -144,7 +145,9 @@ hipError_t launch_boundary_miss(const int32_t *ref, const int32_t *test, int W, 
 // bytes of LDS per superpixel when the statistics live in LDS: sums, means
 // record, flow counters
 constexpr size_t LDS_PER_SP = 6 * 8 + MN_STRIDE * 4 + 2 * 4;
-// bytes of LDS per superpixel when only the means records live in LDS
+// bytes of LDS per superpixel when only the means records live in LDS, and
+// when the flow counters join them
 constexpr size_t LDS_MEANS_PER_SP = MN_STRIDE * 4;
+constexpr size_t LDS_MEANS_FLOW_PER_SP = MN_STRIDE * 4 + 2 * 4;
 
 }  // namespace rapid

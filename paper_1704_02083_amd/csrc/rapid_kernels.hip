@@ -729,7 +729,8 @@ __device__ __attribute__((noinline)) void gate_point(const Job &J, const int64_t
 
 // SL: where the per-superpixel state lives -- 0 all in global memory, 1
 // statistics, means records and flow counters in LDS, 2 the means records
-// in LDS (the hot reads of P1) and the rest in global memory.
+// in LDS (the hot reads of P1) and the rest in global memory, 3 the means
+// records and the flow counters in LDS, the statistics in global memory.
 template <int SL, int GM, bool MERGE>
 __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, Sched sc, LdsPlan lp,
                                                   int s_begin, int s_end, int flags,
@@ -750,10 +751,10 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
         st = reinterpret_cast<int64_t *>(smem);
         mn = reinterpret_cast<int32_t *>(st + 6 * (int64_t)K);   // K records of 16 bytes, 16-byte aligned
         fl = mn + MN_STRIDE * (int64_t)K;
-    } else if (SL == 2) {
+    } else if (SL == 2 || SL == 3) {
         st = J.stats;
         mn = reinterpret_cast<int32_t *>(smem);
-        fl = J.flow;
+        fl = SL == 3 ? mn + MN_STRIDE * (int64_t)K : J.flow;
     } else {
         st = J.stats;
         mn = J.means;
@@ -849,8 +850,10 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
             const uint32_t gp_off = SL == 1 ? lp.off_lists : 0u;
             gate_point(J, st, s - 1, sc.B[s - 1], sc.F, sc.mlp_w, sc.mlp_thresh, smem + gp_off, lp.total - gp_off,
                        tid, nt);
-            if (SL == 2)
+            if (SL == 2 || SL == 3)
                 for (int k = tid; k < K; k += nt) refresh_sp(st, mn, k, sc);
+            if (SL == 3)   // the flow counters are zero between class phases
+                for (int64_t i = tid; i < 2 * (int64_t)K; i += nt) fl[i] = 0;
             // the frontier bitmap shares that LDS and must start the stage clear
             for (int i = tid; i < lp.bm_words; i += nt) l_bm[i] = 0;
         }
@@ -1275,10 +1278,11 @@ hipError_t launch_refine(const Job *jobs_dev, int n_jobs, const Sched &sc, const
     // instantiations: where the per-superpixel state lives, gate mode, merge
     // on underflow
 #define RAPID_K(sl, gm) {k_refine<sl, gm, false>, k_refine<sl, gm, true>}
-    static const Kern table[3][3][2] = {
+    static const Kern table[4][3][2] = {
         {RAPID_K(0, GM_NONE), RAPID_K(0, GM_BITS), RAPID_K(0, GM_FUSED)},
         {RAPID_K(1, GM_NONE), RAPID_K(1, GM_BITS), RAPID_K(1, GM_FUSED)},
-        {RAPID_K(2, GM_NONE), RAPID_K(2, GM_BITS), RAPID_K(2, GM_FUSED)}};
+        {RAPID_K(2, GM_NONE), RAPID_K(2, GM_BITS), RAPID_K(2, GM_FUSED)},
+        {RAPID_K(3, GM_NONE), RAPID_K(3, GM_BITS), RAPID_K(3, GM_FUSED)}};
 #undef RAPID_K
     const int gm = (flags & FLAG_GATE) ? GM_FUSED : lp.gate_words > 0 ? GM_BITS : GM_NONE;
     const Kern fn = table[lp.stats_lds][gm][sc.merge ? 1 : 0];

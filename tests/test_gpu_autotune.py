@@ -24,7 +24,7 @@ def _batch(n):
 
 
 def test_every_launch_shape_same_labels(gpu_lib):
-    """130 images (enough for the in-launch pyramid): all 18 shapes give the
+    """130 images (enough for the in-launch pyramid): all 24 shapes give the
     labels of the default shape; image 7 also equals the oracle."""
     import torch
     imgs, rgbs = _batch(130)
@@ -38,7 +38,7 @@ def test_every_launch_shape_same_labels(gpu_lib):
     old = os.environ.get("RAPID_SHAPE")
     try:
         for t in (256, 512, 1024):
-            for lds in (1, 2, 0):
+            for lds in (1, 3, 2, 0):
                 for py in (1, 0):
                     os.environ["RAPID_SHAPE"] = "%d,%d,%d" % (t, lds, py)
                     _say("case: shape threads %d stats_lds %d pyramid %d" % (t, lds, py))

@@ -369,10 +369,11 @@ def test_state_gate_refuses_non_finite_model(ctx, gpu_lib):
     st.close()
 
 
-@pytest.mark.parametrize("res", [0, 1, 2])
+@pytest.mark.parametrize("res", [0, 1, 2, 3])
 def test_gated_segment_every_residency(gpu_lib, res):
     """The single-launch gated path with the per-superpixel state all in
-    global memory (0), all in LDS (1) or only the means records in LDS (2):
+    global memory (0), all in LDS (1), only the means records in LDS (2) or
+    the means records and flow counters (3):
     the gate point borrows the LDS that holds no statistics, so every
     residency must still give the oracle's features, bits and labels."""
     import os
