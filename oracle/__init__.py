@@ -34,8 +34,22 @@ GATE_RULES = {"either": 0, "both": 1, "differ": 2}
 MAX_STAGES = 8
 
 
+def build_sanitized(out: str) -> str:
+    """The oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (any report aborts), for the sanitizer test; load it by setting
+    ORACLE_LIB=out (and preloading gcc's libasan) in a fresh process."""
+    subprocess.check_call(
+        ["gcc", "-O1", "-g", "-std=gnu11", "-Wall", "-ffp-contract=off", "-shared", "-fPIC",
+         "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+         "-o", out, _SRC, "-lm"])
+    return out
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with the host C compiler (no GPU code involved)."""
+    """Compile the oracle with the host C compiler (no GPU code involved);
+    ORACLE_LIB names another build to load instead (a sanitized one)."""
+    if os.environ.get("ORACLE_LIB"):
+        return os.environ["ORACLE_LIB"]
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
         os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "rapid_oracle.h"))
     ):
