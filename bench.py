@@ -190,6 +190,7 @@ def main():
     ap.add_argument("--gated", action="store_true",
                     help="H&E workloads: also train the gate and time the gated path")
     ap.add_argument("--gate-rule", default="both", choices=["either", "both"])
+    ap.add_argument("--save-gate", default=None, help="write the trained gate network to this .npz file")
     ap.add_argument("--gate-level", type=int, default=3, choices=[1, 2, 3],
                     help="level of the schedule 16 | 8,4 | 2 | 1 from which the gate applies")
     ap.add_argument("--train-tiles", type=int, default=64, help="4096x4096 training tiles of the gate")
@@ -352,7 +353,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def train_gate(ctx, rule: str, n_tiles: int, seed: int = 0, gate_level: int = 3):
+def train_gate(ctx, rule: str, n_tiles: int, seed: int = 0, gate_level: int = 3, save: str | None = None):
     """Gate network trained on n_tiles synthetic 4096x4096 H&E tiles (seeds
     5000...) with 32-px cells: features and targets from plain runs, the
     training itself, all on the GPU through the C-ABI."""
@@ -370,6 +371,8 @@ def train_gate(ctx, rule: str, n_tiles: int, seed: int = 0, gate_level: int = 3)
     t0 = time.perf_counter()
     master, w = gate.train(ctx, X, t, epochs=20, batch=4096, seed=seed)
     torch.cuda.synchronize()
+    if save:
+        gate.save_model(save, master, w, 0.0, gate_level, rule)
     return w, {"tiles": n_tiles, "samples": int(X.shape[0]), "positive_rate": round(float(t.float().mean().item()), 4),
                "train_s": round(time.perf_counter() - t0, 3)}
 
@@ -381,7 +384,7 @@ def bench_gated(args, ctx, rgb, labels, plain, W, H, dt_plain):
     calibrated on held-out tiles for boundary recall >= 0.99."""
     import torch
     from paper_1704_02083_amd import gate, metrics, params, rapid, synth_gpu
-    w, info = train_gate(ctx, args.gate_rule, args.train_tiles, gate_level=args.gate_level)
+    w, info = train_gate(ctx, args.gate_rule, args.train_tiles, gate_level=args.gate_level, save=args.save_gate)
     print("bench: gate trained (%s)" % info, file=sys.stderr, flush=True)
     if args.workload in ("slide", "slide65k"):
         pg = params.gated(2048, 2048, 4096, rule=args.gate_rule, gate_level=args.gate_level)

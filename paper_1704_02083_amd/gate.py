@@ -66,6 +66,29 @@ def train(ctx, X, t, epochs: int = 20, batch: int = 4096, lr: float = 1e-3, seed
     return master, w
 
 
+def save_model(path: str, master, w_bf16, thresh: float = 0.0, gate_level: int = 3, rule: str = "both"):
+    """Write a trained gate to an .npz file (no pickled objects): the fp32
+    master weights, their bf16 bit patterns, the threshold and the schedule
+    point it was trained for."""
+    np.savez(path, master=np.asarray(master.cpu().numpy() if hasattr(master, "cpu") else master,
+                                     dtype=np.float32),
+             w_bf16=np.asarray(w_bf16.cpu().numpy() if hasattr(w_bf16, "cpu") else w_bf16).view(np.int16),
+             thresh=np.float64(thresh), gate_level=np.int32(gate_level), rule=np.array(rule))
+
+
+def load_model(path: str, device="cuda"):
+    """Read a gate written by save_model: (master fp32, w_bf16 int16 bit
+    patterns as torch tensors on device, dict of threshold, gate level and
+    rule).  The bf16 patterns must round the master weights to nearest even."""
+    import torch
+    with np.load(path, allow_pickle=False) as z:
+        master, wb = z["master"], z["w_bf16"]
+        meta = {"thresh": float(z["thresh"]), "gate_level": int(z["gate_level"]), "rule": str(z["rule"])}
+    if master.shape != (5313,) or wb.shape != (5313,):
+        raise ValueError("not a gate model: %s" % path)
+    return torch.from_numpy(master).to(device), torch.from_numpy(wb).to(device), meta
+
+
 def boundary_recall(ctx, ref, test, radius: int = 2) -> float:
     """Boundary recall of test against ref, on the GPU (any map size)."""
     _, nb, nm = ctx.boundary_miss(ref, test, radius=radius, counts=False)

@@ -64,3 +64,22 @@ def test_roi_mask_maps_superpixel_classes():
     labels = torch.tensor([[0, 0, 1], [2, 1, 1]], dtype=torch.int32)
     g = torch.tensor([1, 0, 1], dtype=torch.uint8)
     assert gate.roi_mask(labels, g).tolist() == [[True, True, False], [True, False, False]]
+
+
+def test_gate_model_round_trip(tmp_path):
+    """A trained gate survives save/load bit for bit (no pickled objects)."""
+    import torch
+    from oracle import mlp
+    from paper_1704_02083_amd import gate
+    theta = gate.init_master(5)
+    wb = torch.from_numpy(mlp.to_bf16_bits(theta).view(np.int16))
+    path = str(tmp_path / "gate.npz")
+    gate.save_model(path, torch.from_numpy(theta), wb, thresh=0.75, gate_level=3, rule="both")
+    m, w, meta = gate.load_model(path, device="cpu")
+    assert (m.numpy() == theta).all() and (w.numpy() == wb.numpy()).all()
+    assert meta == {"thresh": 0.75, "gate_level": 3, "rule": "both"}
+    np.savez(str(tmp_path / "bad.npz"), master=np.zeros(3, np.float32), w_bf16=np.zeros(3, np.int16),
+             thresh=0.0, gate_level=3, rule=np.array("both"))
+    import pytest
+    with pytest.raises(ValueError):
+        gate.load_model(str(tmp_path / "bad.npz"), device="cpu")
