@@ -739,7 +739,7 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
     extern __shared__ __align__(16) char smem[];
     __shared__ uint32_t s_lut[8];
     __shared__ int32_t s_cnt[9];
-    __shared__ int32_t s_nprop, s_nchg, s_nreq, s_merged;
+    __shared__ int32_t s_nprop, s_nchg, s_nreq, s_merged, s_any;
     __shared__ unsigned long long s_ctr[6];   // active proposals commits skip_min skip_topo merges
 
     const Job &J = jobs[blockIdx.x];
@@ -836,6 +836,7 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
     for (int k = tid; k < K; k += nt) refresh_sp(st, mn, k, sc);
     wg_sync();
 
+    int out_stage = s_end - 1;   // stage whose label map the output reads
     for (int s = s_begin; s < s_end; s++) {
         const int B = sc.B[s];
         const int nbx = (W + B - 1) / B, nby = (H + B - 1) / B;
@@ -880,7 +881,45 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
         const bool use_f64 = sc.f64[s] != 0;
         if (tid < 9) s_cnt[tid] = 0;
         if (tid < 6) s_ctr[tid] = 0;
+        if (tid == 0) s_any = 0;
         wg_sync();
+        if (GM != GM_NONE && (flags & FLAG_OUT) && s == s_end - 1 && s > 0 && gv.bits != nullptr) {
+            // The last stage of a launch under the gate: when no two adjacent
+            // parent blocks form an active pair, no block of the stage is a
+            // boundary element, so its one sweep finds nothing.  The stage
+            // then writes only its report and the output comes from the
+            // parent map, which spares materialising the finest map.  (The
+            // pair rules are symmetric: east and south neighbours cover
+            // every edge.)
+            const int Bp = sc.B[s - 1];
+            const int nbxp = (W + Bp - 1) / Bp, nbyp = (H + Bp - 1) / Bp;
+            const int32_t *Lp = J.lab[(s - 1) & 1];
+            bool any = false;
+            for (int64_t p = tid; p < (int64_t)nbxp * nbyp && !any; p += nt) {
+                const int pxb = (int)(p % nbxp), pyb = (int)(p / nbxp);
+                const int32_t a = Lp[p];
+                int32_t k = lab_at(Lp, pxb + 1, pyb, nbxp, nbyp);
+                any = k >= 0 && k != a && pair_on(gv, a, k);
+                k = lab_at(Lp, pxb, pyb + 1, nbxp, nbyp);
+                any = any || (k >= 0 && k != a && pair_on(gv, a, k));
+            }
+            if (any) s_any = 1;
+            wg_sync();
+            if (s_any == 0) {   // uniform
+                if (tid == 0) {
+                    rapid_stage_report r;
+                    r.level = sc.level[s];
+                    r.block = B;
+                    r.sweeps = 1;
+                    r.converged = 1;
+                    r.active = r.proposals = r.commits = r.skip_min = r.skip_topo = r.merges = 0;
+                    J.rep[s] = r;
+                }
+                out_stage = s - 1;
+                wg_sync();
+                continue;
+            }
+        }
         if (s > 0) {
             // split: each block inherits the label of the block that holds it.
             // A child is a boundary block only on a side where its parent
@@ -1225,9 +1264,9 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
         for (int64_t i = tid; i < 6 * (int64_t)K; i += nt) J.stats[i] = st[i];
     if ((flags & FLAG_OUT) && s_end > 0 && J.tile) {
         // slide tile: core pixels only, labels as slide-wide cell ids
-        const int B = sc.B[s_end - 1];
+        const int B = sc.B[out_stage];
         const int nbx = (W + B - 1) / B;
-        const int32_t *L = J.lab[(s_end - 1) & 1];
+        const int32_t *L = J.lab[out_stage & 1];
         const int64_t ncore = (int64_t)J.core_w * J.core_h;
         for (int64_t i = tid; i < ncore; i += nt) {
             const int x = J.core_x0 + (int)(i % J.core_w), y = J.core_y0 + (int)(i / J.core_w);
@@ -1236,9 +1275,9 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                 (int32_t)((J.gid_y0 + k / J.gx) * J.gid_w + J.gid_x0 + k % J.gx);
         }
     } else if ((flags & FLAG_OUT) && s_end > 0) {
-        const int B = sc.B[s_end - 1];
+        const int B = sc.B[out_stage];
         const int nbx = (W + B - 1) / B;
-        const int32_t *L = J.lab[(s_end - 1) & 1];
+        const int32_t *L = J.lab[out_stage & 1];
         if (!(B == 1 && L == J.out)) {
             for (int64_t i = tid; i < (int64_t)W * H; i += nt) {
                 int x = (int)(i % W), y = (int)(i / W);

@@ -425,3 +425,24 @@ def test_gated_large_grid_matches_oracle(ctx):
     ref, _, ref_rep = oracle.segment(img, p, gate=g)
     assert (labs[0].cpu().numpy() == ref).all()
     assert reps[0] == ref_rep
+
+
+@pytest.mark.parametrize("rule", ["either", "both", "differ"])
+def test_gated_nothing_marked_matches_oracle(ctx, rule):
+    """No superpixel marked (threshold above every logit): no pair is active
+    in the gated stages, the last one runs no sweep and the output comes
+    from the previous stage's map; labels and stage counters must still be
+    the oracle's under an all-zero gate."""
+    img, p = _he_case()
+    p = dict(p, gate_rule=rule)
+    _, wb = _rand_model(21)
+    K = oracle.n_superpixels(256, 192, p)
+    ref, _, ref_rep = oracle.segment(img, p, gate=np.zeros(K, np.uint8))
+    _say("case: gated, nothing marked, rule %s" % rule)
+    labs, reps, _, g = ctx.segment_gated([_dev(img)], p, _dev(wb), 1e9)
+    assert int(g.sum().item()) == 0
+    assert (labs[0].cpu().numpy() == ref).all()
+    assert reps[0] == ref_rep
+    # and through the caller-supplied gate of rapid_segment
+    lab, rep = ctx.segment(_dev(img), p, gate=_dev(np.zeros(K, np.uint8)))
+    assert (lab.cpu().numpy() == ref).all() and rep == ref_rep
