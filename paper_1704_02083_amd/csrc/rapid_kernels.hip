@@ -894,14 +894,25 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
             const int Bp = sc.B[s - 1];
             const int nbxp = (W + Bp - 1) / Bp, nbyp = (H + Bp - 1) / Bp;
             const int32_t *Lp = J.lab[(s - 1) & 1];
+            // four parents per lane and pass, their loads issued together
+            const int64_t npar = (int64_t)nbxp * nbyp;
             bool any = false;
-            for (int64_t p = tid; p < (int64_t)nbxp * nbyp && !any; p += nt) {
-                const int pxb = (int)(p % nbxp), pyb = (int)(p / nbxp);
-                const int32_t a = Lp[p];
-                int32_t k = lab_at(Lp, pxb + 1, pyb, nbxp, nbyp);
-                any = k >= 0 && k != a && pair_on(gv, a, k);
-                k = lab_at(Lp, pxb, pyb + 1, nbxp, nbyp);
-                any = any || (k >= 0 && k != a && pair_on(gv, a, k));
+            for (int64_t p0 = tid; p0 < npar && !any; p0 += 4 * (int64_t)nt) {
+                int32_t a[4], e[4], d[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int64_t p = p0 + u * (int64_t)nt;
+                    const int pxb = (int)(p % nbxp), pyb = (int)(p / nbxp);
+                    const bool in = p < npar;
+                    a[u] = in ? Lp[p] : -1;
+                    e[u] = in && pxb + 1 < nbxp ? Lp[p + 1] : -1;
+                    d[u] = in && pyb + 1 < nbyp ? Lp[p + nbxp] : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    any = any || (e[u] >= 0 && e[u] != a[u] && pair_on(gv, a[u], e[u]));
+                    any = any || (d[u] >= 0 && d[u] != a[u] && pair_on(gv, a[u], d[u]));
+                }
             }
             if (any) s_any = 1;
             wg_sync();
