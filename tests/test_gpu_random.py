@@ -1,0 +1,79 @@
+"""Randomised parity sweep: seeded random image sizes, schedules, weights,
+size bounds, fixed-point bits, sweep caps, merge on or off, gates with random
+rules and bits, and random launch shapes (workgroup size, residency, pyramid
+placement): labels, statistics counters and stage reports bit-exact against
+the oracle in every case."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1704_02083_amd import params, synth
+
+pytestmark = pytest.mark.gpu
+
+SCHEDULES = [
+    [(1, [16, 8, 4, 2, 1])],
+    [(1, [8, 4, 2, 1])],
+    [(1, [4, 2, 1])],
+    [(4, [2, 1]), (1, [2, 1])],
+    [(16, [1]), (4, [2, 1]), (1, [2, 1])],
+    [(8, [1]), (2, [2, 1]), (1, [1])],
+    [(1, [32, 16, 8, 4, 2, 1])],
+]
+
+
+def _case(seed):
+    rng = np.random.default_rng(1000 + seed)
+    for _ in range(50):
+        W, H = int(rng.integers(20, 220)), int(rng.integers(20, 220))
+        levels = SCHEDULES[int(rng.integers(len(SCHEDULES)))]
+        K = int(rng.integers(1, 60))
+        p = params.default_params(W, H, K, levels=levels)
+        p.update(w_col=int(rng.integers(0, 5000)), w_pos=int(rng.integers(0, 400)),
+                 w_bnd=int(rng.integers(0, 1 << 18)), frac_bits=int(rng.integers(0, 5)),
+                 max_sweeps=int(rng.integers(1, 48)), merge=bool(rng.random() < 0.4))
+        A = max(1, (W * H) // max(1, K))
+        p["min_size"] = int(rng.integers(0, max(1, A // 2)))
+        p["max_size"] = int(rng.integers(max(2, A), 3 * A + 2))
+        if len(levels) > 1 and rng.random() < 0.5:
+            p["gate_level"] = int(rng.integers(1, len(levels)))
+            p["gate_rule"] = ["either", "both", "differ"][int(rng.integers(3))]
+        try:
+            oracle.n_superpixels(W, H, p)
+            img = synth.voronoi_gradient(W, H, seed=seed, regions=(3, 20))
+            oracle.segment(img, p)   # refuses infeasible grids and parameters
+        except (RuntimeError, ValueError):
+            continue
+        return rng, W, H, p, img
+    pytest.skip("no feasible case drawn")
+
+
+@pytest.mark.parametrize("seed", range(64))
+def test_random_configuration(gpu_lib, seed):
+    import torch
+    rng = np.random.default_rng(5000 + seed)
+    _, W, H, p, img = _case(seed)
+    Kp = oracle.n_superpixels(W, H, p)
+    gate = (rng.random(Kp) < 0.5).astype(np.uint8) if p["gate_level"] >= 0 else None
+    ref, ref_stats, ref_rep = oracle.segment(img, p, gate=gate)
+    shape = "%d,%d,%d" % (int(rng.choice([256, 512, 1024])), int(rng.integers(0, 4)), int(rng.integers(0, 2)))
+    old = os.environ.get("RAPID_SHAPE")
+    os.environ["RAPID_SHAPE"] = shape
+    try:
+        print("case: seed %d %dx%d K'=%d levels %s merge %s gate %s shape %s" % (
+            seed, W, H, Kp, p["levels"], p["merge"], p.get("gate_rule") if gate is not None else None, shape),
+            flush=True)
+        c = gpu_lib.Context(0)
+        g = None if gate is None else torch.from_numpy(gate).cuda()
+        lab, rep = c.segment(torch.from_numpy(img).cuda(), p, gate=g)
+        torch.cuda.synchronize()
+        assert (lab.cpu().numpy() == ref).all()
+        assert rep == ref_rep
+        c.close()
+    finally:
+        if old is None:
+            os.environ.pop("RAPID_SHAPE", None)
+        else:
+            os.environ["RAPID_SHAPE"] = old
