@@ -24,12 +24,13 @@ SCHEDULES = [
 ]
 
 
-def _case(seed):
+def _case(seed, large=False):
     rng = np.random.default_rng(1000 + seed)
     for _ in range(50):
-        W, H = int(rng.integers(20, 220)), int(rng.integers(20, 220))
+        lo, hi = (400, 1200) if large else (20, 220)
+        W, H = int(rng.integers(lo, hi)), int(rng.integers(lo, hi))
         levels = SCHEDULES[int(rng.integers(len(SCHEDULES)))]
-        K = int(rng.integers(1, 60))
+        K = int(rng.integers(200, 3000)) if large else int(rng.integers(1, 60))
         p = params.default_params(W, H, K, levels=levels)
         p.update(w_col=int(rng.integers(0, 5000)), w_pos=int(rng.integers(0, 400)),
                  w_bnd=int(rng.integers(0, 1 << 18)), frac_bits=int(rng.integers(0, 5)),
@@ -50,11 +51,14 @@ def _case(seed):
     pytest.skip("no feasible case drawn")
 
 
-@pytest.mark.parametrize("seed", range(64))
-def test_random_configuration(gpu_lib, seed):
+@pytest.mark.parametrize("seed,large", [(s, False) for s in range(64)] + [(100 + s, True) for s in range(8)])
+def test_random_configuration(gpu_lib, seed, large):
+    """Small images in 64 cases; 8 cases of 400-1200 px with up to 3000
+    superpixels, where the per-superpixel state outgrows LDS and classes
+    take several passes of the workgroup."""
     import torch
     rng = np.random.default_rng(5000 + seed)
-    _, W, H, p, img = _case(seed)
+    _, W, H, p, img = _case(seed, large)
     Kp = oracle.n_superpixels(W, H, p)
     gate = (rng.random(Kp) < 0.5).astype(np.uint8) if p["gate_level"] >= 0 else None
     ref, ref_stats, ref_rep = oracle.segment(img, p, gate=gate)
