@@ -890,15 +890,18 @@ rapid_status prepare_batch(rapid_ctx *ctx, const rapid_image *imgs, int32_t n, c
     return RAPID_OK;
 }
 
-// bf16 weights with an all-ones exponent are Inf or NaN
-bool model_finite(const uint16_t *w_dev, hipStream_t stream)
+// The gate model's weights: 1 when every bf16 weight is finite, 0 when one
+// has an all-ones exponent (Inf or NaN), -1 when they could not be read.
+int model_check(rapid_ctx *ctx, const uint16_t *w_dev)
 {
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return -1;
     std::vector<uint16_t> h(MLP_PARAMS);
-    if (hipMemcpyAsync(h.data(), w_dev, 2 * MLP_PARAMS, hipMemcpyDeviceToHost, stream) != hipSuccess) return false;
-    if (hipStreamSynchronize(stream) != hipSuccess) return false;
+    if (hipMemcpyAsync(h.data(), w_dev, 2 * MLP_PARAMS, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess) return -1;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return -1;
     for (uint16_t v : h)
-        if ((v & 0x7F80) == 0x7F80) return false;
-    return true;
+        if ((v & 0x7F80) == 0x7F80) return 0;
+    return 1;
 }
 
 }  // namespace
@@ -939,7 +942,9 @@ static rapid_status gated_impl(rapid_ctx *ctx, const rapid_image *imgs, int32_t 
                                const TileInfo *tiles = nullptr)
 {
     if (!ctx || !imgs || n < 1 || !params || !model || !model->w_bf16_dev) return RAPID_EINVAL;
-    if (!model_finite(model->w_bf16_dev, ctx->stream)) {
+    const int mc = model_check(ctx, model->w_bf16_dev);
+    if (mc < 0) return RAPID_EDEVICE;
+    if (mc == 0) {
         rapid_status r = segment_impl(ctx, imgs, n, params, nullptr, reports, tiles);
         return r ? r : RAPID_EGATE;
     }
@@ -1209,7 +1214,9 @@ rapid_status rapid_gate(rapid_ctx *ctx, rapid_state *st, const rapid_gate_model 
     if (!ctx || !st || st->ctx != ctx || !model || !model->w_bf16_dev || !gate_dev) return RAPID_EINVAL;
     if (st->next_level < 0) return RAPID_ESTATE;
     const int64_t K = st->job.K;
-    if (!model_finite(model->w_bf16_dev, ctx->stream)) {
+    const int mc = model_check(ctx, model->w_bf16_dev);
+    if (mc < 0) return RAPID_EDEVICE;
+    if (mc == 0) {
         // refuse the model: every superpixel stays marked (refine all)
         std::lock_guard<std::mutex> lock(ctx->mu);
         if (hipSetDevice(ctx->device) != hipSuccess) return RAPID_EDEVICE;
