@@ -35,7 +35,8 @@ __device__ __forceinline__ int wave_append(int32_t *counter, bool pred)
                                            __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
     int base = 0;
     if (lane_id() == leader) base = atomicAdd(counter, __popcll(m));
-    base = __shfl(base, leader);
+    // the leader is wave-uniform: a scalar lane read, no LDS round trip
+    base = __builtin_amdgcn_readlane(base, leader);
     return pred ? base + prefix : -1;
 }
 
