@@ -283,7 +283,9 @@ def main():
         refine_ms.append(ctx.last_timings()["refine_ms"])
     tm = ctx.last_timings()
     shape = {"threads": tm["threads"], "stats_lds": tm["stats_lds"], "pyramid_in_launch": tm["pyramid"],
-             "autotuned": not args.no_autotune}
+             "workgroups_per_image": tm["workgroups"], "autotuned": not args.no_autotune}
+    # one image spread over a cooperative launch runs the k_refine_mc kernel
+    kname = "k_refine_mc" if tm["workgroups"] > 1 else "k_refine"
 
     # counters of the same (deterministic) work, from one untimed call
     if len(rgbs) == 1:
@@ -296,7 +298,7 @@ def main():
     alg = refine_alg_bytes(imgs, reps)
     achieved = alg / (avg_refine * 1e-3) / 1e9
     src_hash = kernel_source_hash()
-    traffic = profile_traffic("k_refine", args.workload + ("_merge" if args.merge else ""), src_hash)
+    traffic = profile_traffic(kname, args.workload + ("_merge" if args.merge else ""), src_hash)
     out = {
         "metric": METRIC,
         "value": round(pixels * args.steps / dt / 1e6, 3),
@@ -314,7 +316,7 @@ def main():
                    "superpixels_per_image": p["K"], "path": "plain+merge" if args.merge else "plain"},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_refine",
+            "kernel": kname,
             "achieved": round(achieved, 3),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -583,7 +585,9 @@ def bench_he(args):
     dt, ref_ms = timed(lambda: run(), steps, warm)
     tm = ctx.last_timings()
     shape = {"threads": tm["threads"], "stats_lds": tm["stats_lds"], "pyramid_in_launch": tm["pyramid"],
-             "autotuned": not args.no_autotune}
+             "workgroups_per_image": tm["workgroups"], "autotuned": not args.no_autotune}
+    # one image spread over a cooperative launch runs the k_refine_mc kernel
+    kname = "k_refine_mc" if tm["workgroups"] > 1 else "k_refine"
     plain = labels.clone()
     # per-stage counters of the same deterministic work, from one untimed call
     if args.workload in ("slide", "slide65k"):
@@ -599,11 +603,11 @@ def bench_he(args):
         "steps": steps, "warmup": warm, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": desc, "pixels": W * H, "path": "plain"},
-        "roofline": {"bound": "hbm", "kernel": "k_refine", "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "roofline": {"bound": "hbm", "kernel": kname, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "avg_launch_ms": round(avg_refine, 3), "achieved": round(achieved, 3),
                      "frac": round(achieved / HBM_PEAK_GBS, 6),
-                     "traffic": profile_traffic("k_refine", args.workload + ("_grain%d" % args.grain if args.grain > 1
-                                                                           else ""), kernel_source_hash()),
+                     "traffic": profile_traffic(kname, args.workload + ("_grain%d" % args.grain if args.grain > 1
+                                                                      else ""), kernel_source_hash()),
                      "alg_bytes_per_launch": alg},
         "launch_shape": shape,
     }

@@ -72,8 +72,9 @@ typedef struct {
      * workgroup size 256, 512 or 1024; per-superpixel state all in LDS,
      * the means records and flow counters, only the means records, or
      * nothing in LDS (as far as they fit); block-sum pyramid inside the
-     * launch or in
-     * separate launches -- and keeps the fastest; later calls of that
+     * launch or in separate launches; and, for a single image without gate
+     * or merge, the image spread over 8 .. 256 workgroups of a cooperative
+     * launch -- and keeps the fastest; later calls of that
      * shape use it.  Every candidate computes the same labels (the result
      * never depends on the shape), so tuning costs time only.  Only calls
      * that start from the image tune (not rapid_refine_level).
@@ -96,6 +97,9 @@ typedef struct {
                               the means records in LDS, 0 all global,   */
     int32_t pyramid;       /* pyramid inside the refinement launch (1)   */
     int32_t tuned;         /* 1 when this call ran the autotuner         */
+    int32_t workgroups;    /* workgroups per image: 1, or the size of the
+                              cooperative launch that spread a single
+                              image over many workgroups                  */
 } rapid_timings;
 
 /* Method parameters, all integers (the paper gives no values for the
@@ -186,10 +190,11 @@ typedef struct {
 /* Create a context on cfg->device: builds the 256-entry simple-point table
  * of the topology term (Eq. (1), E_topo) and uploads it.  *out receives the
  * context; rapid_destroy releases it.  Environment: RAPID_THREADS=n (64 ..
- * 1024, a multiple of 64) fixes the workgroup size; RAPID_SHAPE=t,l,p fixes
- * the whole launch shape (workgroup size, residency l as in
- * rapid_timings.stats_lds when it fits, pyramid inside the launch) and
- * bypasses the autotuner. */
+ * 1024, a multiple of 64) fixes the workgroup size; RAPID_SHAPE=t,l,p[,g]
+ * fixes the whole launch shape (workgroup size, residency l as in
+ * rapid_timings.stats_lds when it fits, pyramid inside the launch, and g
+ * workgroups per image where a single plain image may spread over a
+ * cooperative launch) and bypasses the autotuner. */
 rapid_status rapid_init(const rapid_config *cfg, rapid_ctx **out);
 void rapid_destroy(rapid_ctx *ctx);   /* NULL-safe; waits for queued work */
 

@@ -24,6 +24,8 @@ struct LaunchShape {
     int threads = 1024;
     int stats_lds = 1;
     int pyramid = 1;
+    int groups = 1;    // workgroups per job: > 1 spreads a single image over
+                       // a cooperative launch (state global, pyramid apart)
     float ms = 0.0f;   // autotuner: time of the choice
 };
 
@@ -278,6 +280,7 @@ struct Layout {
     size_t off_stats, off_means, off_flow, off_rep;
     size_t off_fmean, off_facc, off_moved, off_moms;
     size_t off_merge[8];   // merge on: mreq mlist mbox mkey mlen mstate mpick mwin
+    size_t off_ctl;
     int64_t capc = 0;
 };
 
@@ -308,6 +311,7 @@ Layout plan(int32_t W, int32_t H, int32_t K, const Sched &sc, int moms_stage = -
     L.off_means = take(4 * MN_STRIDE * (size_t)K);
     L.off_flow = take(4 * 2 * (size_t)K);
     L.off_rep = take(sizeof(rapid_stage_report) * MAXST);
+    L.off_ctl = take(4 * (size_t)CTL_WORDS);
     L.off_fmean = take(4 * 3 * (size_t)K);
     L.off_facc = take(8 * FACC * (size_t)K);
     L.off_moved = take(8 * (size_t)K);
@@ -353,6 +357,7 @@ void fill_job(Job &J, char *base, const Layout &L, const rapid_image *img, int32
     J.means = reinterpret_cast<int32_t *>(base + L.off_means);
     J.flow = reinterpret_cast<int32_t *>(base + L.off_flow);
     J.rep = reinterpret_cast<rapid_stage_report *>(base + L.off_rep);
+    J.ctl = reinterpret_cast<uint32_t *>(base + L.off_ctl);
     J.gate = gate;
     J.fmean = reinterpret_cast<int32_t *>(base + L.off_fmean);
     J.facc = reinterpret_cast<int64_t *>(base + L.off_facc);
@@ -448,7 +453,7 @@ std::string shape_key(const std::vector<Job> &jobs, const Sched &sc, int s_begin
 
 // Cache file: one JSON object, one entry per line:
 //   {"rapid_autotune": 1, "arch": "<gcnArchName>", "entries": {
-//   "<key>": [threads, stats_lds, pyramid, ms],
+//   "<key>": [threads, stats_lds, pyramid, groups, ms],
 //   ...
 //   }}
 void cache_load(rapid_ctx *ctx)
@@ -468,9 +473,16 @@ void cache_load(rapid_ctx *ctx)
         if (!arch_ok) break;
         char key[1024];
         LaunchShape sh;
-        if (std::sscanf(line, " \"%1023[^\"]\": [%d, %d, %d, %f]", key, &sh.threads, &sh.stats_lds, &sh.pyramid,
-                        &sh.ms) == 5 &&
-            sh.threads >= 64 && sh.threads <= 1024 && sh.threads % 64 == 0)
+        // entries without the groups field (one workgroup per job) are read too
+        const int got = std::sscanf(line, " \"%1023[^\"]\": [%d, %d, %d, %d, %f]", key, &sh.threads, &sh.stats_lds,
+                                    &sh.pyramid, &sh.groups, &sh.ms);
+        if (got != 6) {
+            sh.groups = 1;
+            if (std::sscanf(line, " \"%1023[^\"]\": [%d, %d, %d, %f]", key, &sh.threads, &sh.stats_lds, &sh.pyramid,
+                            &sh.ms) != 5)
+                continue;
+        }
+        if (sh.threads >= 64 && sh.threads <= 1024 && sh.threads % 64 == 0 && sh.groups >= 1 && sh.groups <= 4096)
             ctx->tuned[key] = sh;
     }
     std::fclose(f);
@@ -485,8 +497,8 @@ void cache_save(const rapid_ctx *ctx)
     std::fprintf(f, "{\"rapid_autotune\": 1, \"arch\": \"%s\", \"entries\": {\n", ctx->arch.c_str());
     size_t i = 0;
     for (const auto &e : ctx->tuned)
-        std::fprintf(f, "\"%s\": [%d, %d, %d, %.4f]%s\n", e.first.c_str(), e.second.threads, e.second.stats_lds,
-                     e.second.pyramid, e.second.ms, ++i < ctx->tuned.size() ? "," : "");
+        std::fprintf(f, "\"%s\": [%d, %d, %d, %d, %.4f]%s\n", e.first.c_str(), e.second.threads, e.second.stats_lds,
+                     e.second.pyramid, e.second.groups, e.second.ms, ++i < ctx->tuned.size() ? "," : "");
     std::fprintf(f, "}}\n");
     std::fclose(f);
     std::rename(tmp.c_str(), ctx->cache_path.c_str());
@@ -521,6 +533,15 @@ rapid_status launch_shape(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sc
                      "gate_words %d total %u\n",
                      sh.threads, ctx->lds_limit, lp.stats_lds, lp.capl, lp.capp, lp.capx, lp.bm_words,
                      lp.gate_words, lp.total);
+    if (sh.groups > 1) {
+        // one image on many workgroups: its control words start at zero
+        HIPCHK(hipMemsetAsync(jobs[0].ctl, 0, 4 * (size_t)CTL_WORDS, ctx->stream));
+        if (e1) HIPCHK(hipEventRecord(e1, ctx->stream));
+        HIPCHK(launch_refine_mc(ctx->jobs_dev, sh.groups, sc, s_begin, s_end, flags, ctx->lut_dev, sh.threads,
+                                ctx->stream));
+        if (e2) HIPCHK(hipEventRecord(e2, ctx->stream));
+        return RAPID_OK;
+    }
     if (e1) HIPCHK(hipEventRecord(e1, ctx->stream));
     HIPCHK(launch_refine(ctx->jobs_dev, (int)n, sc, lp, s_begin, s_end, flags, ctx->lut_dev, sh.threads,
                          ctx->stream));
@@ -560,6 +581,11 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
 
     // launch shape: the tuned one for this problem shape, else the default
     // (enough jobs to fill the chip: the pyramid inside the launch)
+    // a single plain image may spread over the workgroups of a cooperative
+    // launch (no gate, no merge, not a slide tile)
+    int coop_max = 0;
+    if (n == 1 && !gated && !sc.merge && !jobs[0].tile && !(flags & FLAG_GATE))
+        HIPCHK(max_coop_groups(1024, &coop_max));
     LaunchShape sh;
     sh.threads = ctx->threads;
     sh.stats_lds = lds_residency(ctx->lds_limit, Kmax, gated, 1);
@@ -600,13 +626,39 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
                 }
             }
         }
+        // one image on 8 .. 256 workgroups of 1024 lanes
+        if (!ctx->threads_forced || ctx->threads == 1024)
+            for (int g = 8; g <= std::min(coop_max, 256); g *= 2) {
+                LaunchShape c;
+                c.threads = 1024;
+                c.stats_lds = 0;
+                c.pyramid = 0;
+                c.groups = g;
+                rapid_status r = launch_shape(ctx, jobs, sc, s_begin, s_end, flags, Kmax, nbF_max, gated, c,
+                                              ctx->tev[0], nullptr, ctx->tev[1]);
+                if (r) return r;
+                HIPCHK(hipEventSynchronize(ctx->tev[1]));
+                HIPCHK(hipEventElapsedTime(&c.ms, ctx->tev[0], ctx->tev[1]));
+                if (best.ms < 0.0f || c.ms < best.ms) best = c;
+            }
         sh = best;
         ctx->tuned[key] = best;
         ctx->last_tuned = 1;
         cache_save(ctx);
         if (ctx->verbose)
-            std::fprintf(stderr, "rapid: tuned %s -> threads %d stats_lds %d pyramid %d (%.3f ms)\n", key.c_str(),
-                         best.threads, best.stats_lds, best.pyramid, best.ms);
+            std::fprintf(stderr, "rapid: tuned %s -> threads %d stats_lds %d pyramid %d groups %d (%.3f ms)\n",
+                         key.c_str(), best.threads, best.stats_lds, best.pyramid, best.groups, best.ms);
+    }
+    if (sh.groups > 1) {
+        // the cooperative shape where this call allows it (state global,
+        // pyramid in separate launches), else one workgroup per job
+        sh.groups = std::min(sh.groups, coop_max);
+        if (sh.groups > 1) {
+            sh.stats_lds = 0;
+            sh.pyramid = 0;
+        } else {
+            sh.groups = 1;
+        }
     }
     sh.stats_lds = lds_residency(ctx->lds_limit, Kmax, gated, sh.stats_lds);
     ctx->last = sh;
@@ -622,6 +674,13 @@ rapid_status fetch_reports(rapid_ctx *ctx, const std::vector<Job> &jobs, const S
                            int s_end, rapid_report *reports)
 {
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (ctx->last.groups > 1 && jobs.size() == 1) {
+        // a cooperative launch whose grid barrier gave up left its workgroups
+        // early: its labels are not the method's
+        uint32_t abort_w = 0;
+        HIPCHK(hipMemcpy(&abort_w, jobs[0].ctl + CTL_ABORT, 4, hipMemcpyDeviceToHost));
+        if (abort_w) return RAPID_EDEVICE;
+    }
     for (size_t j = 0; j < jobs.size(); j++) {
         rapid_report &R = reports[j];
         std::memset(&R, 0, sizeof R);
@@ -709,8 +768,9 @@ rapid_status rapid_init(const rapid_config *cfg, rapid_ctx **out)
     }
     if (const char *t = std::getenv("RAPID_SHAPE")) {
         LaunchShape f;
-        if (std::sscanf(t, "%d,%d,%d", &f.threads, &f.stats_lds, &f.pyramid) == 3 && f.threads >= 64 &&
-            f.threads <= 1024 && f.threads % 64 == 0) {
+        const int got = std::sscanf(t, "%d,%d,%d,%d", &f.threads, &f.stats_lds, &f.pyramid, &f.groups);
+        if ((got == 3 || got == 4) && f.threads >= 64 && f.threads <= 1024 && f.threads % 64 == 0 &&
+            f.groups >= 1 && f.groups <= 4096) {
             ctx->forced = f;
             ctx->shape_forced = true;
         }
@@ -768,6 +828,7 @@ rapid_status rapid_last_timings(rapid_ctx *ctx, rapid_timings *out)
     out->stats_lds = ctx->last.stats_lds;
     out->pyramid = ctx->last.pyramid;
     out->tuned = ctx->last_tuned;
+    out->workgroups = ctx->last.groups;
     return RAPID_OK;
 }
 

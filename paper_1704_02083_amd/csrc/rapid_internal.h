@@ -108,7 +108,16 @@ struct Job {
     int4 *mbox;
     int32_t *mkey, *mlen, *mstate;
     int32_t *mpick, *mwin;
+    // control words of a launch that spreads this job over many workgroups
+    // (CTL_WORDS, zeroed by the host before each such launch)
+    uint32_t *ctl;
 };
+
+// Control words of a cooperative launch (k_refine_mc): the grid barrier's
+// arrival counter and abort word on lines of their own, the class counts
+// (two buffers of 9), the proposal counter, the changed-block counters (two
+// buffers) and the stage counters (6 x uint64 at a 64-bit aligned word).
+enum { CTL_BAR = 0, CTL_ABORT = 32, CTL_CNT = 64, CTL_NPROP = 96, CTL_NCHG = 98, CTL_CTR = 128, CTL_WORDS = 256 };
 
 // merge on underflow: neighbour slots per asker
 constexpr int MERGE_NB = 8;
@@ -119,6 +128,12 @@ hipError_t launch_expand(const int32_t *L, int W, int H, int B, int32_t *out, in
 hipError_t launch_refine(const Job *jobs_dev, int n_jobs, const Sched &sc, const LdsPlan &lp,
                          int s_begin, int s_end, int flags, const uint32_t *lut_dev, int threads,
                          hipStream_t stream);
+// one job on `groups` workgroups of a cooperative launch (no gate, no merge,
+// not a slide tile); max_coop_groups: the most workgroups of `threads`
+// lanes that can be resident together on the current device
+hipError_t launch_refine_mc(const Job *jobs_dev, int groups, const Sched &sc, int s_begin, int s_end, int flags,
+                            const uint32_t *lut_dev, int threads, hipStream_t stream);
+hipError_t max_coop_groups(int threads, int *out);
 
 // gate network size and feature accumulators
 constexpr int MLP_PARAMS = 5313;

@@ -732,6 +732,115 @@ __device__ __attribute__((noinline)) void gate_point(const Job &J, const int64_t
 // statistics, means records and flow counters in LDS, 2 the means records
 // in LDS (the hot reads of P1) and the rest in global memory, 3 the means
 // records and the flow counters in LDS, the statistics in global memory.
+// P1 for one active block bi of the current class: the source keeps its
+// minimum size (Sec. 3.1), the block is a simple point of its label (the
+// topology rule, 3x3 window), then the strict argmin of E' over the source
+// and its distinct 4-neighbour labels that stay within the maximum size
+// (Eq. (3); ties keep the source or the smaller label).  Reads the
+// class-start state only.
+template <bool MERGE>
+__device__ __forceinline__ void propose_block(const Job &J, int s, int B, int32_t bi, int nbx, int nby, int W,
+                                              int H, const int32_t *L, const int32_t *mn, const uint32_t *s_lut,
+                                              const Sched &sc, const GateView &gv, bool use_f64, int32_t *s_nreq,
+                                              int32_t &a, int32_t &best, int64_t &m, uint64_t &Ipk, bool &prop,
+                                              bool &smin, bool &stopo)
+{
+    const int bx = bi % nbx, by = bi / nbx;
+    const bool hw = bx > 0, he = bx + 1 < nbx, hn = by > 0, hs = by + 1 < nby;
+    // every global load of the block at once: its label,
+    // its 3x3 ring and its colour sum
+    const int32_t *Lc = L + bi;
+    a = Lc[0];
+    int32_t rl[8];
+    rl[0] = (hn && hw) ? Lc[-nbx - 1] : -1;
+    rl[1] = hn ? Lc[-nbx] : -1;
+    rl[2] = (hn && he) ? Lc[-nbx + 1] : -1;
+    rl[3] = hw ? Lc[-1] : -1;
+    rl[4] = he ? Lc[1] : -1;
+    rl[5] = (hs && hw) ? Lc[nbx - 1] : -1;
+    rl[6] = hs ? Lc[nbx] : -1;
+    rl[7] = (hs && he) ? Lc[nbx + 1] : -1;
+    int64_t I[3];
+    block_rgb(J, s, B, bi, bx, by, I);
+    Ipk = pack_rgb(I[0], I[1], I[2]);
+    Geo g = block_geo(bx, by, B, W, H);
+    m = g.m;
+    int4 ra;
+    int2 rb;
+    load_mn(mn, a, ra, rb);
+    if ((int64_t)rb.y - g.m < sc.min_size) {
+        smin = true;
+        if (MERGE) merge_ask(J, a, s_nreq);
+    } else {
+        uint32_t mask = 0;
+#pragma unroll
+        for (int q = 0; q < 8; q++) mask |= (rl[q] == a ? 1u : 0u) << q;
+        if (!((s_lut[mask >> 5] >> (mask & 31)) & 1u)) {
+            stopo = true;
+        } else {
+            // 4-neighbours W, E, N, S and their shared edge lengths
+            const int32_t nl[4] = {rl[3], rl[4], rl[1], rl[6]};
+            const int el[4] = {g.h, g.h, g.w, g.w};
+            // candidate labels: distinct, != a, ascending
+            // (sorting network; excluded values sink as INT_MAX)
+            int32_t q0 = (nl[0] < 0 || nl[0] == a) ? INT32_MAX : nl[0];
+            int32_t q1 = (nl[1] < 0 || nl[1] == a) ? INT32_MAX : nl[1];
+            int32_t q2 = (nl[2] < 0 || nl[2] == a) ? INT32_MAX : nl[2];
+            int32_t q3 = (nl[3] < 0 || nl[3] == a) ? INT32_MAX : nl[3];
+            int32_t t0 = min(q0, q1), t1 = max(q0, q1), t2 = min(q2, q3), t3 = max(q2, q3);
+            int32_t s0 = min(t0, t2), s2 = max(t0, t2), s1 = min(t1, t3), s3 = max(t1, t3);
+            int32_t u1 = min(s1, s2), u2 = max(s1, s2);
+            const int32_t cs[4] = {s0, u1, u2, s3};
+            int bnd_a = 0;
+#pragma unroll
+            for (int d = 0; d < 4; d++) bnd_a += (nl[d] >= 0 && nl[d] != a) ? el[d] : 0;
+            best = a;
+            if (use_f64) {
+                const double dm = (double)g.m, dI0 = (double)I[0], dI1 = (double)I[1],
+                             dI2 = (double)I[2], dpx = (double)g.px, dpy = (double)g.py;
+                double estar = energy_f64(ra, rb, sc, dm, dI0, dI1, dI2, dpx, dpy, sc.d_wb * (double)bnd_a);
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int32_t k = cs[u];
+                    if (k == INT32_MAX || (u > 0 && k == cs[u - 1])) continue;
+                    int4 ka;
+                    int2 kb;
+                    load_mn(mn, k, ka, kb);
+                    if ((int64_t)kb.y + g.m > sc.max_size) continue;
+                    int bnd = 0;
+#pragma unroll
+                    for (int d = 0; d < 4; d++) bnd += (nl[d] >= 0 && nl[d] != k) ? el[d] : 0;
+                    double ek = energy_f64(ka, kb, sc, dm, dI0, dI1, dI2, dpx, dpy, sc.d_wb * (double)bnd);
+                    if (ek < estar) {
+                        estar = ek;
+                        best = k;
+                    }
+                }
+            } else {
+                int64_t estar = block_energy(ra, rb, g, I, bnd_a, sc);
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int32_t k = cs[u];
+                    if (k == INT32_MAX || (u > 0 && k == cs[u - 1])) continue;
+                    int4 ka;
+                    int2 kb;
+                    load_mn(mn, k, ka, kb);
+                    if ((int64_t)kb.y + g.m > sc.max_size) continue;
+                    int bnd = 0;
+#pragma unroll
+                    for (int d = 0; d < 4; d++) bnd += (nl[d] >= 0 && nl[d] != k) ? el[d] : 0;
+                    int64_t ek = block_energy(ka, kb, g, I, bnd, sc);
+                    if (ek < estar) {
+                        estar = ek;
+                        best = k;
+                    }
+                }
+            }
+            prop = best != a && pair_on(gv, a, best);
+        }
+    }
+}
+
 template <int SL, int GM, bool MERGE>
 __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, Sched sc, LdsPlan lp,
                                                   int s_begin, int s_end, int flags,
@@ -1010,100 +1119,8 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                     uint64_t Ipk = 0;
                     if (e < ncls) {
                         bi = list_get(llst, capl, J.lists, c * capg, e);
-                        const int bx = bi % nbx, by = bi / nbx;
-                        const bool hw = bx > 0, he = bx + 1 < nbx, hn = by > 0, hs = by + 1 < nby;
-                        // every global load of the block at once: its label,
-                        // its 3x3 ring and its colour sum
-                        const int32_t *Lc = L + bi;
-                        a = Lc[0];
-                        int32_t rl[8];
-                        rl[0] = (hn && hw) ? Lc[-nbx - 1] : -1;
-                        rl[1] = hn ? Lc[-nbx] : -1;
-                        rl[2] = (hn && he) ? Lc[-nbx + 1] : -1;
-                        rl[3] = hw ? Lc[-1] : -1;
-                        rl[4] = he ? Lc[1] : -1;
-                        rl[5] = (hs && hw) ? Lc[nbx - 1] : -1;
-                        rl[6] = hs ? Lc[nbx] : -1;
-                        rl[7] = (hs && he) ? Lc[nbx + 1] : -1;
-                        int64_t I[3];
-                        block_rgb(J, s, B, bi, bx, by, I);
-                        Ipk = pack_rgb(I[0], I[1], I[2]);
-                        Geo g = block_geo(bx, by, B, W, H);
-                        m = g.m;
-                        int4 ra;
-                        int2 rb;
-                        load_mn(mn, a, ra, rb);
-                        if ((int64_t)rb.y - g.m < sc.min_size) {
-                            smin = true;
-                            if (MERGE) merge_ask(J, a, &s_nreq);
-                        } else {
-                            uint32_t mask = 0;
-#pragma unroll
-                            for (int q = 0; q < 8; q++) mask |= (rl[q] == a ? 1u : 0u) << q;
-                            if (!((s_lut[mask >> 5] >> (mask & 31)) & 1u)) {
-                                stopo = true;
-                            } else {
-                                // 4-neighbours W, E, N, S and their shared edge lengths
-                                const int32_t nl[4] = {rl[3], rl[4], rl[1], rl[6]};
-                                const int el[4] = {g.h, g.h, g.w, g.w};
-                                // candidate labels: distinct, != a, ascending
-                                // (sorting network; excluded values sink as INT_MAX)
-                                int32_t q0 = (nl[0] < 0 || nl[0] == a) ? INT32_MAX : nl[0];
-                                int32_t q1 = (nl[1] < 0 || nl[1] == a) ? INT32_MAX : nl[1];
-                                int32_t q2 = (nl[2] < 0 || nl[2] == a) ? INT32_MAX : nl[2];
-                                int32_t q3 = (nl[3] < 0 || nl[3] == a) ? INT32_MAX : nl[3];
-                                int32_t t0 = min(q0, q1), t1 = max(q0, q1), t2 = min(q2, q3), t3 = max(q2, q3);
-                                int32_t s0 = min(t0, t2), s2 = max(t0, t2), s1 = min(t1, t3), s3 = max(t1, t3);
-                                int32_t u1 = min(s1, s2), u2 = max(s1, s2);
-                                const int32_t cs[4] = {s0, u1, u2, s3};
-                                int bnd_a = 0;
-#pragma unroll
-                                for (int d = 0; d < 4; d++) bnd_a += (nl[d] >= 0 && nl[d] != a) ? el[d] : 0;
-                                best = a;
-                                if (use_f64) {
-                                    const double dm = (double)g.m, dI0 = (double)I[0], dI1 = (double)I[1],
-                                                 dI2 = (double)I[2], dpx = (double)g.px, dpy = (double)g.py;
-                                    double estar = energy_f64(ra, rb, sc, dm, dI0, dI1, dI2, dpx, dpy, sc.d_wb * (double)bnd_a);
-#pragma unroll
-                                    for (int u = 0; u < 4; u++) {
-                                        const int32_t k = cs[u];
-                                        if (k == INT32_MAX || (u > 0 && k == cs[u - 1])) continue;
-                                        int4 ka;
-                                        int2 kb;
-                                        load_mn(mn, k, ka, kb);
-                                        if ((int64_t)kb.y + g.m > sc.max_size) continue;
-                                        int bnd = 0;
-#pragma unroll
-                                        for (int d = 0; d < 4; d++) bnd += (nl[d] >= 0 && nl[d] != k) ? el[d] : 0;
-                                        double ek = energy_f64(ka, kb, sc, dm, dI0, dI1, dI2, dpx, dpy, sc.d_wb * (double)bnd);
-                                        if (ek < estar) {
-                                            estar = ek;
-                                            best = k;
-                                        }
-                                    }
-                                } else {
-                                    int64_t estar = block_energy(ra, rb, g, I, bnd_a, sc);
-#pragma unroll
-                                    for (int u = 0; u < 4; u++) {
-                                        const int32_t k = cs[u];
-                                        if (k == INT32_MAX || (u > 0 && k == cs[u - 1])) continue;
-                                        int4 ka;
-                                        int2 kb;
-                                        load_mn(mn, k, ka, kb);
-                                        if ((int64_t)kb.y + g.m > sc.max_size) continue;
-                                        int bnd = 0;
-#pragma unroll
-                                        for (int d = 0; d < 4; d++) bnd += (nl[d] >= 0 && nl[d] != k) ? el[d] : 0;
-                                        int64_t ek = block_energy(ka, kb, g, I, bnd, sc);
-                                        if (ek < estar) {
-                                            estar = ek;
-                                            best = k;
-                                        }
-                                    }
-                                }
-                                prop = best != a && pair_on(gv, a, best);
-                            }
-                        }
+                        propose_block<MERGE>(J, s, B, bi, nbx, nby, W, H, L, mn, s_lut, sc, gv, use_f64, &s_nreq, a, best, m,
+                                             Ipk, prop, smin, stopo);
                     }
                     n_smin += smin;
                     n_stopo += stopo;
@@ -1299,6 +1316,393 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
     }
 }
 
+// ------------------------------------------- one image on many workgroups
+// k_refine_mc: the same stage loop, class phases and counters as k_refine,
+// for a single image whose class phases hold thousands of blocks.  G
+// workgroups of one cooperative launch share the image: every pass is split
+// over all G * nt lanes, and the phases are separated by grid barriers
+// instead of workgroup barriers.  The per-superpixel state, the work lists
+// and their counters live in global memory (the control words J.ctl, zeroed
+// by the host before the launch); device-scope integer atomics keep every
+// sum exact, so the labels equal those of k_refine bit for bit.
+
+// Grid barrier over the workgroups of a cooperative launch.  The arrival
+// counter only grows (the n-th barrier waits for n * G arrivals); thread 0
+// publishes the workgroup's writes before it arrives and invalidates its
+// caches after the wait (agent-scope fences).  The wait is bounded: past
+// the spin limit, or when another workgroup gave up, it raises the abort
+// word and returns false, and the caller leaves the kernel, so that every
+// workgroup exits.
+constexpr uint32_t GRID_SPIN_LIMIT = 1u << 22;
+
+__device__ __forceinline__ bool grid_sync(uint32_t *ctl, uint32_t &target, int32_t *s_ok)
+{
+    __syncthreads();
+    target += gridDim.x;
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        __threadfence();
+        atomicAdd(&ctl[CTL_BAR], 1u);
+        uint32_t spins = 0;
+        while (__hip_atomic_load(&ctl[CTL_BAR], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(&ctl[CTL_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+                ++spins > GRID_SPIN_LIMIT) {
+                atomicExch(&ctl[CTL_ABORT], 1u);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __threadfence();
+        *s_ok = ok;
+    }
+    __syncthreads();
+    return *s_ok != 0;
+}
+
+// A word of the control block that other workgroups update, read after a
+// grid barrier (an atomic load: never served from a stale cache).
+__device__ __forceinline__ int32_t ctl_read(const uint32_t *ctl, int w)
+{
+    return (int32_t)__hip_atomic_load(&ctl[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Class-list append aggregated per workgroup and pass: slots are taken with
+// LDS atomics, then one global atomic per class reserves the workgroup's
+// range.  Every thread of the workgroup calls it once per pass.
+__device__ __forceinline__ void class_push_wg(bool e, int cls, int32_t v, int32_t *l_cnt, int32_t *l_base,
+                                              uint32_t *g_cnt, int32_t *glob, int64_t capg)
+{
+    const int slot = e ? atomicAdd(&l_cnt[cls], 1) : 0;
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        const int n = l_cnt[threadIdx.x];
+        l_base[threadIdx.x] = n ? (int32_t)atomicAdd(&g_cnt[threadIdx.x], (uint32_t)n) : 0;
+        l_cnt[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    if (e) glob[cls * capg + l_base[cls] + slot] = v;
+}
+
+#define MC_SYNC()                                  \
+    do {                                           \
+        if (!grid_sync(ctl, bar, &s_ok)) return;   \
+    } while (0)
+
+__global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs, Sched sc, int s_begin, int s_end,
+                                                    int flags, const uint32_t *__restrict__ lut_g)
+{
+    __shared__ uint32_t s_lut[8];
+    __shared__ int32_t s_ok, s_nreq;
+    __shared__ int32_t l_cnt[9], l_base[9];
+    __shared__ unsigned long long s_skip[2];
+
+    const Job &J = jobs[0];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int64_t gt = (int64_t)blockIdx.x * nt + tid, gn = (int64_t)gridDim.x * nt;
+    const int64_t wg0 = (int64_t)blockIdx.x * nt;   // first lane of this workgroup
+    const int W = J.W, H = J.H, K = J.K;
+    int64_t *const st = J.stats;
+    int32_t *const mn = J.means, *const fl = J.flow;
+    uint32_t *const ctl = J.ctl;
+    unsigned long long *const ctr = reinterpret_cast<unsigned long long *>(ctl + CTL_CTR);
+    Prop *const props = J.props;
+    const int64_t capg = J.capc;
+    uint32_t bar = 0;
+    GateView gv;
+    gv.bits = nullptr;
+    gv.tt = 0;
+
+    if (tid < 8) s_lut[tid] = lut_g[tid];
+    if (tid < 9) l_cnt[tid] = 0;
+    if (tid < 2) s_skip[tid] = 0;
+    if (tid == 0) s_nreq = 0;
+    for (int64_t i = gt; i < 2 * (int64_t)K; i += gn) fl[i] = 0;
+    if (s_end > s_begin) {
+        // visit stamps are unique per (stage, sweep) of this launch
+        const int Bf = sc.B[s_end - 1];
+        const int64_t nbf = (int64_t)((W + Bf - 1) / Bf) * ((H + Bf - 1) / Bf);
+        for (int64_t i = gt; i < nbf; i += gn) J.stamp[i] = 0;
+    }
+    if (flags & FLAG_INIT) {
+        // grid initialisation and statistics (Algorithm RAPID, first step)
+        for (int64_t i = gt; i < 6 * (int64_t)K; i += gn) st[i] = 0;
+        MC_SYNC();
+        const int B0 = sc.B[0];
+        const int nbx = (W + B0 - 1) / B0, nby = (H + B0 - 1) / B0;
+        int32_t *L = J.lab[0];
+        for (int64_t i = gt; i < (int64_t)nbx * nby; i += gn) {
+            int bx = (int)(i % nbx), by = (int)(i / nbx);
+            Geo g = block_geo(bx, by, B0, W, H);
+            int64_t row = ((2 * (int64_t)by * B0 + g.h) * J.gy) / (2 * (int64_t)H);
+            int64_t col = ((2 * (int64_t)bx * B0 + g.w) * J.gx) / (2 * (int64_t)W);
+            int32_t k = (int32_t)(row * J.gx + col);
+            L[i] = k;
+            int64_t I[3];
+            block_rgb(J, 0, B0, i, bx, by, I);
+            int64_t *r = st + 6 * (int64_t)k;
+            add64(r + 0, g.m);
+            add64(r + 1, I[0]);
+            add64(r + 2, I[1]);
+            add64(r + 3, I[2]);
+            add64(r + 4, g.px);
+            add64(r + 5, g.py);
+        }
+    }
+    MC_SYNC();
+    for (int64_t k = gt; k < K; k += gn) refresh_sp(st, mn, (int)k, sc);
+    MC_SYNC();
+
+    // Class counts are double-buffered: the sweep reads cnt[par] while the
+    // frontier rebuild fills cnt[par ^ 1]; the changed-block counter of a
+    // sweep is nchg[par].
+    int par = 0;
+    for (int s = s_begin; s < s_end; s++) {
+        const int B = sc.B[s];
+        const int nbx = (W + B - 1) / B, nby = (H + B - 1) / B;
+        const int64_t nb = (int64_t)nbx * nby;
+        int32_t *L = J.lab[s & 1];
+        const bool use_f64 = sc.f64[s] != 0;
+        int64_t *const mv = J.moved;
+        if (gt < 9) ctl[CTL_CNT + 9 * par + gt] = 0;
+        if (gt == 0) {
+            ctl[CTL_NCHG] = 0;
+            ctl[CTL_NCHG + 1] = 0;
+        }
+        MC_SYNC();
+        uint32_t *cnt = ctl + CTL_CNT + 9 * par;
+        if (s > 0) {
+            // split: each block inherits its parent's label; a child is a
+            // boundary block only on a side where its parent borders another
+            // label
+            const int Bp = sc.B[s - 1];
+            const int nbxp = (W + Bp - 1) / Bp, nbyp = (H + Bp - 1) / Bp;
+            const int64_t nbp = (int64_t)nbxp * nbyp;
+            const int32_t *Lp = J.lab[(s - 1) & 1];
+            const int r = Bp / B;
+            for (int64_t p0 = wg0; p0 < nbp; p0 += gn) {
+                const int64_t p = p0 + tid;
+                int32_t a = 0;
+                bool sw = false, se = false, sn = false, ss = false;
+                int pxb = 0, pyb = 0;
+                if (p < nbp) {
+                    pxb = (int)(p % nbxp);
+                    pyb = (int)(p / nbxp);
+                    a = Lp[p];
+                    int32_t k;
+                    k = lab_at(Lp, pxb - 1, pyb, nbxp, nbyp);
+                    sw = k >= 0 && k != a;
+                    k = lab_at(Lp, pxb + 1, pyb, nbxp, nbyp);
+                    se = k >= 0 && k != a;
+                    k = lab_at(Lp, pxb, pyb - 1, nbxp, nbyp);
+                    sn = k >= 0 && k != a;
+                    k = lab_at(Lp, pxb, pyb + 1, nbxp, nbyp);
+                    ss = k >= 0 && k != a;
+                }
+                for (int ch = 0; ch < r * r; ch++) {
+                    const int cx = pxb * r + ch % r, cy = pyb * r + ch / r;
+                    const bool valid = p < nbp && cx < nbx && cy < nby;
+                    if (valid) L[(int64_t)cy * nbx + cx] = a;
+                    const bool e = valid && ((sw && ch % r == 0) || (se && ch % r == r - 1) ||
+                                             (sn && ch / r == 0) || (ss && ch / r == r - 1));
+                    class_push_wg(e, 3 * (cy % 3) + (cx % 3), cy * nbx + cx, l_cnt, l_base, cnt, J.lists, capg);
+                }
+            }
+        } else {
+            // boundary blocks of the grid (Eq. (2))
+            for (int64_t i0 = wg0; i0 < nb; i0 += gn) {
+                const int64_t i = i0 + tid;
+                bool e = false;
+                int cls = 0;
+                if (i < nb) {
+                    const int bx = (int)(i % nbx), by = (int)(i / nbx);
+                    e = eligible(L, bx, by, nbx, nby, gv);
+                    cls = 3 * (by % 3) + (bx % 3);
+                }
+                class_push_wg(e, cls, (int32_t)i, l_cnt, l_base, cnt, J.lists, capg);
+            }
+        }
+        MC_SYNC();
+
+        int sweeps = 0, converged = 0;
+        int n_smin = 0, n_stopo = 0;
+        for (int t = 0; t < sc.max_sweeps; t++) {
+            cnt = ctl + CTL_CNT + 9 * par;
+            // the other buffers start the sweep clear (their last readers
+            // passed at least one grid barrier ago)
+            if (gt < 9) ctl[CTL_CNT + 9 * (par ^ 1) + gt] = 0;
+            if (gt == 0) {
+                int64_t tot = 0;
+                for (int c = 0; c < 9; c++) tot += ctl_read(cnt, c);
+                ctr[0] += (unsigned long long)tot;
+                ctl[CTL_NCHG + par] = 0;
+            }
+            int32_t *const nchg = reinterpret_cast<int32_t *>(ctl + CTL_NCHG + par);
+            for (int c = 0; c < 9; c++) {
+                const int ncls = ctl_read(cnt, c);   // stable during the sweep
+                if (ncls == 0) continue;
+                const int32_t *llst = J.lists + c * capg;
+                // ---- P1: propose from the class-start state
+                for (int64_t e0 = wg0; e0 < ncls; e0 += gn) {
+                    const int e = (int)(e0 + tid);
+                    bool prop = false, smin = false, stopo = false;
+                    int32_t bi = 0, a = 0, best = 0;
+                    int64_t m = 0;
+                    uint64_t Ipk = 0;
+                    if (e < ncls) {
+                        bi = llst[e];
+                        propose_block<false>(J, s, B, bi, nbx, nby, W, H, L, mn, s_lut, sc, gv, use_f64, &s_nreq, a,
+                                             best, m, Ipk, prop, smin, stopo);
+                    }
+                    n_smin += smin;
+                    n_stopo += stopo;
+                    if (prop && J.involved && s >= J.involve_stage) {
+                        J.involved[a] = 1;
+                        J.involved[best] = 1;
+                    }
+                    const int slot = wave_append(reinterpret_cast<int32_t *>(ctl + CTL_NPROP), prop);
+                    if (slot >= 0) {
+                        Prop rec;
+                        rec.bi = bi;
+                        rec.a = a;
+                        rec.k = best;
+                        rec.pad = 0;
+                        rec.I = Ipk;
+                        props[slot] = rec;
+                        atomicAdd(&fl[2 * (int64_t)a], (int32_t)m);
+                        atomicAdd(&fl[2 * (int64_t)best + 1], (int32_t)m);
+                    }
+                }
+                MC_SYNC();
+                const int np = ctl_read(ctl, CTL_NPROP);
+                if (np == 0) continue;   // uniform
+                // ---- P2: class-wide size filter, commit, statistic moves
+                // (lane 0 of a proposal: source side and label write, lane 1
+                // target side)
+                for (int64_t e0 = wg0; e0 < 2 * (int64_t)np; e0 += gn) {
+                    const int64_t q = e0 + tid;
+                    const int e = (int)(q >> 1), side = (int)(q & 1);
+                    bool com = false;
+                    int32_t bi = 0;
+                    if (e < np) {
+                        const Prop rec = props[e];
+                        bi = rec.bi;
+                        const int32_t a = rec.a, k = rec.k;
+                        com = mn_size(mn, a) - fl[2 * a] >= sc.min_size &&
+                              mn_size(mn, k) + fl[2 * k + 1] <= sc.max_size;
+                        if (com) {
+                            const int bx = bi % nbx, by = bi / nbx;
+                            const Geo g = block_geo(bx, by, B, W, H);
+                            const int64_t sg = side ? 1 : -1;
+                            int64_t *rr = st + 6 * (int64_t)(side ? k : a);
+                            add64(rr + 0, sg * g.m);
+                            add64(rr + 1, sg * (int64_t)(rec.I & 0x1FFFFFull));
+                            add64(rr + 2, sg * (int64_t)((rec.I >> 21) & 0x1FFFFFull));
+                            add64(rr + 3, sg * (int64_t)(rec.I >> 42));
+                            add64(rr + 4, sg * g.px);
+                            add64(rr + 5, sg * g.py);
+                            if (mv)
+                                atomicAdd(reinterpret_cast<unsigned long long *>(mv + (side ? k : a)),
+                                          (unsigned long long)g.m);
+                            if (side == 0) {
+                                L[bi] = k;
+                                props[e].pad = 1;
+                            }
+                        }
+                    }
+                    const int slot = wave_append(nchg, com && side == 0);
+                    if (slot >= 0) J.changed[slot] = bi;
+                }
+                MC_SYNC();
+                // ---- P3: refresh the superpixels of committed moves, clear
+                // the flow counters
+                for (int64_t q = gt; q < 2 * (int64_t)np; q += gn) {
+                    const int e = (int)(q >> 1), side = (int)(q & 1);
+                    const Prop rec = props[e];
+                    const int32_t sp = side ? rec.k : rec.a;
+                    fl[2 * sp + side] = 0;
+                    if (rec.pad) refresh_sp(st, mn, sp, sc);
+                }
+                // every lane read np before the P2 barrier: safe to reset
+                if (gt == 0) {
+                    ctr[1] += (unsigned long long)np;
+                    ctl[CTL_NPROP] = 0;
+                }
+                MC_SYNC();
+            }
+            MC_SYNC();
+            sweeps = t + 1;
+            const int commits = ctl_read(ctl, CTL_NCHG + par);
+            if (gt == 0) ctr[2] += (unsigned long long)commits;
+            if (commits == 0) {
+                converged = 1;
+                break;
+            }
+            // next boundary set: eligible blocks within one block of a
+            // change, first visits found with the global stamps
+            const int32_t stamp = s * (sc.max_sweeps + 1) + t + 1;
+            uint32_t *const ncnt = ctl + CTL_CNT + 9 * (par ^ 1);
+            for (int64_t q0 = wg0; q0 < 9 * (int64_t)commits; q0 += gn) {
+                const int64_t q = q0 + tid;
+                bool e = false;
+                int cls = 0;
+                int32_t ni = 0;
+                if (q < 9 * (int64_t)commits) {
+                    const int32_t bi = J.changed[q / 9];
+                    const int d = (int)(q % 9);
+                    const int bx = bi % nbx + (d % 3) - 1, by = bi / nbx + (d / 3) - 1;
+                    if (bx >= 0 && by >= 0 && bx < nbx && by < nby) {
+                        ni = by * nbx + bx;
+                        e = atomicExch(&J.stamp[ni], stamp) != stamp && eligible(L, bx, by, nbx, nby, gv);
+                        cls = 3 * (by % 3) + (bx % 3);
+                    }
+                }
+                class_push_wg(e, cls, ni, l_cnt, l_base, ncnt, J.lists, capg);
+            }
+            MC_SYNC();
+            par ^= 1;
+        }
+        // skip counts: one LDS sum per workgroup, one global atomic each
+        if (n_smin) atomicAdd(&s_skip[0], (unsigned long long)n_smin);
+        if (n_stopo) atomicAdd(&s_skip[1], (unsigned long long)n_stopo);
+        __syncthreads();
+        if (tid == 0) {
+            if (s_skip[0]) atomicAdd(&ctr[3], s_skip[0]);
+            if (s_skip[1]) atomicAdd(&ctr[4], s_skip[1]);
+            s_skip[0] = 0;
+            s_skip[1] = 0;
+        }
+        MC_SYNC();
+        if (gt == 0) {
+            rapid_stage_report rp;
+            rp.level = sc.level[s];
+            rp.block = B;
+            rp.sweeps = sweeps;
+            rp.converged = converged;
+            rp.active = (int64_t)ctr[0];
+            rp.proposals = (int64_t)ctr[1];
+            rp.commits = (int64_t)ctr[2];
+            rp.skip_min = (int64_t)ctr[3];
+            rp.skip_topo = (int64_t)ctr[4];
+            rp.merges = 0;
+            J.rep[s] = rp;
+            for (int i = 0; i < 6; i++) ctr[i] = 0;
+        }
+    }
+    if ((flags & FLAG_OUT) && s_end > 0) {
+        const int B = sc.B[s_end - 1];
+        const int nbx = (W + B - 1) / B;
+        const int32_t *L = J.lab[(s_end - 1) & 1];
+        if (!(B == 1 && L == J.out)) {
+            for (int64_t i = gt; i < (int64_t)W * H; i += gn) {
+                const int x = (int)(i % W), y = (int)(i / W);
+                J.out[(int64_t)y * J.out_stride + x] = L[(int64_t)(y / B) * nbx + x / B];
+            }
+        }
+    }
+}
+#undef MC_SYNC
+
 // ------------------------------------------------------------ launchers
 
 hipError_t launch_block_sums(const Job *jobs_dev, int n_jobs, int s, int B, int64_t max_nb, hipStream_t stream)
@@ -1342,6 +1746,26 @@ hipError_t launch_refine(const Job *jobs_dev, int n_jobs, const Sched &sc, const
     hipLaunchKernelGGL(fn, dim3((unsigned)n_jobs), dim3(threads), lp.total, stream, jobs_dev, sc, lp, s_begin,
                        s_end, flags, lut_dev);
     return hipGetLastError();
+}
+
+hipError_t launch_refine_mc(const Job *jobs_dev, int groups, const Sched &sc, int s_begin, int s_end, int flags,
+                            const uint32_t *lut_dev, int threads, hipStream_t stream)
+{
+    Sched sc_arg = sc;
+    void *args[] = {(void *)&jobs_dev, (void *)&sc_arg, (void *)&s_begin, (void *)&s_end, (void *)&flags,
+                    (void *)&lut_dev};
+    return hipLaunchCooperativeKernel((const void *)k_refine_mc, dim3((unsigned)groups), dim3((unsigned)threads),
+                                      args, 0, stream);
+}
+
+hipError_t max_coop_groups(int threads, int *out)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_refine_mc, threads, 0);
+    *out = e == hipSuccess ? cus * per_cu : 0;
+    return e;
 }
 
 }  // namespace rapid

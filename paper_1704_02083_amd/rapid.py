@@ -42,7 +42,8 @@ class Config(C.Structure):
 
 class Timings(C.Structure):
     _fields_ = [("block_sums_ms", C.c_float), ("refine_ms", C.c_float), ("threads", C.c_int32),
-                ("stats_lds", C.c_int32), ("pyramid", C.c_int32), ("tuned", C.c_int32)]
+                ("stats_lds", C.c_int32), ("pyramid", C.c_int32), ("tuned", C.c_int32),
+                ("workgroups", C.c_int32)]
 
 
 class Params(C.Structure):
@@ -388,7 +389,7 @@ class Context:
         _check(_lib.rapid_last_timings(self._h, C.byref(t)), "rapid_last_timings")
         return {"block_sums_ms": float(t.block_sums_ms), "refine_ms": float(t.refine_ms),
                 "threads": int(t.threads), "stats_lds": int(t.stats_lds), "pyramid": int(t.pyramid),
-                "tuned": int(t.tuned)}
+                "tuned": int(t.tuned), "workgroups": int(t.workgroups)}
 
     def state(self, rgb, params: dict) -> "State":
         return State(self, rgb, params)

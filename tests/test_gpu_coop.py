@@ -1,0 +1,211 @@
+"""One image on many workgroups: the cooperative launch shape, in which the
+class phases of a single image are split over G workgroups separated by grid
+barriers, gives the labels, statistics and stage counters of the oracle bit
+for bit, at every G, and falls back to one workgroup per image where it does
+not apply (batches, merge on underflow, gates)."""
+import contextlib
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1704_02083_amd import params, synth, synth_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@contextlib.contextmanager
+def _shape(groups):
+    """Contexts created inside use one image on `groups` workgroups of 1024
+    lanes (state in global memory, block sums in separate launches)."""
+    old = os.environ.get("RAPID_SHAPE")
+    os.environ["RAPID_SHAPE"] = "1024,0,0,%d" % groups
+    try:
+        yield
+    finally:
+        if old is None:
+            os.environ.pop("RAPID_SHAPE", None)
+        else:
+            os.environ["RAPID_SHAPE"] = old
+
+
+def _run(ctx, img, p):
+    import torch
+    rgb = torch.from_numpy(np.ascontiguousarray(img)).cuda()
+    lab, rep = ctx.segment(rgb, p)
+    torch.cuda.synchronize()
+    return lab.cpu().numpy(), rep
+
+
+CASES = [
+    # W, H, K, levels, min, seed
+    (64, 64, 4, [(1, [16, 8, 4, 2, 1])], 0, 1),
+    (97, 61, 12, [(1, [8, 4, 2, 1])], 10, 2),          # ragged edges on both axes
+    (33, 17, 2, [(1, [16, 8, 4, 2, 1])], 0, 3),         # 1-px edge column and row
+    (128, 96, 24, params.THREE_LEVEL, 64, 5),          # three levels, ratio 4
+    (64, 64, 1, [(1, [16, 8, 4, 2, 1])], 0, 7),         # one superpixel: no boundary
+    (16, 16, 1, [(1, [1])], 0, 8),                      # single stage at B = 1
+    (481, 321, 400, [(1, [16, 8, 4, 2, 1])], 0, 9),    # a batch image's shape
+]
+
+
+def test_coop_small_cases_bit_exact(gpu_lib):
+    refs = []
+    imgs = []
+    for (W, H, K, levels, mn, seed) in CASES:
+        img = synth.voronoi_blur(W, H, regions=max(3, K // 2), seed=seed)
+        p = params.default_params(W, H, K, levels=levels, min_size=mn)
+        ref, _, ref_rep = oracle.segment(img, p)
+        imgs.append((img, p))
+        refs.append((ref, ref_rep))
+    for g in (2, 8, 64, 256):
+        with _shape(g):
+            c = gpu_lib.Context(0, timing=True)
+        try:
+            for (W, H, K, _, _, seed), (img, p), (ref, ref_rep) in zip(CASES, imgs, refs):
+                _say("case: coop G=%d %dx%d K=%d seed=%d" % (g, W, H, K, seed))
+                got, rep = _run(c, img, p)
+                assert c.last_timings()["workgroups"] == g
+                mism = int((got != ref).sum())
+                assert mism == 0, "G=%d %dx%d: %d labels differ" % (g, W, H, mism)
+                assert rep == ref_rep, "G=%d %dx%d: stage counters differ" % (g, W, H)
+        finally:
+            c.close()
+
+
+def test_coop_config1_and_he_bit_exact(gpu_lib):
+    """The 256^2 image with K = 64, and a 1024 x 768 H&E tile with three
+    levels and K = 768, on 8, 64 and 256 workgroups."""
+    cases = [(synth.voronoi_blur(), params.config1())]
+    he = synth.he_tile(1024, 768, seed=31)
+    cases.append((he, params.default_params(1024, 768, 768, levels=params.THREE_LEVEL)))
+    refs = [oracle.segment(img, p) for img, p in cases]
+    for g in (8, 64, 256):
+        with _shape(g):
+            c = gpu_lib.Context(0)
+        try:
+            for i, ((img, p), (ref, _, ref_rep)) in enumerate(zip(cases, refs)):
+                _say("case: coop G=%d image %d" % (g, i))
+                got, rep = _run(c, img, p)
+                assert (got == ref).all() and rep == ref_rep, (g, i)
+        finally:
+            c.close()
+
+
+def test_coop_he4096_three_levels_bit_exact(gpu_lib):
+    """The 4096^2 H&E tile with K = 16384 and three levels on 64 and 256
+    workgroups equals the oracle."""
+    import torch
+    rgb = synth_gpu.he_slide(4096, 4096, seed=3, background=0.3, device="cuda")
+    p = params.config3()
+    ref, _, ref_rep = oracle.segment(rgb.cpu().numpy(), p)
+    for g in (64, 256):
+        with _shape(g):
+            c = gpu_lib.Context(0, timing=True)
+        try:
+            _say("case: coop G=%d 4096^2 K=16384" % g)
+            lab, rep = c.segment(rgb, p)
+            torch.cuda.synchronize()
+            assert c.last_timings()["workgroups"] == g
+            mism = int((lab.cpu().numpy() != ref).sum())
+            assert mism == 0, "G=%d: %d labels differ" % (g, mism)
+            assert rep == ref_rep
+        finally:
+            c.close()
+
+
+def test_coop_level_by_level_state(gpu_lib):
+    """rapid_state_create and rapid_refine_level per level on 64 workgroups:
+    labels, statistics and counters equal the one-workgroup state path, and
+    the involvement and moved-pixel tracking match too."""
+    import torch
+    img = synth.he_tile(512, 384, seed=41)
+    p = params.default_params(512, 384, 192, levels=params.THREE_LEVEL)
+    rgb = torch.from_numpy(img).cuda()
+    out = []
+    for g in (1, 64):
+        with _shape(g):
+            c = gpu_lib.Context(0)
+        try:
+            _say("case: level by level, G=%d" % g)
+            st = c.state(rgb, p)
+            K = st.K
+            inv = torch.zeros(K, dtype=torch.uint8, device="cuda")
+            mv = torch.zeros(K, dtype=torch.int64, device="cuda")
+            st.track(involved=inv, moved=mv)
+            reps = st.refine_level(0) + st.refine_level(1) + st.refine_level(2)
+            lab, stats = st.export()
+            torch.cuda.synchronize()
+            out.append((lab.cpu().numpy(), stats.cpu().numpy(), reps, inv.cpu().numpy(), mv.cpu().numpy()))
+            st.close()
+        finally:
+            c.close()
+    (l1, s1, r1, i1, m1), (l2, s2, r2, i2, m2) = out
+    assert (l1 == l2).all() and (s1 == s2).all() and r1 == r2
+    assert (i1 == i2).all() and (m1 == m2).all()
+    ref, ref_stats, ref_rep = oracle.segment(img, p)
+    assert (l2 == ref).all() and r2 == ref_rep
+
+
+def test_coop_shape_falls_back_where_it_does_not_apply(gpu_lib):
+    """Merge on underflow and batches run one workgroup per image even when
+    the cooperative shape is asked for, with the oracle's labels."""
+    import torch
+    img = synth.voronoi_blur(160, 120, regions=20, seed=51)
+    p = params.default_params(160, 120, 40, min_size=120)
+    p["merge"] = 1
+    ref, _, ref_rep = oracle.segment(img, p)
+    with _shape(64):
+        c = gpu_lib.Context(0, timing=True)
+    try:
+        _say("case: coop asked, merge on")
+        got, rep = _run(c, img, p)
+        assert c.last_timings()["workgroups"] == 1
+        assert (got == ref).all() and rep == ref_rep
+        _say("case: coop asked, batch of 3")
+        imgs = [synth.voronoi_blur(96, 80, regions=10, seed=60 + i) for i in range(3)]
+        pb = params.default_params(96, 80, 12)
+        labs, reps = c.segment_batch([torch.from_numpy(im).cuda() for im in imgs], pb)
+        torch.cuda.synchronize()
+        assert c.last_timings()["workgroups"] == 1
+        for im, lab, rp in zip(imgs, labs, reps):
+            r, _, rr = oracle.segment(im, pb)
+            assert (lab.cpu().numpy() == r).all() and rp == rr
+    finally:
+        c.close()
+
+
+def test_coop_autotune_single_image(gpu_lib, tmp_path):
+    """The autotuner times the cooperative shapes beside the one-workgroup
+    shapes for a single plain image; whatever it picks gives the oracle's
+    labels, and the choice (with its workgroup count) survives the cache."""
+    import torch
+    img = synth.he_tile(1024, 1024, seed=61)
+    p = params.default_params(1024, 1024, 1024, levels=params.THREE_LEVEL)
+    ref, _, ref_rep = oracle.segment(img, p)
+    rgb = torch.from_numpy(img).cuda()
+    cache = str(tmp_path / "tune.json")
+    _say("case: autotune single 1024^2 image")
+    c = gpu_lib.Context(0, timing=True, autotune=True, autotune_cache=cache)
+    try:
+        lab, rep = c.segment(rgb, p)
+        torch.cuda.synchronize()
+        t1 = c.last_timings()
+        assert t1["tuned"] == 1 and t1["workgroups"] >= 1
+        assert (lab.cpu().numpy() == ref).all() and rep == ref_rep
+    finally:
+        c.close()
+    c = gpu_lib.Context(0, timing=True, autotune=True, autotune_cache=cache)
+    try:
+        lab, rep = c.segment(rgb, p)
+        torch.cuda.synchronize()
+        t2 = c.last_timings()
+        assert t2["tuned"] == 0 and t2["workgroups"] == t1["workgroups"]
+        assert (lab.cpu().numpy() == ref).all()
+    finally:
+        c.close()
