@@ -73,8 +73,9 @@ typedef struct {
      * the means records and flow counters, only the means records, or
      * nothing in LDS (as far as they fit); block-sum pyramid inside the
      * launch or in separate launches; and, for a single image without gate
-     * or merge, the image spread over 8 .. 256 workgroups of a cooperative
-     * launch -- and keeps the fastest; later calls of that
+     * or merge, the image spread over 8 .. 128 workgroups of a cooperative
+     * launch, with small sweeps on the whole grid or on one workgroup --
+     * and keeps the fastest; later calls of that
      * shape use it.  Every candidate computes the same labels (the result
      * never depends on the shape), so tuning costs time only.  Only calls
      * that start from the image tune (not rapid_refine_level).
@@ -190,11 +191,12 @@ typedef struct {
 /* Create a context on cfg->device: builds the 256-entry simple-point table
  * of the topology term (Eq. (1), E_topo) and uploads it.  *out receives the
  * context; rapid_destroy releases it.  Environment: RAPID_THREADS=n (64 ..
- * 1024, a multiple of 64) fixes the workgroup size; RAPID_SHAPE=t,l,p[,g]
+ * 1024, a multiple of 64) fixes the workgroup size; RAPID_SHAPE=t,l,p[,g[,s]]
  * fixes the whole launch shape (workgroup size, residency l as in
- * rapid_timings.stats_lds when it fits, pyramid inside the launch, and g
+ * rapid_timings.stats_lds when it fits, pyramid inside the launch, g
  * workgroups per image where a single plain image may spread over a
- * cooperative launch) and bypasses the autotuner. */
+ * cooperative launch, whose sweeps with at most s active blocks run on one
+ * workgroup) and bypasses the autotuner. */
 rapid_status rapid_init(const rapid_config *cfg, rapid_ctx **out);
 void rapid_destroy(rapid_ctx *ctx);   /* NULL-safe; waits for queued work */
 

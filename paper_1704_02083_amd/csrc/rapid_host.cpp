@@ -26,6 +26,8 @@ struct LaunchShape {
     int pyramid = 1;
     int groups = 1;    // workgroups per job: > 1 spreads a single image over
                        // a cooperative launch (state global, pyramid apart)
+    int solo = -1;     // cooperative launch: sweeps with at most this many
+                       // active blocks run on one workgroup (-1: never)
     float ms = 0.0f;   // autotuner: time of the choice
 };
 
@@ -453,7 +455,7 @@ std::string shape_key(const std::vector<Job> &jobs, const Sched &sc, int s_begin
 
 // Cache file: one JSON object, one entry per line:
 //   {"rapid_autotune": 1, "arch": "<gcnArchName>", "entries": {
-//   "<key>": [threads, stats_lds, pyramid, groups, ms],
+//   "<key>": [threads, stats_lds, pyramid, groups, solo, ms],
 //   ...
 //   }}
 void cache_load(rapid_ctx *ctx)
@@ -473,11 +475,13 @@ void cache_load(rapid_ctx *ctx)
         if (!arch_ok) break;
         char key[1024];
         LaunchShape sh;
-        // entries without the groups field (one workgroup per job) are read too
-        const int got = std::sscanf(line, " \"%1023[^\"]\": [%d, %d, %d, %d, %f]", key, &sh.threads, &sh.stats_lds,
-                                    &sh.pyramid, &sh.groups, &sh.ms);
-        if (got != 6) {
+        // entries without the cooperative fields (one workgroup per job) are
+        // read too
+        const int got = std::sscanf(line, " \"%1023[^\"]\": [%d, %d, %d, %d, %d, %f]", key, &sh.threads,
+                                    &sh.stats_lds, &sh.pyramid, &sh.groups, &sh.solo, &sh.ms);
+        if (got != 7) {
             sh.groups = 1;
+            sh.solo = -1;
             if (std::sscanf(line, " \"%1023[^\"]\": [%d, %d, %d, %f]", key, &sh.threads, &sh.stats_lds, &sh.pyramid,
                             &sh.ms) != 5)
                 continue;
@@ -497,8 +501,9 @@ void cache_save(const rapid_ctx *ctx)
     std::fprintf(f, "{\"rapid_autotune\": 1, \"arch\": \"%s\", \"entries\": {\n", ctx->arch.c_str());
     size_t i = 0;
     for (const auto &e : ctx->tuned)
-        std::fprintf(f, "\"%s\": [%d, %d, %d, %d, %.4f]%s\n", e.first.c_str(), e.second.threads, e.second.stats_lds,
-                     e.second.pyramid, e.second.groups, e.second.ms, ++i < ctx->tuned.size() ? "," : "");
+        std::fprintf(f, "\"%s\": [%d, %d, %d, %d, %d, %.4f]%s\n", e.first.c_str(), e.second.threads,
+                     e.second.stats_lds, e.second.pyramid, e.second.groups, e.second.solo, e.second.ms,
+                     ++i < ctx->tuned.size() ? "," : "");
     std::fprintf(f, "}}\n");
     std::fclose(f);
     std::rename(tmp.c_str(), ctx->cache_path.c_str());
@@ -538,7 +543,7 @@ rapid_status launch_shape(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sc
         HIPCHK(hipMemsetAsync(jobs[0].ctl, 0, 4 * (size_t)CTL_WORDS, ctx->stream));
         if (e1) HIPCHK(hipEventRecord(e1, ctx->stream));
         HIPCHK(launch_refine_mc(ctx->jobs_dev, sh.groups, sc, s_begin, s_end, flags, ctx->lut_dev, sh.threads,
-                                ctx->stream));
+                                sh.solo, ctx->stream));
         if (e2) HIPCHK(hipEventRecord(e2, ctx->stream));
         return RAPID_OK;
     }
@@ -626,28 +631,33 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
                 }
             }
         }
-        // one image on 8 .. 256 workgroups of 1024 lanes
+        // one image on 8 .. 128 workgroups of 1024 lanes (more pay more for
+        // each grid barrier than they gain), small sweeps on the whole grid
+        // or on one workgroup
+        const int solo_all[3] = {-1, 4096, 16384};
         if (!ctx->threads_forced || ctx->threads == 1024)
-            for (int g = 8; g <= std::min(coop_max, 256); g *= 2) {
-                LaunchShape c;
-                c.threads = 1024;
-                c.stats_lds = 0;
-                c.pyramid = 0;
-                c.groups = g;
-                rapid_status r = launch_shape(ctx, jobs, sc, s_begin, s_end, flags, Kmax, nbF_max, gated, c,
-                                              ctx->tev[0], nullptr, ctx->tev[1]);
-                if (r) return r;
-                HIPCHK(hipEventSynchronize(ctx->tev[1]));
-                HIPCHK(hipEventElapsedTime(&c.ms, ctx->tev[0], ctx->tev[1]));
-                if (best.ms < 0.0f || c.ms < best.ms) best = c;
-            }
+            for (int g = 8; g <= std::min(coop_max, 128); g *= 2)
+                for (int so = 0; so < 3; so++) {
+                    LaunchShape c;
+                    c.threads = 1024;
+                    c.stats_lds = 0;
+                    c.pyramid = 0;
+                    c.groups = g;
+                    c.solo = solo_all[so];
+                    rapid_status r = launch_shape(ctx, jobs, sc, s_begin, s_end, flags, Kmax, nbF_max, gated, c,
+                                                  ctx->tev[0], nullptr, ctx->tev[1]);
+                    if (r) return r;
+                    HIPCHK(hipEventSynchronize(ctx->tev[1]));
+                    HIPCHK(hipEventElapsedTime(&c.ms, ctx->tev[0], ctx->tev[1]));
+                    if (best.ms < 0.0f || c.ms < best.ms) best = c;
+                }
         sh = best;
         ctx->tuned[key] = best;
         ctx->last_tuned = 1;
         cache_save(ctx);
         if (ctx->verbose)
-            std::fprintf(stderr, "rapid: tuned %s -> threads %d stats_lds %d pyramid %d groups %d (%.3f ms)\n",
-                         key.c_str(), best.threads, best.stats_lds, best.pyramid, best.groups, best.ms);
+            std::fprintf(stderr, "rapid: tuned %s -> threads %d stats_lds %d pyramid %d groups %d solo %d (%.3f ms)\n",
+                         key.c_str(), best.threads, best.stats_lds, best.pyramid, best.groups, best.solo, best.ms);
     }
     if (sh.groups > 1) {
         // the cooperative shape where this call allows it (state global,
@@ -768,9 +778,9 @@ rapid_status rapid_init(const rapid_config *cfg, rapid_ctx **out)
     }
     if (const char *t = std::getenv("RAPID_SHAPE")) {
         LaunchShape f;
-        const int got = std::sscanf(t, "%d,%d,%d,%d", &f.threads, &f.stats_lds, &f.pyramid, &f.groups);
-        if ((got == 3 || got == 4) && f.threads >= 64 && f.threads <= 1024 && f.threads % 64 == 0 &&
-            f.groups >= 1 && f.groups <= 4096) {
+        const int got = std::sscanf(t, "%d,%d,%d,%d,%d", &f.threads, &f.stats_lds, &f.pyramid, &f.groups, &f.solo);
+        if (got >= 3 && f.threads >= 64 && f.threads <= 1024 && f.threads % 64 == 0 && f.groups >= 1 &&
+            f.groups <= 4096) {
             ctx->forced = f;
             ctx->shape_forced = true;
         }

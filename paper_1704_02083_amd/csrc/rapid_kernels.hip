@@ -1390,7 +1390,7 @@ __device__ __forceinline__ void class_push_wg(bool e, int cls, int32_t v, int32_
     } while (0)
 
 __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs, Sched sc, int s_begin, int s_end,
-                                                    int flags, const uint32_t *__restrict__ lut_g)
+                                                    int flags, const uint32_t *__restrict__ lut_g, int64_t solo_max)
 {
     __shared__ uint32_t s_lut[8];
     __shared__ int32_t s_ok, s_nreq;
@@ -1528,138 +1528,154 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
         int n_smin = 0, n_stopo = 0;
         for (int t = 0; t < sc.max_sweeps; t++) {
             cnt = ctl + CTL_CNT + 9 * par;
+            int64_t tot = 0;
+            for (int c = 0; c < 9; c++) tot += ctl_read(cnt, c);
+            // A sweep with few active blocks runs on workgroup 0 alone, with
+            // workgroup barriers; the other workgroups wait at its end.
+            const bool solo = tot <= solo_max;
+            const int64_t first = solo ? 0 : wg0, step = solo ? (int64_t)nt : gn;
+#define SW_SYNC()              \
+    do {                       \
+        if (solo)              \
+            __syncthreads();   \
+        else                   \
+            MC_SYNC();         \
+    } while (0)
             // the other buffers start the sweep clear (their last readers
             // passed at least one grid barrier ago)
             if (gt < 9) ctl[CTL_CNT + 9 * (par ^ 1) + gt] = 0;
             if (gt == 0) {
-                int64_t tot = 0;
-                for (int c = 0; c < 9; c++) tot += ctl_read(cnt, c);
                 ctr[0] += (unsigned long long)tot;
                 ctl[CTL_NCHG + par] = 0;
             }
             int32_t *const nchg = reinterpret_cast<int32_t *>(ctl + CTL_NCHG + par);
-            for (int c = 0; c < 9; c++) {
-                const int ncls = ctl_read(cnt, c);   // stable during the sweep
-                if (ncls == 0) continue;
-                const int32_t *llst = J.lists + c * capg;
-                // ---- P1: propose from the class-start state
-                for (int64_t e0 = wg0; e0 < ncls; e0 += gn) {
-                    const int e = (int)(e0 + tid);
-                    bool prop = false, smin = false, stopo = false;
-                    int32_t bi = 0, a = 0, best = 0;
-                    int64_t m = 0;
-                    uint64_t Ipk = 0;
-                    if (e < ncls) {
-                        bi = llst[e];
-                        propose_block<false>(J, s, B, bi, nbx, nby, W, H, L, mn, s_lut, sc, gv, use_f64, &s_nreq, a,
-                                             best, m, Ipk, prop, smin, stopo);
-                    }
-                    n_smin += smin;
-                    n_stopo += stopo;
-                    if (prop && J.involved && s >= J.involve_stage) {
-                        J.involved[a] = 1;
-                        J.involved[best] = 1;
-                    }
-                    const int slot = wave_append(reinterpret_cast<int32_t *>(ctl + CTL_NPROP), prop);
-                    if (slot >= 0) {
-                        Prop rec;
-                        rec.bi = bi;
-                        rec.a = a;
-                        rec.k = best;
-                        rec.pad = 0;
-                        rec.I = Ipk;
-                        props[slot] = rec;
-                        atomicAdd(&fl[2 * (int64_t)a], (int32_t)m);
-                        atomicAdd(&fl[2 * (int64_t)best + 1], (int32_t)m);
-                    }
-                }
-                MC_SYNC();
-                const int np = ctl_read(ctl, CTL_NPROP);
-                if (np == 0) continue;   // uniform
-                // ---- P2: class-wide size filter, commit, statistic moves
-                // (lane 0 of a proposal: source side and label write, lane 1
-                // target side)
-                for (int64_t e0 = wg0; e0 < 2 * (int64_t)np; e0 += gn) {
-                    const int64_t q = e0 + tid;
-                    const int e = (int)(q >> 1), side = (int)(q & 1);
-                    bool com = false;
-                    int32_t bi = 0;
-                    if (e < np) {
-                        const Prop rec = props[e];
-                        bi = rec.bi;
-                        const int32_t a = rec.a, k = rec.k;
-                        com = mn_size(mn, a) - fl[2 * a] >= sc.min_size &&
-                              mn_size(mn, k) + fl[2 * k + 1] <= sc.max_size;
-                        if (com) {
-                            const int bx = bi % nbx, by = bi / nbx;
-                            const Geo g = block_geo(bx, by, B, W, H);
-                            const int64_t sg = side ? 1 : -1;
-                            int64_t *rr = st + 6 * (int64_t)(side ? k : a);
-                            add64(rr + 0, sg * g.m);
-                            add64(rr + 1, sg * (int64_t)(rec.I & 0x1FFFFFull));
-                            add64(rr + 2, sg * (int64_t)((rec.I >> 21) & 0x1FFFFFull));
-                            add64(rr + 3, sg * (int64_t)(rec.I >> 42));
-                            add64(rr + 4, sg * g.px);
-                            add64(rr + 5, sg * g.py);
-                            if (mv)
-                                atomicAdd(reinterpret_cast<unsigned long long *>(mv + (side ? k : a)),
-                                          (unsigned long long)g.m);
-                            if (side == 0) {
-                                L[bi] = k;
-                                props[e].pad = 1;
-                            }
+            if (!solo || blockIdx.x == 0) {
+                for (int c = 0; c < 9; c++) {
+                    const int ncls = ctl_read(cnt, c);   // stable during the sweep
+                    if (ncls == 0) continue;
+                    const int32_t *llst = J.lists + c * capg;
+                    // ---- P1: propose from the class-start state
+                    for (int64_t e0 = first; e0 < ncls; e0 += step) {
+                        const int e = (int)(e0 + tid);
+                        bool prop = false, smin = false, stopo = false;
+                        int32_t bi = 0, a = 0, best = 0;
+                        int64_t m = 0;
+                        uint64_t Ipk = 0;
+                        if (e < ncls) {
+                            bi = llst[e];
+                            propose_block<false>(J, s, B, bi, nbx, nby, W, H, L, mn, s_lut, sc, gv, use_f64, &s_nreq,
+                                                 a, best, m, Ipk, prop, smin, stopo);
+                        }
+                        n_smin += smin;
+                        n_stopo += stopo;
+                        if (prop && J.involved && s >= J.involve_stage) {
+                            J.involved[a] = 1;
+                            J.involved[best] = 1;
+                        }
+                        const int slot = wave_append(reinterpret_cast<int32_t *>(ctl + CTL_NPROP), prop);
+                        if (slot >= 0) {
+                            Prop rec;
+                            rec.bi = bi;
+                            rec.a = a;
+                            rec.k = best;
+                            rec.pad = 0;
+                            rec.I = Ipk;
+                            props[slot] = rec;
+                            atomicAdd(&fl[2 * (int64_t)a], (int32_t)m);
+                            atomicAdd(&fl[2 * (int64_t)best + 1], (int32_t)m);
                         }
                     }
-                    const int slot = wave_append(nchg, com && side == 0);
-                    if (slot >= 0) J.changed[slot] = bi;
+                    SW_SYNC();
+                    const int np = ctl_read(ctl, CTL_NPROP);
+                    if (np == 0) continue;   // uniform
+                    // ---- P2: class-wide size filter, commit, statistic
+                    // moves (lane 0 of a proposal: source side and label
+                    // write, lane 1 target side)
+                    for (int64_t e0 = first; e0 < 2 * (int64_t)np; e0 += step) {
+                        const int64_t q = e0 + tid;
+                        const int e = (int)(q >> 1), side = (int)(q & 1);
+                        bool com = false;
+                        int32_t bi = 0;
+                        if (e < np) {
+                            const Prop rec = props[e];
+                            bi = rec.bi;
+                            const int32_t a = rec.a, k = rec.k;
+                            com = mn_size(mn, a) - fl[2 * a] >= sc.min_size &&
+                                  mn_size(mn, k) + fl[2 * k + 1] <= sc.max_size;
+                            if (com) {
+                                const int bx = bi % nbx, by = bi / nbx;
+                                const Geo g = block_geo(bx, by, B, W, H);
+                                const int64_t sg = side ? 1 : -1;
+                                int64_t *rr = st + 6 * (int64_t)(side ? k : a);
+                                add64(rr + 0, sg * g.m);
+                                add64(rr + 1, sg * (int64_t)(rec.I & 0x1FFFFFull));
+                                add64(rr + 2, sg * (int64_t)((rec.I >> 21) & 0x1FFFFFull));
+                                add64(rr + 3, sg * (int64_t)(rec.I >> 42));
+                                add64(rr + 4, sg * g.px);
+                                add64(rr + 5, sg * g.py);
+                                if (mv)
+                                    atomicAdd(reinterpret_cast<unsigned long long *>(mv + (side ? k : a)),
+                                              (unsigned long long)g.m);
+                                if (side == 0) {
+                                    L[bi] = k;
+                                    props[e].pad = 1;
+                                }
+                            }
+                        }
+                        const int slot = wave_append(nchg, com && side == 0);
+                        if (slot >= 0) J.changed[slot] = bi;
+                    }
+                    SW_SYNC();
+                    // ---- P3: refresh the superpixels of committed moves,
+                    // clear the flow counters
+                    for (int64_t q = first + tid; q < 2 * (int64_t)np; q += step) {
+                        const int e = (int)(q >> 1), side = (int)(q & 1);
+                        const Prop rec = props[e];
+                        const int32_t sp = side ? rec.k : rec.a;
+                        fl[2 * sp + side] = 0;
+                        if (rec.pad) refresh_sp(st, mn, sp, sc);
+                    }
+                    // every lane read np before the P2 barrier: safe to reset
+                    if (gt == 0) {
+                        ctr[1] += (unsigned long long)np;
+                        ctl[CTL_NPROP] = 0;
+                    }
+                    SW_SYNC();
                 }
-                MC_SYNC();
-                // ---- P3: refresh the superpixels of committed moves, clear
-                // the flow counters
-                for (int64_t q = gt; q < 2 * (int64_t)np; q += gn) {
-                    const int e = (int)(q >> 1), side = (int)(q & 1);
-                    const Prop rec = props[e];
-                    const int32_t sp = side ? rec.k : rec.a;
-                    fl[2 * sp + side] = 0;
-                    if (rec.pad) refresh_sp(st, mn, sp, sc);
+                SW_SYNC();
+                const int commits = ctl_read(ctl, CTL_NCHG + par);
+                if (gt == 0) ctr[2] += (unsigned long long)commits;
+                if (commits > 0) {
+                    // next boundary set: eligible blocks within one block of
+                    // a change, first visits found with the global stamps
+                    const int32_t stamp = s * (sc.max_sweeps + 1) + t + 1;
+                    uint32_t *const ncnt = ctl + CTL_CNT + 9 * (par ^ 1);
+                    for (int64_t q0 = first; q0 < 9 * (int64_t)commits; q0 += step) {
+                        const int64_t q = q0 + tid;
+                        bool e = false;
+                        int cls = 0;
+                        int32_t ni = 0;
+                        if (q < 9 * (int64_t)commits) {
+                            const int32_t bi = J.changed[q / 9];
+                            const int d = (int)(q % 9);
+                            const int bx = bi % nbx + (d % 3) - 1, by = bi / nbx + (d / 3) - 1;
+                            if (bx >= 0 && by >= 0 && bx < nbx && by < nby) {
+                                ni = by * nbx + bx;
+                                e = atomicExch(&J.stamp[ni], stamp) != stamp && eligible(L, bx, by, nbx, nby, gv);
+                                cls = 3 * (by % 3) + (bx % 3);
+                            }
+                        }
+                        class_push_wg(e, cls, ni, l_cnt, l_base, ncnt, J.lists, capg);
+                    }
                 }
-                // every lane read np before the P2 barrier: safe to reset
-                if (gt == 0) {
-                    ctr[1] += (unsigned long long)np;
-                    ctl[CTL_NPROP] = 0;
-                }
-                MC_SYNC();
             }
+#undef SW_SYNC
             MC_SYNC();
             sweeps = t + 1;
-            const int commits = ctl_read(ctl, CTL_NCHG + par);
-            if (gt == 0) ctr[2] += (unsigned long long)commits;
-            if (commits == 0) {
+            if (ctl_read(ctl, CTL_NCHG + par) == 0) {
                 converged = 1;
                 break;
             }
-            // next boundary set: eligible blocks within one block of a
-            // change, first visits found with the global stamps
-            const int32_t stamp = s * (sc.max_sweeps + 1) + t + 1;
-            uint32_t *const ncnt = ctl + CTL_CNT + 9 * (par ^ 1);
-            for (int64_t q0 = wg0; q0 < 9 * (int64_t)commits; q0 += gn) {
-                const int64_t q = q0 + tid;
-                bool e = false;
-                int cls = 0;
-                int32_t ni = 0;
-                if (q < 9 * (int64_t)commits) {
-                    const int32_t bi = J.changed[q / 9];
-                    const int d = (int)(q % 9);
-                    const int bx = bi % nbx + (d % 3) - 1, by = bi / nbx + (d / 3) - 1;
-                    if (bx >= 0 && by >= 0 && bx < nbx && by < nby) {
-                        ni = by * nbx + bx;
-                        e = atomicExch(&J.stamp[ni], stamp) != stamp && eligible(L, bx, by, nbx, nby, gv);
-                        cls = 3 * (by % 3) + (bx % 3);
-                    }
-                }
-                class_push_wg(e, cls, ni, l_cnt, l_base, ncnt, J.lists, capg);
-            }
-            MC_SYNC();
             par ^= 1;
         }
         // skip counts: one LDS sum per workgroup, one global atomic each
@@ -1749,11 +1765,11 @@ hipError_t launch_refine(const Job *jobs_dev, int n_jobs, const Sched &sc, const
 }
 
 hipError_t launch_refine_mc(const Job *jobs_dev, int groups, const Sched &sc, int s_begin, int s_end, int flags,
-                            const uint32_t *lut_dev, int threads, hipStream_t stream)
+                            const uint32_t *lut_dev, int threads, int64_t solo_max, hipStream_t stream)
 {
     Sched sc_arg = sc;
     void *args[] = {(void *)&jobs_dev, (void *)&sc_arg, (void *)&s_begin, (void *)&s_end, (void *)&flags,
-                    (void *)&lut_dev};
+                    (void *)&lut_dev, (void *)&solo_max};
     return hipLaunchCooperativeKernel((const void *)k_refine_mc, dim3((unsigned)groups), dim3((unsigned)threads),
                                       args, 0, stream);
 }

@@ -1,8 +1,9 @@
 """One image on many workgroups: the cooperative launch shape, in which the
 class phases of a single image are split over G workgroups separated by grid
-barriers, gives the labels, statistics and stage counters of the oracle bit
-for bit, at every G, and falls back to one workgroup per image where it does
-not apply (batches, merge on underflow, gates)."""
+barriers (and sweeps with at most S active blocks run on one workgroup),
+gives the labels, statistics and stage counters of the oracle bit for bit,
+at every G and S, and falls back to one workgroup per image where it does not
+apply (batches, merge on underflow, gates)."""
 import contextlib
 import os
 
@@ -20,11 +21,12 @@ def _say(*a):
 
 
 @contextlib.contextmanager
-def _shape(groups):
+def _shape(groups, solo=-1):
     """Contexts created inside use one image on `groups` workgroups of 1024
-    lanes (state in global memory, block sums in separate launches)."""
+    lanes (state in global memory, block sums in separate launches), sweeps
+    with at most `solo` active blocks on one workgroup."""
     old = os.environ.get("RAPID_SHAPE")
-    os.environ["RAPID_SHAPE"] = "1024,0,0,%d" % groups
+    os.environ["RAPID_SHAPE"] = "1024,0,0,%d,%d" % (groups, solo)
     try:
         yield
     finally:
@@ -63,12 +65,13 @@ def test_coop_small_cases_bit_exact(gpu_lib):
         ref, _, ref_rep = oracle.segment(img, p)
         imgs.append((img, p))
         refs.append((ref, ref_rep))
-    for g in (2, 8, 64, 256):
-        with _shape(g):
+    # S = 2^30: every sweep on one workgroup; 4096: the small ones
+    for g, so in ((2, -1), (8, -1), (64, -1), (256, -1), (64, 4096), (8, 1 << 30)):
+        with _shape(g, so):
             c = gpu_lib.Context(0, timing=True)
         try:
             for (W, H, K, _, _, seed), (img, p), (ref, ref_rep) in zip(CASES, imgs, refs):
-                _say("case: coop G=%d %dx%d K=%d seed=%d" % (g, W, H, K, seed))
+                _say("case: coop G=%d S=%d %dx%d K=%d seed=%d" % (g, so, W, H, K, seed))
                 got, rep = _run(c, img, p)
                 assert c.last_timings()["workgroups"] == g
                 mism = int((got != ref).sum())
@@ -99,16 +102,17 @@ def test_coop_config1_and_he_bit_exact(gpu_lib):
 
 def test_coop_he4096_three_levels_bit_exact(gpu_lib):
     """The 4096^2 H&E tile with K = 16384 and three levels on 64 and 256
-    workgroups equals the oracle."""
+    workgroups, and on 32 with sweeps of at most 16384 active blocks on one
+    workgroup, equals the oracle."""
     import torch
     rgb = synth_gpu.he_slide(4096, 4096, seed=3, background=0.3, device="cuda")
     p = params.config3()
     ref, _, ref_rep = oracle.segment(rgb.cpu().numpy(), p)
-    for g in (64, 256):
-        with _shape(g):
+    for g, so in ((64, -1), (256, -1), (32, 16384)):
+        with _shape(g, so):
             c = gpu_lib.Context(0, timing=True)
         try:
-            _say("case: coop G=%d 4096^2 K=16384" % g)
+            _say("case: coop G=%d S=%d 4096^2 K=16384" % (g, so))
             lab, rep = c.segment(rgb, p)
             torch.cuda.synchronize()
             assert c.last_timings()["workgroups"] == g
@@ -129,7 +133,7 @@ def test_coop_level_by_level_state(gpu_lib):
     rgb = torch.from_numpy(img).cuda()
     out = []
     for g in (1, 64):
-        with _shape(g):
+        with _shape(g, 8192):
             c = gpu_lib.Context(0)
         try:
             _say("case: level by level, G=%d" % g)
