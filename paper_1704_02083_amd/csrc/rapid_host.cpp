@@ -543,7 +543,7 @@ rapid_status launch_shape(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sc
         HIPCHK(hipMemsetAsync(jobs[0].ctl, 0, 4 * (size_t)CTL_WORDS, ctx->stream));
         if (e1) HIPCHK(hipEventRecord(e1, ctx->stream));
         HIPCHK(launch_refine_mc(ctx->jobs_dev, sh.groups, sc, s_begin, s_end, flags, ctx->lut_dev, sh.threads,
-                                sh.solo, ctx->stream));
+                                sh.solo, lp.gate_words, ctx->stream));
         if (e2) HIPCHK(hipEventRecord(e2, ctx->stream));
         return RAPID_OK;
     }
@@ -554,8 +554,10 @@ rapid_status launch_shape(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sc
     return RAPID_OK;
 }
 
+// follow: when the shape of an earlier launch spread the image over many
+// workgroups, this launch does too (where it may)
 rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched &sc, int s_begin,
-                      int s_end, int flags, int32_t Kmax, int64_t nbF_max)
+                      int s_end, int flags, int32_t Kmax, int64_t nbF_max, const LaunchShape *follow = nullptr)
 {
     size_t n = jobs.size();
     if (n > ctx->jobs_cap) {
@@ -586,10 +588,10 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
 
     // launch shape: the tuned one for this problem shape, else the default
     // (enough jobs to fill the chip: the pyramid inside the launch)
-    // a single plain image may spread over the workgroups of a cooperative
-    // launch (no gate, no merge, not a slide tile)
+    // a single image may spread over the workgroups of a cooperative launch
+    // (no merge, not a slide tile, no gate evaluated inside the launch)
     int coop_max = 0;
-    if (n == 1 && !gated && !sc.merge && !jobs[0].tile && !(flags & FLAG_GATE))
+    if (n == 1 && !sc.merge && !jobs[0].tile && !(flags & FLAG_GATE))
         HIPCHK(max_coop_groups(1024, &coop_max));
     LaunchShape sh;
     sh.threads = ctx->threads;
@@ -600,6 +602,8 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
     ctx->last_tuned = 0;
     if (ctx->shape_forced) {
         sh = ctx->forced;
+    } else if (follow && follow->groups > 1 && coop_max > 1) {
+        sh = *follow;
     } else if (it != ctx->tuned.end()) {
         sh = it->second;
         if (ctx->threads_forced) sh.threads = ctx->threads;
@@ -858,6 +862,7 @@ struct Batch {
     int64_t max_nb[MAXST] = {};
     float *X = nullptr;
     uint8_t *gates = nullptr;
+    int64_t *xoff_dev = nullptr;   // gated: feature row offset of each image
 };
 
 struct TileInfo {
@@ -908,11 +913,12 @@ rapid_status prepare_batch(rapid_ctx *ctx, const rapid_image *imgs, int32_t n, c
         Wmax = std::max(Wmax, imgs[i].W);
         Hmax = std::max(Hmax, imgs[i].H);
     }
-    size_t off_x = total, off_g = 0;
+    size_t off_x = total, off_g = 0, off_xo = 0;
     if (gated) {
         off_x = align256(total);
         off_g = align256(off_x + 4 * 16 * (size_t)b.Ktot);
-        total = align256(off_g + (size_t)b.Ktot);
+        off_xo = align256(off_g + (size_t)b.Ktot);
+        total = align256(off_xo + 8 * (size_t)n);
     }
     if (total > ctx->pool_size) {
         HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -947,6 +953,7 @@ rapid_status prepare_batch(rapid_ctx *ctx, const rapid_image *imgs, int32_t n, c
     if (gated) {
         b.X = reinterpret_cast<float *>(ctx->pool + off_x);
         b.gates = reinterpret_cast<uint8_t *>(ctx->pool + off_g);
+        b.xoff_dev = reinterpret_cast<int64_t *>(ctx->pool + off_xo);
         // the gate is evaluated inside the refinement launch (FLAG_GATE),
         // which also clears the moved counters
         for (int i = 0; i < n; i++) {
@@ -1024,13 +1031,40 @@ static rapid_status gated_impl(rapid_ctx *ctx, const rapid_image *imgs, int32_t 
     Batch b;
     rapid_status r = prepare_batch(ctx, imgs, n, params, nullptr, true, b, tiles);
     if (r) return r;
-    // one launch: the levels before the gate, then in every workgroup the
-    // features of its superpixels and the network's decision (Eq. (6)),
-    // then the finer levels under the gate (Eq. (7))
     b.sc.mlp_w = model->w_bf16_dev;
     b.sc.mlp_thresh = model->thresh;
-    if ((r = run_jobs(ctx, b.jobs, b.sc, 0, b.sc.n_stages, FLAG_INIT | FLAG_OUT | FLAG_GATE, b.Kmax, b.nbF_max)))
-        return r;
+    int coop_max = 0;
+    if (n == 1 && !tiles && !b.sc.merge) HIPCHK(max_coop_groups(1024, &coop_max));
+    // separate launches for a large image, or when a fixed launch shape
+    // spreads images over many workgroups
+    const bool large = (int64_t)imgs[0].W * imgs[0].H >= ((int64_t)1 << 20);
+    if (coop_max > 1 && (ctx->shape_forced ? ctx->forced.groups > 1 : large)) {
+        // A large single image: the levels before the gate, then the
+        // features and the network's decision (Eq. (6)) in launches of
+        // their own, then the levels under the gate (Eq. (7)); both
+        // refinement launches may spread over many workgroups.  The gate
+        // bits equal those of the single launch below (same features).
+        Job &J = b.jobs[0];
+        const int gs = b.sc.gate_stage;
+        HIPCHK(hipMemsetAsync(J.moved, 0, 8 * (size_t)J.K, ctx->stream));
+        HIPCHK(hipMemsetAsync(b.xoff_dev, 0, 8, ctx->stream));
+        J.gate = nullptr;
+        if ((r = run_jobs(ctx, b.jobs, b.sc, 0, gs, FLAG_INIT, b.Kmax, b.nbF_max))) return r;
+        const LaunchShape first = ctx->last;
+        HIPCHK(launch_features(ctx->jobs_dev, 1, b.sc.B[gs - 1], (gs - 1) & 1, b.sc.F, J.K, b.max_nb[gs - 1],
+                               b.xoff_dev, b.X, ctx->stream));
+        HIPCHK(launch_mlp_fwd(b.X, J.K, model->w_bf16_dev, model->thresh, nullptr, b.gates, ctx->stream));
+        J.gate = b.gates;
+        J.moved = nullptr;
+        if ((r = run_jobs(ctx, b.jobs, b.sc, gs, b.sc.n_stages, FLAG_OUT, b.Kmax, b.nbF_max, &first))) return r;
+    } else {
+        // one launch: the levels before the gate, then in every workgroup
+        // the features of its superpixels and the network's decision
+        // (Eq. (6)), then the finer levels under the gate (Eq. (7))
+        if ((r = run_jobs(ctx, b.jobs, b.sc, 0, b.sc.n_stages, FLAG_INIT | FLAG_OUT | FLAG_GATE, b.Kmax,
+                          b.nbF_max)))
+            return r;
+    }
     if (features_dev)
         HIPCHK(hipMemcpyAsync(features_dev, b.X, 4 * 16 * (size_t)b.Ktot, hipMemcpyDeviceToDevice, ctx->stream));
     if (gate_dev)

@@ -128,13 +128,15 @@ hipError_t launch_expand(const int32_t *L, int W, int H, int B, int32_t *out, in
 hipError_t launch_refine(const Job *jobs_dev, int n_jobs, const Sched &sc, const LdsPlan &lp,
                          int s_begin, int s_end, int flags, const uint32_t *lut_dev, int threads,
                          hipStream_t stream);
-// one job on `groups` workgroups of a cooperative launch (no gate, no merge,
-// not a slide tile); sweeps with at most solo_max active blocks run on the
+// one job on `groups` workgroups of a cooperative launch (no merge, not a
+// slide tile, gate bits from the caller or none: gate_words > 0 loads them);
+// sweeps with at most solo_max active blocks run on the
 // first workgroup alone (solo_max < 0: never); max_coop_groups: the most
 // workgroups of `threads` lanes that can be resident together on the
 // current device
 hipError_t launch_refine_mc(const Job *jobs_dev, int groups, const Sched &sc, int s_begin, int s_end, int flags,
-                            const uint32_t *lut_dev, int threads, int64_t solo_max, hipStream_t stream);
+                            const uint32_t *lut_dev, int threads, int64_t solo_max, int gate_words,
+                            hipStream_t stream);
 hipError_t max_coop_groups(int threads, int *out);
 
 // gate network size and feature accumulators

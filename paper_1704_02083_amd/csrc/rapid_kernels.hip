@@ -1389,9 +1389,13 @@ __device__ __forceinline__ void class_push_wg(bool e, int cls, int32_t v, int32_
         if (!grid_sync(ctl, bar, &s_ok)) return;   \
     } while (0)
 
+template <int GM>
 __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs, Sched sc, int s_begin, int s_end,
                                                     int flags, const uint32_t *__restrict__ lut_g, int64_t solo_max)
 {
+    // GM_BITS: the gate bits of all superpixels, loaded into LDS (dynamic,
+    // (K + 31) / 32 words) at the first gated stage
+    extern __shared__ uint32_t l_gate[];
     __shared__ uint32_t s_lut[8];
     __shared__ int32_t s_ok, s_nreq;
     __shared__ int32_t l_cnt[9], l_base[9];
@@ -1411,7 +1415,8 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
     uint32_t bar = 0;
     GateView gv;
     gv.bits = nullptr;
-    gv.tt = 0;
+    gv.tt = rule_table(sc.gate_rule);
+    bool gate_loaded = false;
 
     if (tid < 8) s_lut[tid] = lut_g[tid];
     if (tid < 9) l_cnt[tid] = 0;
@@ -1464,6 +1469,19 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
         int32_t *L = J.lab[s & 1];
         const bool use_f64 = sc.f64[s] != 0;
         int64_t *const mv = J.moved;
+        if (GM == GM_BITS && J.gate && s >= sc.gate_stage) {
+            if (!gate_loaded) {
+                // first gated stage: every workgroup its own copy of the bits
+                // (read-only; the grid barrier below orders it before use)
+                for (int w = tid; w < (K + 31) / 32; w += nt) {
+                    uint32_t v = 0;
+                    for (int b = 0; b < 32 && 32 * w + b < K; b++) v |= (J.gate[32 * w + b] != 0 ? 1u : 0u) << b;
+                    l_gate[w] = v;
+                }
+                gate_loaded = true;
+            }
+            gv.bits = l_gate;
+        }
         if (gt < 9) ctl[CTL_CNT + 9 * par + gt] = 0;
         if (gt == 0) {
             ctl[CTL_NCHG] = 0;
@@ -1474,7 +1492,7 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
         if (s > 0) {
             // split: each block inherits its parent's label; a child is a
             // boundary block only on a side where its parent borders another
-            // label
+            // (active) label
             const int Bp = sc.B[s - 1];
             const int nbxp = (W + Bp - 1) / Bp, nbyp = (H + Bp - 1) / Bp;
             const int64_t nbp = (int64_t)nbxp * nbyp;
@@ -1491,13 +1509,13 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
                     a = Lp[p];
                     int32_t k;
                     k = lab_at(Lp, pxb - 1, pyb, nbxp, nbyp);
-                    sw = k >= 0 && k != a;
+                    sw = k >= 0 && k != a && pair_on(gv, a, k);
                     k = lab_at(Lp, pxb + 1, pyb, nbxp, nbyp);
-                    se = k >= 0 && k != a;
+                    se = k >= 0 && k != a && pair_on(gv, a, k);
                     k = lab_at(Lp, pxb, pyb - 1, nbxp, nbyp);
-                    sn = k >= 0 && k != a;
+                    sn = k >= 0 && k != a && pair_on(gv, a, k);
                     k = lab_at(Lp, pxb, pyb + 1, nbxp, nbyp);
-                    ss = k >= 0 && k != a;
+                    ss = k >= 0 && k != a && pair_on(gv, a, k);
                 }
                 for (int ch = 0; ch < r * r; ch++) {
                     const int cx = pxb * r + ch % r, cy = pyb * r + ch / r;
@@ -1509,7 +1527,7 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
                 }
             }
         } else {
-            // boundary blocks of the grid (Eq. (2))
+            // boundary blocks of the grid (Eq. (2); Eq. (7) under the gate)
             for (int64_t i0 = wg0; i0 < nb; i0 += gn) {
                 const int64_t i = i0 + tid;
                 bool e = false;
@@ -1765,13 +1783,15 @@ hipError_t launch_refine(const Job *jobs_dev, int n_jobs, const Sched &sc, const
 }
 
 hipError_t launch_refine_mc(const Job *jobs_dev, int groups, const Sched &sc, int s_begin, int s_end, int flags,
-                            const uint32_t *lut_dev, int threads, int64_t solo_max, hipStream_t stream)
+                            const uint32_t *lut_dev, int threads, int64_t solo_max, int gate_words,
+                            hipStream_t stream)
 {
     Sched sc_arg = sc;
     void *args[] = {(void *)&jobs_dev, (void *)&sc_arg, (void *)&s_begin, (void *)&s_end, (void *)&flags,
                     (void *)&lut_dev, (void *)&solo_max};
-    return hipLaunchCooperativeKernel((const void *)k_refine_mc, dim3((unsigned)groups), dim3((unsigned)threads),
-                                      args, 0, stream);
+    const void *fn = gate_words > 0 ? (const void *)k_refine_mc<GM_BITS> : (const void *)k_refine_mc<GM_NONE>;
+    return hipLaunchCooperativeKernel(fn, dim3((unsigned)groups), dim3((unsigned)threads), args,
+                                      4 * (size_t)gate_words, stream);
 }
 
 hipError_t max_coop_groups(int threads, int *out)
@@ -1779,7 +1799,9 @@ hipError_t max_coop_groups(int threads, int *out)
     int dev = 0, cus = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_refine_mc, threads, 0);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_refine_mc<GM_BITS>, threads,
+                                                         4 * MAX_GATE_WORDS);
     *out = e == hipSuccess ? cus * per_cu : 0;
     return e;
 }

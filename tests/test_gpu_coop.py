@@ -213,3 +213,101 @@ def test_coop_autotune_single_image(gpu_lib, tmp_path):
         assert (lab.cpu().numpy() == ref).all()
     finally:
         c.close()
+
+
+def _gate_helpers():
+    from tests.test_gpu_gate import _dev, _he_case, _oracle_gated, _rand_model
+    return _dev, _he_case, _oracle_gated, _rand_model
+
+
+def test_coop_gated_matches_oracle(gpu_lib):
+    """A gated single image on many workgroups: the levels before the gate
+    and the gated levels in cooperative launches, the features and the
+    network's bits in launches of their own between them.  Features, bits,
+    labels and counters against the oracle, for the caller-supplied bits of
+    rapid_segment too."""
+    _dev, _he_case, _oracle_gated, _rand_model = _gate_helpers()
+    img, p = _he_case()
+    theta, wb = _rand_model(21)
+    thresh, bits, ref, ref_rep, Xo = _oracle_gated(img, p, theta)
+    for g, so in ((8, -1), (64, 4096)):
+        with _shape(g, so):
+            c = gpu_lib.Context(0, timing=True)
+        try:
+            _say("case: coop gated G=%d S=%d, marked %d of %d" % (g, so, bits.sum(), len(bits)))
+            labs, reps, X, gb = c.segment_gated([_dev(img)], p, _dev(wb), thresh, features=True)
+            assert c.last_timings()["workgroups"] == g
+            assert np.abs(X.cpu().numpy() - Xo).max() <= 1e-6
+            assert (gb.cpu().numpy() == bits).all()
+            assert (labs[0].cpu().numpy() == ref).all()
+            assert reps[0] == ref_rep
+            lab, rep = c.segment(_dev(img), p, gate=_dev(bits))
+            assert c.last_timings()["workgroups"] == g
+            assert (lab.cpu().numpy() == ref).all() and rep == ref_rep
+        finally:
+            c.close()
+
+
+@pytest.mark.parametrize("rule", ["either", "both", "differ"])
+def test_coop_gated_nothing_marked(gpu_lib, rule):
+    """No superpixel marked: no pair is active in the gated stages; labels
+    and counters are the oracle's under an all-zero gate."""
+    _dev, _he_case, _, _rand_model = _gate_helpers()
+    img, p = _he_case()
+    p = dict(p, gate_rule=rule)
+    _, wb = _rand_model(21)
+    K = oracle.n_superpixels(256, 192, p)
+    ref, _, ref_rep = oracle.segment(img, p, gate=np.zeros(K, np.uint8))
+    with _shape(16):
+        c = gpu_lib.Context(0)
+    try:
+        _say("case: coop gated, nothing marked, rule %s" % rule)
+        labs, reps, _, gb = c.segment_gated([_dev(img)], p, _dev(wb), 1e9)
+        assert int(gb.sum().item()) == 0
+        assert (labs[0].cpu().numpy() == ref).all()
+        assert reps[0] == ref_rep
+    finally:
+        c.close()
+
+
+def test_coop_gated_large_image(gpu_lib):
+    """A 1024^2 H&E image with K = 4096, gated at the second level, takes
+    the route of separate launches without being asked to (it is large;
+    the autotuner picks the shape of the levels before the gate, the gated
+    levels follow it): labels and counters against the oracle under the
+    GPU's bits, and features, bits and labels against the single-launch
+    route's."""
+    _dev, _, _, _rand_model = _gate_helpers()
+    img = synth.he_tile(1024, 1024, seed=33)
+    p = params.default_params(1024, 1024, 4096, levels=params.THREE_LEVEL, gate_level=1)
+    theta, wb = _rand_model(23)
+    c = gpu_lib.Context(0, timing=True, autotune=True)
+    try:
+        _say("case: coop gated 1024^2 K=4096")
+        labs, reps, X, gb = c.segment_gated([_dev(img)], p, _dev(wb), 0.0, features=True)
+        t = c.last_timings()
+        gbits = gb.cpu().numpy()
+        ref, _, ref_rep = oracle.segment(img, p, gate=gbits)
+        assert (labs[0].cpu().numpy() == ref).all()
+        assert reps[0] == ref_rep
+    finally:
+        c.close()
+    # the single-launch route (one workgroup, gate inside the launch) for
+    # the same image decides the same bits from the same features
+    old = os.environ.get("RAPID_SHAPE")
+    os.environ["RAPID_SHAPE"] = "1024,0,0"
+    try:
+        c = gpu_lib.Context(0)
+    finally:
+        if old is None:
+            os.environ.pop("RAPID_SHAPE", None)
+        else:
+            os.environ["RAPID_SHAPE"] = old
+    try:
+        labs1, _, X1, gb1 = c.segment_gated([_dev(img)], p, _dev(wb), 0.0, features=True)
+        assert (X1.cpu().numpy() == X.cpu().numpy()).all()
+        assert (gb1.cpu().numpy() == gbits).all()
+        assert (labs1[0].cpu().numpy() == labs[0].cpu().numpy()).all()
+    finally:
+        c.close()
+    _say("autotuned shape of the gated levels: %d workgroups" % t["workgroups"])
