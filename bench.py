@@ -51,6 +51,9 @@ def workload(name: str):
     if name == "he4096":
         return None, params.config3(gate_level=1), (
             "one 4096x4096 RGB uint8 synthetic H&E tile (30% background), K=16384, three levels 16|8,4|2,1")
+    if name == "he8192":
+        return None, params.config3(8192, 8192, 65536), (
+            "one 8192x8192 RGB uint8 synthetic H&E image (30% background), K=65536, three levels 16|8,4|2,1")
     if name == "batch":
         imgs = synth.batch_images(200)
         p = params.config2(481, 321)
@@ -186,7 +189,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batch", choices=["batch", "single256", "he4096", "slide", "slide65k", "roi"])
+    ap.add_argument("--workload", default="batch", choices=["batch", "single256", "he4096", "he8192", "slide", "slide65k",
+                                                             "roi"])
     ap.add_argument("--gated", action="store_true",
                     help="H&E workloads: also train the gate and time the gated path")
     ap.add_argument("--gate-rule", default="both", choices=["either", "both"])
@@ -242,7 +246,7 @@ def main():
                           "copy_GBps": round(2 * n / (ms * 1e-3) / 1e9, 1)}), flush=True)
         return
 
-    if args.workload in ("slide", "slide65k", "he4096"):
+    if args.workload in ("slide", "slide65k", "he4096", "he8192"):
         return bench_he(args)
     if args.workload == "roi":
         return bench_roi(args)
@@ -554,7 +558,9 @@ def bench_he(args):
         def run(w=None, th=0.0):
             ctx.segment_slide(rgb, p, tile=2048, halo=64, cell=32, labels=labels, w_bf16=w, thresh=th)
     else:
-        W = H = 4096
+        if args.gated and args.workload != "he4096":
+            raise SystemExit("--gated applies to he4096, slide and slide65k")
+        W = H = 8192 if args.workload == "he8192" else 4096
         rgb = synth_gpu.he_slide(W, H, seed=3, background=0.3, device="cuda")
         labels = torch.empty((H, W), dtype=torch.int32, device="cuda")
 

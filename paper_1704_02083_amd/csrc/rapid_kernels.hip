@@ -728,22 +728,18 @@ __device__ __attribute__((noinline)) void gate_point(const Job &J, const int64_t
     wg_sync();
 }
 
-// SL: where the per-superpixel state lives -- 0 all in global memory, 1
-// statistics, means records and flow counters in LDS, 2 the means records
-// in LDS (the hot reads of P1) and the rest in global memory, 3 the means
-// records and the flow counters in LDS, the statistics in global memory.
-// P1 for one active block bi of the current class: the source keeps its
-// minimum size (Sec. 3.1), the block is a simple point of its label (the
-// topology rule, 3x3 window), then the strict argmin of E' over the source
-// and its distinct 4-neighbour labels that stay within the maximum size
-// (Eq. (3); ties keep the source or the smaller label).  Reads the
+// P1 for one active block bi of the current class (the cooperative
+// kernel's; k_refine writes the same steps out in place): the source keeps
+// its minimum size (Sec. 3.1), the block is a simple point of its label
+// (the topology rule, 3x3 window), then the strict argmin of E' over the
+// source and its distinct 4-neighbour labels that stay within the maximum
+// size (Eq. (3); ties keep the source or the smaller label).  Reads the
 // class-start state only.
-template <bool MERGE>
 __device__ __forceinline__ void propose_block(const Job &J, int s, int B, int32_t bi, int nbx, int nby, int W,
                                               int H, const int32_t *L, const int32_t *mn, const uint32_t *s_lut,
-                                              const Sched &sc, const GateView &gv, bool use_f64, int32_t *s_nreq,
-                                              int32_t &a, int32_t &best, int64_t &m, uint64_t &Ipk, bool &prop,
-                                              bool &smin, bool &stopo)
+                                              const Sched &sc, const GateView &gv, bool use_f64, int32_t &a,
+                                              int32_t &best, int64_t &m, uint64_t &Ipk, bool &prop, bool &smin,
+                                              bool &stopo)
 {
     const int bx = bi % nbx, by = bi / nbx;
     const bool hw = bx > 0, he = bx + 1 < nbx, hn = by > 0, hs = by + 1 < nby;
@@ -770,7 +766,6 @@ __device__ __forceinline__ void propose_block(const Job &J, int s, int B, int32_
     load_mn(mn, a, ra, rb);
     if ((int64_t)rb.y - g.m < sc.min_size) {
         smin = true;
-        if (MERGE) merge_ask(J, a, s_nreq);
     } else {
         uint32_t mask = 0;
 #pragma unroll
@@ -841,6 +836,10 @@ __device__ __forceinline__ void propose_block(const Job &J, int s, int B, int32_
     }
 }
 
+// SL: where the per-superpixel state lives -- 0 all in global memory, 1
+// statistics, means records and flow counters in LDS, 2 the means records
+// in LDS (the hot reads of P1) and the rest in global memory, 3 the means
+// records and the flow counters in LDS, the statistics in global memory.
 template <int SL, int GM, bool MERGE>
 __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, Sched sc, LdsPlan lp,
                                                   int s_begin, int s_end, int flags,
@@ -1119,8 +1118,103 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
                     uint64_t Ipk = 0;
                     if (e < ncls) {
                         bi = list_get(llst, capl, J.lists, c * capg, e);
-                        propose_block<MERGE>(J, s, B, bi, nbx, nby, W, H, L, mn, s_lut, sc, gv, use_f64, &s_nreq, a, best, m,
-                                             Ipk, prop, smin, stopo);
+                        // the steps of propose_block written out in place:
+                        // the call cost this kernel 1 % in instruction
+                        // scheduling (both are checked against the oracle)
+                        const int bx = bi % nbx, by = bi / nbx;
+                        const bool hw = bx > 0, he = bx + 1 < nbx, hn = by > 0, hs = by + 1 < nby;
+                        // every global load of the block at once: its label,
+                        // its 3x3 ring and its colour sum
+                        const int32_t *Lc = L + bi;
+                        a = Lc[0];
+                        int32_t rl[8];
+                        rl[0] = (hn && hw) ? Lc[-nbx - 1] : -1;
+                        rl[1] = hn ? Lc[-nbx] : -1;
+                        rl[2] = (hn && he) ? Lc[-nbx + 1] : -1;
+                        rl[3] = hw ? Lc[-1] : -1;
+                        rl[4] = he ? Lc[1] : -1;
+                        rl[5] = (hs && hw) ? Lc[nbx - 1] : -1;
+                        rl[6] = hs ? Lc[nbx] : -1;
+                        rl[7] = (hs && he) ? Lc[nbx + 1] : -1;
+                        int64_t I[3];
+                        block_rgb(J, s, B, bi, bx, by, I);
+                        Ipk = pack_rgb(I[0], I[1], I[2]);
+                        Geo g = block_geo(bx, by, B, W, H);
+                        m = g.m;
+                        int4 ra;
+                        int2 rb;
+                        load_mn(mn, a, ra, rb);
+                        if ((int64_t)rb.y - g.m < sc.min_size) {
+                            smin = true;
+                            if (MERGE) merge_ask(J, a, &s_nreq);
+                        } else {
+                            uint32_t mask = 0;
+#pragma unroll
+                            for (int q = 0; q < 8; q++) mask |= (rl[q] == a ? 1u : 0u) << q;
+                            if (!((s_lut[mask >> 5] >> (mask & 31)) & 1u)) {
+                                stopo = true;
+                            } else {
+                                // 4-neighbours W, E, N, S and their shared edge lengths
+                                const int32_t nl[4] = {rl[3], rl[4], rl[1], rl[6]};
+                                const int el[4] = {g.h, g.h, g.w, g.w};
+                                // candidate labels: distinct, != a, ascending
+                                // (sorting network; excluded values sink as INT_MAX)
+                                int32_t q0 = (nl[0] < 0 || nl[0] == a) ? INT32_MAX : nl[0];
+                                int32_t q1 = (nl[1] < 0 || nl[1] == a) ? INT32_MAX : nl[1];
+                                int32_t q2 = (nl[2] < 0 || nl[2] == a) ? INT32_MAX : nl[2];
+                                int32_t q3 = (nl[3] < 0 || nl[3] == a) ? INT32_MAX : nl[3];
+                                int32_t t0 = min(q0, q1), t1 = max(q0, q1), t2 = min(q2, q3), t3 = max(q2, q3);
+                                int32_t s0 = min(t0, t2), s2 = max(t0, t2), s1 = min(t1, t3), s3 = max(t1, t3);
+                                int32_t u1 = min(s1, s2), u2 = max(s1, s2);
+                                const int32_t cs[4] = {s0, u1, u2, s3};
+                                int bnd_a = 0;
+#pragma unroll
+                                for (int d = 0; d < 4; d++) bnd_a += (nl[d] >= 0 && nl[d] != a) ? el[d] : 0;
+                                best = a;
+                                if (use_f64) {
+                                    const double dm = (double)g.m, dI0 = (double)I[0], dI1 = (double)I[1],
+                                                 dI2 = (double)I[2], dpx = (double)g.px, dpy = (double)g.py;
+                                    double estar = energy_f64(ra, rb, sc, dm, dI0, dI1, dI2, dpx, dpy, sc.d_wb * (double)bnd_a);
+#pragma unroll
+                                    for (int u = 0; u < 4; u++) {
+                                        const int32_t k = cs[u];
+                                        if (k == INT32_MAX || (u > 0 && k == cs[u - 1])) continue;
+                                        int4 ka;
+                                        int2 kb;
+                                        load_mn(mn, k, ka, kb);
+                                        if ((int64_t)kb.y + g.m > sc.max_size) continue;
+                                        int bnd = 0;
+#pragma unroll
+                                        for (int d = 0; d < 4; d++) bnd += (nl[d] >= 0 && nl[d] != k) ? el[d] : 0;
+                                        double ek = energy_f64(ka, kb, sc, dm, dI0, dI1, dI2, dpx, dpy, sc.d_wb * (double)bnd);
+                                        if (ek < estar) {
+                                            estar = ek;
+                                            best = k;
+                                        }
+                                    }
+                                } else {
+                                    int64_t estar = block_energy(ra, rb, g, I, bnd_a, sc);
+#pragma unroll
+                                    for (int u = 0; u < 4; u++) {
+                                        const int32_t k = cs[u];
+                                        if (k == INT32_MAX || (u > 0 && k == cs[u - 1])) continue;
+                                        int4 ka;
+                                        int2 kb;
+                                        load_mn(mn, k, ka, kb);
+                                        if ((int64_t)kb.y + g.m > sc.max_size) continue;
+                                        int bnd = 0;
+#pragma unroll
+                                        for (int d = 0; d < 4; d++) bnd += (nl[d] >= 0 && nl[d] != k) ? el[d] : 0;
+                                        int64_t ek = block_energy(ka, kb, g, I, bnd, sc);
+                                        if (ek < estar) {
+                                            estar = ek;
+                                            best = k;
+                                        }
+                                    }
+                                }
+                                prop = best != a && pair_on(gv, a, best);
+                            }
+                        }
                     }
                     n_smin += smin;
                     n_stopo += stopo;
@@ -1397,7 +1491,7 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
     // (K + 31) / 32 words) at the first gated stage
     extern __shared__ uint32_t l_gate[];
     __shared__ uint32_t s_lut[8];
-    __shared__ int32_t s_ok, s_nreq;
+    __shared__ int32_t s_ok;
     __shared__ int32_t l_cnt[9], l_base[9];
     __shared__ unsigned long long s_skip[2];
 
@@ -1421,7 +1515,6 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
     if (tid < 8) s_lut[tid] = lut_g[tid];
     if (tid < 9) l_cnt[tid] = 0;
     if (tid < 2) s_skip[tid] = 0;
-    if (tid == 0) s_nreq = 0;
     for (int64_t i = gt; i < 2 * (int64_t)K; i += gn) fl[i] = 0;
     if (s_end > s_begin) {
         // visit stamps are unique per (stage, sweep) of this launch
@@ -1581,8 +1674,8 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
                         uint64_t Ipk = 0;
                         if (e < ncls) {
                             bi = llst[e];
-                            propose_block<false>(J, s, B, bi, nbx, nby, W, H, L, mn, s_lut, sc, gv, use_f64, &s_nreq,
-                                                 a, best, m, Ipk, prop, smin, stopo);
+                            propose_block(J, s, B, bi, nbx, nby, W, H, L, mn, s_lut, sc, gv, use_f64, a, best, m, Ipk,
+                                          prop, smin, stopo);
                         }
                         n_smin += smin;
                         n_stopo += stopo;

@@ -311,3 +311,30 @@ def test_coop_gated_large_image(gpu_lib):
     finally:
         c.close()
     _say("autotuned shape of the gated levels: %d workgroups" % t["workgroups"])
+
+
+def test_coop_he8192_max_size_matches_one_workgroup(gpu_lib):
+    """The largest single image the boundary accepts (8192^2, K = 65536,
+    three levels) on 64 workgroups with small sweeps on one workgroup, as
+    the benchmark's autotuner picks it, equals the one-workgroup launch
+    (whose parity with the oracle the 4096^2 and smaller cases pin) in
+    labels, statistics-derived counters and every stage report."""
+    import torch
+    rgb = synth_gpu.he_slide(8192, 8192, seed=3, background=0.3, device="cuda")
+    p = params.config3(8192, 8192, 65536)
+    out = []
+    for g, so in ((1, -1), (64, 16384)):
+        with _shape(g, so):
+            c = gpu_lib.Context(0, timing=True)
+        try:
+            _say("case: 8192^2 K=65536, G=%d S=%d" % (g, so))
+            lab, rep = c.segment(rgb, p)
+            torch.cuda.synchronize()
+            assert c.last_timings()["workgroups"] == g
+            out.append((lab, rep))
+        finally:
+            c.close()
+    (l1, r1), (l2, r2) = out
+    assert bool((l1 == l2).all().item())
+    assert r1 == r2
+    assert int(l2.min().item()) == 0 and int(l2.max().item()) == 65535
