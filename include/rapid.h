@@ -91,7 +91,10 @@ typedef struct {
     float block_sums_ms;   /* block-sum launches before the refinement
                               kernel (0 when that kernel builds the
                               pyramids itself)                        */
-    float refine_ms;       /* the refinement kernel (all stages)   */
+    float refine_ms;       /* the refinement kernel (all stages); a gated
+                              single image run as separate launches: from
+                              the first refinement launch to the end of
+                              the last, the gate's launches included  */
     int32_t threads;       /* launch shape of that call: workgroup size, */
     int32_t stats_lds;     /* per-superpixel state: 1 all in LDS, 3 the
                               means records and flow counters in LDS, 2

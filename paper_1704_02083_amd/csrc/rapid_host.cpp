@@ -1056,7 +1056,14 @@ static rapid_status gated_impl(rapid_ctx *ctx, const rapid_image *imgs, int32_t 
         HIPCHK(launch_mlp_fwd(b.X, J.K, model->w_bf16_dev, model->thresh, nullptr, b.gates, ctx->stream));
         J.gate = b.gates;
         J.moved = nullptr;
-        if ((r = run_jobs(ctx, b.jobs, b.sc, gs, b.sc.n_stages, FLAG_OUT, b.Kmax, b.nbF_max, &first))) return r;
+        // the timings keep the first launch's start: the refinement time then
+        // covers both launches and the gate's launches between them
+        const bool timing = ctx->timing;
+        ctx->timing = false;
+        r = run_jobs(ctx, b.jobs, b.sc, gs, b.sc.n_stages, FLAG_OUT, b.Kmax, b.nbF_max, &first);
+        ctx->timing = timing;
+        if (r) return r;
+        if (timing) HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
     } else {
         // one launch: the levels before the gate, then in every workgroup
         // the features of its superpixels and the network's decision

@@ -1665,6 +1665,82 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
                     const int ncls = ctl_read(cnt, c);   // stable during the sweep
                     if (ncls == 0) continue;
                     const int32_t *llst = J.lists + c * capg;
+                    if (ncls <= step) {
+                        // One pass: every lane keeps its block's proposal in
+                        // registers through P2 and P3 (no proposal records;
+                        // the proposal counter only counts).
+                        const int64_t e = first + tid;
+                        bool prop = false, smin = false, stopo = false;
+                        int32_t bi = 0, a = 0, best = 0;
+                        int64_t m = 0;
+                        uint64_t Ipk = 0;
+                        if (e < ncls) {
+                            bi = llst[e];
+                            propose_block(J, s, B, bi, nbx, nby, W, H, L, mn, s_lut, sc, gv, use_f64, a, best, m, Ipk,
+                                          prop, smin, stopo);
+                        }
+                        n_smin += smin;
+                        n_stopo += stopo;
+                        if (prop && J.involved && s >= J.involve_stage) {
+                            J.involved[a] = 1;
+                            J.involved[best] = 1;
+                        }
+                        const uint64_t pm = __ballot(prop);
+                        if (pm != 0 && lane_id() == __ffsll((unsigned long long)pm) - 1)
+                            atomicAdd(&ctl[CTL_NPROP], (uint32_t)__popcll(pm));
+                        if (prop) {
+                            atomicAdd(&fl[2 * (int64_t)a], (int32_t)m);
+                            atomicAdd(&fl[2 * (int64_t)best + 1], (int32_t)m);
+                        }
+                        SW_SYNC();
+                        const int np = ctl_read(ctl, CTL_NPROP);
+                        if (np == 0) continue;   // uniform
+                        // ---- P2: size filter on the class-wide flows, commit
+                        // (both sides of the move in one lane)
+                        bool com = false;
+                        if (prop) {
+                            com = mn_size(mn, a) - fl[2 * (int64_t)a] >= sc.min_size &&
+                                  mn_size(mn, best) + fl[2 * (int64_t)best + 1] <= sc.max_size;
+                            if (com) {
+                                const Geo g = block_geo(bi % nbx, bi / nbx, B, W, H);
+                                const int64_t d[6] = {g.m, (int64_t)(Ipk & 0x1FFFFFull),
+                                                      (int64_t)((Ipk >> 21) & 0x1FFFFFull), (int64_t)(Ipk >> 42),
+                                                      g.px, g.py};
+                                int64_t *ra = st + 6 * (int64_t)a, *rk = st + 6 * (int64_t)best;
+#pragma unroll
+                                for (int q = 0; q < 6; q++) {
+                                    add64(ra + q, -d[q]);
+                                    add64(rk + q, d[q]);
+                                }
+                                if (mv) {
+                                    atomicAdd(reinterpret_cast<unsigned long long *>(mv + a), (unsigned long long)g.m);
+                                    atomicAdd(reinterpret_cast<unsigned long long *>(mv + best),
+                                              (unsigned long long)g.m);
+                                }
+                                L[bi] = best;
+                            }
+                        }
+                        const int slot = wave_append(nchg, com);
+                        if (slot >= 0) J.changed[slot] = bi;
+                        SW_SYNC();
+                        // ---- P3: refresh the moved superpixels, clear the
+                        // flow counters
+                        if (prop) {
+                            fl[2 * (int64_t)a] = 0;
+                            fl[2 * (int64_t)best + 1] = 0;
+                            if (com) {
+                                refresh_sp(st, mn, a, sc);
+                                refresh_sp(st, mn, best, sc);
+                            }
+                        }
+                        // every lane read np before the P2 barrier: safe to reset
+                        if (gt == 0) {
+                            ctr[1] += (unsigned long long)np;
+                            ctl[CTL_NPROP] = 0;
+                        }
+                        SW_SYNC();
+                        continue;
+                    }
                     // ---- P1: propose from the class-start state
                     for (int64_t e0 = first; e0 < ncls; e0 += step) {
                         const int e = (int)(e0 + tid);
@@ -1889,8 +1965,13 @@ hipError_t launch_refine_mc(const Job *jobs_dev, int groups, const Sched &sc, in
 
 hipError_t max_coop_groups(int threads, int *out)
 {
-    int dev = 0, cus = 0, per_cu = 0;
+    int dev = 0, cus = 0, per_cu = 0, coop = 0;
     hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+    if (e == hipSuccess && !coop) {
+        *out = 0;   // no cooperative launches on this device: one workgroup per image
+        return hipSuccess;
+    }
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_refine_mc<GM_BITS>, threads,
