@@ -338,3 +338,25 @@ def test_coop_he8192_max_size_matches_one_workgroup(gpu_lib):
     assert bool((l1 == l2).all().item())
     assert r1 == r2
     assert int(l2.min().item()) == 0 and int(l2.max().item()) == 65535
+
+
+@pytest.mark.parametrize("max_sweeps", [1, 2, 5])
+def test_coop_sweep_cap_unconverged_stages(gpu_lib, max_sweeps):
+    """Sweep caps that end stages unconverged (the class counts then stand
+    swapped at the next stage) on 8 workgroups, with small sweeps on the
+    grid, on one workgroup, or all on one workgroup: labels and stage
+    reports ("not converged" included) equal the oracle's."""
+    img = synth.voronoi_gradient(481, 321, seed=1003)
+    p = params.config2(481, 321)
+    p["max_sweeps"] = max_sweeps
+    ref, _, ref_rep = oracle.segment(img, p)
+    assert any(not r["converged"] for r in ref_rep)
+    for so in (-1, 2048, 1 << 30):
+        with _shape(8, so):
+            c = gpu_lib.Context(0)
+        try:
+            _say("case: coop G=8 S=%d max_sweeps %d" % (so, max_sweeps))
+            got, rep = _run(c, img, p)
+            assert (got == ref).all() and rep == ref_rep, (so, max_sweeps)
+        finally:
+            c.close()

@@ -81,3 +81,40 @@ def test_random_configuration(gpu_lib, seed, large):
             os.environ.pop("RAPID_SHAPE", None)
         else:
             os.environ["RAPID_SHAPE"] = old
+
+
+@pytest.mark.parametrize("seed,large", [(s, False) for s in range(64)] + [(100 + s, True) for s in range(8)])
+def test_random_configuration_cooperative(gpu_lib, seed, large):
+    """The same 72 cases with the image spread over a cooperative launch of
+    random size, small sweeps on one workgroup at a random threshold (never,
+    some, every sweep): sweep caps that end stages unconverged, caller gate
+    bits and every schedule against the oracle (merge cases fall back to one
+    workgroup and must still match)."""
+    import torch
+    rng = np.random.default_rng(7000 + seed)
+    _, W, H, p, img = _case(seed, large)
+    Kp = oracle.n_superpixels(W, H, p)
+    gate = (rng.random(Kp) < 0.5).astype(np.uint8) if p["gate_level"] >= 0 else None
+    ref, ref_stats, ref_rep = oracle.segment(img, p, gate=gate)
+    groups = int(rng.choice([2, 4, 8, 32, 64]))
+    solo = int(rng.choice([-1, 64, 1024, 1 << 30]))
+    shape = "1024,0,0,%d,%d" % (groups, solo)
+    old = os.environ.get("RAPID_SHAPE")
+    os.environ["RAPID_SHAPE"] = shape
+    try:
+        print("case: seed %d %dx%d K'=%d levels %s sweeps %d merge %s gate %s shape %s" % (
+            seed, W, H, Kp, p["levels"], p["max_sweeps"], p["merge"],
+            p.get("gate_rule") if gate is not None else None, shape), flush=True)
+        c = gpu_lib.Context(0, timing=True)
+        g = None if gate is None else torch.from_numpy(gate).cuda()
+        lab, rep = c.segment(torch.from_numpy(img).cuda(), p, gate=g)
+        torch.cuda.synchronize()
+        assert c.last_timings()["workgroups"] == (1 if p["merge"] else groups)
+        assert (lab.cpu().numpy() == ref).all()
+        assert rep == ref_rep
+        c.close()
+    finally:
+        if old is None:
+            os.environ.pop("RAPID_SHAPE", None)
+        else:
+            os.environ["RAPID_SHAPE"] = old
