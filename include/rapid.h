@@ -277,7 +277,13 @@ typedef struct {
  * features of all images' superpixels, image after image (sum of gx*gy rows
  * of 16 floats); gate_dev (nullable) the gate bits in the same order.
  * gate_level must be in [1, n_levels).  A model with non-finite weights is
- * refused: the images are segmented plain and RAPID_EGATE is returned. */
+ * refused: the images are segmented plain and RAPID_EGATE is returned.
+ * Several images, or a single small one, run as one launch that decides the
+ * gate inside; a single image of at least 2^20 pixels (or any single image
+ * when RAPID_SHAPE asks for several workgroups per image) runs as the
+ * levels before the gate, the feature and network launches, and the gated
+ * levels, so that its refinement launches can spread over many
+ * workgroups.  Both routes decide the same bits and labels. */
 rapid_status rapid_segment_gated(rapid_ctx *ctx, const rapid_image *imgs, int32_t n,
                                  const rapid_params *params, const rapid_gate_model *model,
                                  float *features_dev, uint8_t *gate_dev, rapid_report *reports);
