@@ -612,9 +612,28 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
         // per candidate shape (the labels are the same for all of them)
         for (int i = 0; i < 2; i++)
             if (!ctx->tev[i]) HIPCHK(hipEventCreate(&ctx->tev[i]));
+        // candidates: for a single image first the cooperative shapes (8 ..
+        // 128 workgroups of 1024 lanes; more pay more for each grid barrier
+        // than they gain; small sweeps on the whole grid or on one
+        // workgroup), then the one-workgroup shapes, the default first
+        std::vector<LaunchShape> cand;
+        const int solo_all[3] = {-1, 4096, 16384};
+        if (!ctx->threads_forced || ctx->threads == 1024)
+            for (int g = 8; g <= std::min(coop_max, 128); g *= 2)
+                for (int so = 0; so < 3; so++) {
+                    LaunchShape c;
+                    c.threads = 1024;
+                    c.stats_lds = 0;
+                    c.pyramid = 0;
+                    c.groups = g;
+                    c.solo = solo_all[so];
+                    cand.push_back(c);
+                }
+        const size_t n_coop = cand.size();
+        LaunchShape dflt = sh;
+        if (ctx->threads_forced) dflt.threads = ctx->threads;
+        cand.push_back(dflt);
         const int thr_all[3] = {256, 512, 1024};
-        LaunchShape best;
-        best.ms = -1.0f;
         const int res_all[4] = {1, 3, 2, 0};
         for (int t = 0; t < 3; t++) {
             if (ctx->threads_forced && thr_all[t] != ctx->threads) continue;
@@ -626,35 +645,27 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
                     c.threads = thr_all[t];
                     c.stats_lds = l;
                     c.pyramid = py;
-                    rapid_status r = launch_shape(ctx, jobs, sc, s_begin, s_end, flags, Kmax, nbF_max, gated, c,
-                                                  ctx->tev[0], nullptr, ctx->tev[1]);
-                    if (r) return r;
-                    HIPCHK(hipEventSynchronize(ctx->tev[1]));
-                    HIPCHK(hipEventElapsedTime(&c.ms, ctx->tev[0], ctx->tev[1]));
-                    if (best.ms < 0.0f || c.ms < best.ms) best = c;
+                    if (c.threads == dflt.threads && c.stats_lds == dflt.stats_lds && c.pyramid == dflt.pyramid)
+                        continue;
+                    cand.push_back(c);
                 }
             }
         }
-        // one image on 8 .. 128 workgroups of 1024 lanes (more pay more for
-        // each grid barrier than they gain), small sweeps on the whole grid
-        // or on one workgroup
-        const int solo_all[3] = {-1, 4096, 16384};
-        if (!ctx->threads_forced || ctx->threads == 1024)
-            for (int g = 8; g <= std::min(coop_max, 128); g *= 2)
-                for (int so = 0; so < 3; so++) {
-                    LaunchShape c;
-                    c.threads = 1024;
-                    c.stats_lds = 0;
-                    c.pyramid = 0;
-                    c.groups = g;
-                    c.solo = solo_all[so];
-                    rapid_status r = launch_shape(ctx, jobs, sc, s_begin, s_end, flags, Kmax, nbF_max, gated, c,
-                                                  ctx->tev[0], nullptr, ctx->tev[1]);
-                    if (r) return r;
-                    HIPCHK(hipEventSynchronize(ctx->tev[1]));
-                    HIPCHK(hipEventElapsedTime(&c.ms, ctx->tev[0], ctx->tev[1]));
-                    if (best.ms < 0.0f || c.ms < best.ms) best = c;
-                }
+        LaunchShape best;
+        best.ms = -1.0f;
+        for (size_t ci = 0; ci < cand.size(); ci++) {
+            LaunchShape c = cand[ci];
+            rapid_status r = launch_shape(ctx, jobs, sc, s_begin, s_end, flags, Kmax, nbF_max, gated, c,
+                                          ctx->tev[0], nullptr, ctx->tev[1]);
+            if (r) return r;
+            HIPCHK(hipEventSynchronize(ctx->tev[1]));
+            HIPCHK(hipEventElapsedTime(&c.ms, ctx->tev[0], ctx->tev[1]));
+            if (best.ms < 0.0f || c.ms < best.ms) best = c;
+            // a default one-workgroup launch more than twice as slow as the
+            // best cooperative one: the other one-workgroup shapes (which
+            // differ from it by far less) are not timed
+            if (ci == n_coop && n_coop > 0 && c.ms > 2.0f * best.ms) break;
+        }
         sh = best;
         ctx->tuned[key] = best;
         ctx->last_tuned = 1;
