@@ -53,6 +53,10 @@ CASES = [
     (64, 64, 1, [(1, [16, 8, 4, 2, 1])], 0, 7),         # one superpixel: no boundary
     (16, 16, 1, [(1, [1])], 0, 8),                      # single stage at B = 1
     (481, 321, 400, [(1, [16, 8, 4, 2, 1])], 0, 9),    # a batch image's shape
+    (1, 64, 4, [(1, [1])], 0, 21),                      # one pixel wide
+    (64, 1, 4, [(1, [1])], 0, 22),                      # one pixel tall
+    (2, 300, 8, [(1, [2, 1])], 0, 23),                  # two pixels wide, blocks clipped to the image
+    (300, 2, 8, [(1, [2, 1])], 0, 24),
 ]
 
 
