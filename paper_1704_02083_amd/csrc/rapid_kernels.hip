@@ -1422,8 +1422,9 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
 
 // Grid barrier over the workgroups of a cooperative launch.  The arrival
 // counter only grows (the n-th barrier waits for n * G arrivals); thread 0
-// publishes the workgroup's writes before it arrives and invalidates its
-// caches after the wait (agent-scope fences).  The wait is bounded: past
+// publishes the workgroup's writes before it arrives (agent-scope release:
+// L2 writeback) and invalidates its caches after the wait (agent-scope
+// acquire: L2 invalidation), one of each per barrier.  The wait is bounded: past
 // the spin limit, or when another workgroup gave up, it raises the abort
 // word and returns false, and the caller leaves the kernel, so that every
 // workgroup exits.
@@ -1435,7 +1436,7 @@ __device__ __forceinline__ bool grid_sync(uint32_t *ctl, uint32_t &target, int32
     target += gridDim.x;
     if (threadIdx.x == 0) {
         int ok = 1;
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         atomicAdd(&ctl[CTL_BAR], 1u);
         uint32_t spins = 0;
         while (__hip_atomic_load(&ctl[CTL_BAR], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -1447,7 +1448,7 @@ __device__ __forceinline__ bool grid_sync(uint32_t *ctl, uint32_t &target, int32
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         *s_ok = ok;
     }
     __syncthreads();
