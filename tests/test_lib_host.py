@@ -48,6 +48,8 @@ def test_check_params_accepts_workloads():
     assert rapid.check_params(481, 321, params.config2(481, 321)) == 400
     assert rapid.check_params(321, 481, params.config2(321, 481)) == 408
     assert rapid.check_params(4096, 4096, params.config3()) == 16384
+    # the largest single image the boundary takes (the 8192^2 benchmark image)
+    assert rapid.check_params(8192, 8192, params.config3(8192, 8192, 65536)) == 65536
 
 
 @pytest.mark.parametrize("mutate", [
