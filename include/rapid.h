@@ -75,7 +75,9 @@ typedef struct {
      * launch or in separate launches; and, for a single image without gate
      * or merge, the image spread over 8 .. 128 workgroups of a cooperative
      * launch, with small sweeps on the whole grid or on one workgroup --
-     * and keeps the fastest; later calls of that
+     * and keeps the fastest (without tuning, a single image whose finest
+     * stage has 2^20 blocks or more runs on 64 workgroups, sweeps of at
+     * most 16384 active blocks on one); later calls of that
      * shape use it.  Every candidate computes the same labels (the result
      * never depends on the shape), so tuning costs time only.  Only calls
      * that start from the image tune (not rapid_refine_level).

@@ -597,6 +597,13 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
     sh.threads = ctx->threads;
     sh.stats_lds = lds_residency(ctx->lds_limit, Kmax, gated, 1);
     sh.pyramid = (int)n >= PYRAMID_MIN_JOBS ? 1 : 0;
+    if (coop_max > 1 && nbF_max >= ((int64_t)1 << 20) && (!ctx->threads_forced || ctx->threads == 1024)) {
+        // untuned default for a single image of a million finest blocks or
+        // more: the cooperative shape that measured fastest on such images
+        sh.threads = 1024;
+        sh.groups = std::min(64, coop_max);
+        sh.solo = 16384;
+    }
     const std::string key = shape_key(jobs, sc, s_begin, s_end, flags, Kmax, gated);
     auto it = ctx->tuned.find(key);
     ctx->last_tuned = 0;
@@ -630,8 +637,10 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
                     cand.push_back(c);
                 }
         const size_t n_coop = cand.size();
-        LaunchShape dflt = sh;
-        if (ctx->threads_forced) dflt.threads = ctx->threads;
+        LaunchShape dflt;   // the default one-workgroup shape
+        dflt.threads = ctx->threads;
+        dflt.stats_lds = lds_residency(ctx->lds_limit, Kmax, gated, 1);
+        dflt.pyramid = (int)n >= PYRAMID_MIN_JOBS ? 1 : 0;
         cand.push_back(dflt);
         const int thr_all[3] = {256, 512, 1024};
         const int res_all[4] = {1, 3, 2, 0};
