@@ -124,3 +124,65 @@ def test_gate_with_targets_is_plain():
     _, st1, _ = oracle.segment(img, p1)
     changed = np.any(st1 != st, axis=1)
     assert np.all(inv[changed] == 1)
+
+
+def _four_region_map():
+    """40 x 20 label map worked by hand: 1 = x < 10, 2 = x >= 30, 0 = the
+    middle columns above y = 10, 3 = the middle columns below.  Flat colours
+    per label.  Superpixel 0 meets 1 along 10 pixel pairs (x = 9|10, y <
+    10), 2 along 10 and 3 along 20 (y = 9|10); superpixel 3 likewise meets
+    1 and 2 along 10 pairs each and 0 along 20."""
+    H, W = 20, 40
+    ys, xs = np.mgrid[0:H, 0:W]
+    lab = np.where(xs < 10, 1, np.where(xs >= 30, 2, np.where(ys < 10, 0, 3))).astype(np.int32)
+    col = {0: (100, 100, 100), 1: (0, 100, 100), 2: (100, 100, 160), 3: (100, 180, 100)}
+    img = np.zeros((H, W, 3), np.uint8)
+    for k, c in col.items():
+        img[lab == k] = c
+    st = np.zeros((4, 6), np.int64)
+    for k in range(4):
+        m = lab == k
+        st[k] = [m.sum(), *(img[m].astype(np.int64).sum(0)), xs[m].sum(), ys[m].sum()]
+    return img, lab, st
+
+
+def test_features_contrast_max_rms_min_by_hand():
+    """Features 10-12 (max, edge-weighted rms and min distance of the mean
+    colours across the superpixel's boundary pixel pairs) on a map whose
+    neighbour contrasts and shared edge lengths all differ, so that a max/min
+    swap, an unweighted (per-neighbour) rms or a mean in place of the rms
+    fails.  Means are fixed point with F = 4 (2^4 = 16 per colour unit), so a
+    colour difference d gives a fixed-point distance 16 d and the features
+    divide by 255 * 16 = 4080."""
+    img, lab, st = _four_region_map()
+    f = oracle.features(img, lab, 1, st, None, 2, 2)
+    cs = 4080.0
+    # superpixel 0 (100,100,100): to 1 d = 100 (10 pairs), to 2 d = 60 (10
+    # pairs), to 3 d = 80 (20 pairs)
+    d01, d02, d03 = 1600.0, 960.0, 1280.0
+    rms0 = np.sqrt((10 * d01 ** 2 + 10 * d02 ** 2 + 20 * d03 ** 2) / 40)   # 1299.846...
+    assert np.isclose(f[0, 10], d01 / cs, rtol=1e-6)
+    assert np.isclose(f[0, 11], rms0 / cs, rtol=1e-6)
+    assert np.isclose(f[0, 12], d02 / cs, rtol=1e-6)
+    # the unweighted rms over the three neighbours (1306.4) and the mean
+    # distance (1280) are both more than 1e-3 away
+    assert abs(f[0, 11] - np.sqrt((d01 ** 2 + d02 ** 2 + d03 ** 2) / 3) / cs) > 1e-3
+    assert abs(f[0, 11] - 1280.0 / cs) > 1e-3
+    # superpixel 3 (100,180,100): to 1 |(100,80,0)| (10 pairs), to 2
+    # |(0,80,60)| = 100 (10 pairs), to 0 80 (20 pairs)
+    d31, d32, d30 = 16 * np.sqrt(100 ** 2 + 80 ** 2), 1600.0, 1280.0
+    rms3 = np.sqrt((10 * d31 ** 2 + 10 * d32 ** 2 + 20 * d30 ** 2) / 40)
+    assert np.isclose(f[3, 10], d31 / cs, rtol=1e-6)
+    assert np.isclose(f[3, 11], rms3 / cs, rtol=1e-6)
+    assert np.isclose(f[3, 12], d30 / cs, rtol=1e-6)
+    # superpixel 1 (0,100,100): to 0 d = 100 (10 pairs), to 3 |(100,80,0)|
+    # (10 pairs): max, rms and min of two equal-length edges
+    d10, d13 = 1600.0, d31
+    assert np.isclose(f[1, 10], d13 / cs, rtol=1e-6)
+    assert np.isclose(f[1, 11], np.sqrt((d10 ** 2 + d13 ** 2) / 2) / cs, rtol=1e-6)
+    assert np.isclose(f[1, 12], d10 / cs, rtol=1e-6)
+    # boundary lengths (pixel pairs): 40, 20, 20, 40; A = 800 / 4 = 200
+    for k, bl in enumerate([40, 20, 20, 40]):
+        assert np.isclose(f[k, 7], bl / (4 * np.sqrt(200)), rtol=1e-6)
+        assert np.isclose(f[k, 8], bl * bl / (16 * 200), rtol=1e-6)
+    assert np.allclose(f[:, 3:6], 0) and np.allclose(f[:, 14], 0) and np.allclose(f[:, 15], 1)

@@ -456,3 +456,25 @@ def test_sweep_cap_reports_not_converged():
     assert all(r["sweeps"] == 1 for r in rep)
     assert all(r["converged"] == (1 if r["commits"] == 0 else 0) for r in rep)
     assert any(r["converged"] == 0 for r in rep)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_energy_equals_pixel_level_eq1(seed):
+    """orc_energy is Eq. (1) at pixel level with fixed-point means: equal,
+    as an exact integer, to the restatement in Python integers, on a
+    refined state and on a random (disconnected) label map, with random
+    weights and F."""
+    rng = np.random.default_rng(50 + seed)
+    W, H = 23 + 5 * seed, 17 + 3 * seed
+    img = rng.integers(0, 256, size=(H, W, 3), dtype=np.uint8)
+    p = dict(params.default_params(W, H, 6, levels=[(1, [4, 2, 1])]),
+             w_col=int(rng.integers(1, 50)), w_pos=int(rng.integers(0, 50)), w_bnd=int(rng.integers(0, 5000)),
+             frac_bits=int(rng.integers(0, 5)), min_size=0)
+    K = oracle.n_superpixels(W, H, p)
+    refined, _, _ = oracle.segment(img, p)
+    rand = rng.integers(0, K, size=(H, W)).astype(np.int32)
+    rand.ravel()[:K] = np.arange(K)   # every label non-empty
+    for lab in (refined, rand):
+        n, S, T = pyref.stats(img, lab, K)
+        c, mu = pyref.means(n, S, T, p["frac_bits"])
+        assert oracle.energy(img, p, lab) == pyref.global_energy(img, lab, c, mu, p)
