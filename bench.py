@@ -1,16 +1,19 @@
 """Benchmark of the RAPID refinement sweep on one MI355X.
 
-A step is one whole segmentation of the batch (block-sum pyramid, grid,
-every stage and sweep of the refinement, pixel labels written) with the
-images already resident in HBM.  The default workload is the batched one:
-200 synthetic RGB uint8 images (100 of 481x321 and 100 of 321x481, Voronoi
-mosaics of 30..120 regions with linear colour gradients and N(0, 6^2) noise),
-400 superpixels each, one level with block sizes 16, 8, 4, 2, 1.
+A step is one whole segmentation (block-sum pyramid, grid, every level,
+stage and sweep of the refinement, and the gate's features and network when
+gated; pixel labels written) with the input already resident in HBM.  The
+default workload is the whole-slide one: a 65536 x 49152 synthetic H&E slide
+(3.22 GPixel, 40 % background) cut into 768 tiles of 2048^2 with a 64-px
+halo, 32-px superpixel cells (3,145,728 superpixels), three levels of ratio
+4 (effective blocks 16 | 8, 4 | 2, 1), all tiles in one launch; plain, then
+under the learned prediction gate at the thresholds calibrated on held-out
+tiles for boundary recall >= 0.99 and >= 0.995 against the plain labels.
 
-Prints one JSON line: throughput in MPixel/s, the roofline of the dominant
-kernel (the refinement kernel, HBM-bound by design: there is no dense
-contraction), and the CPU oracle timed on a bounded sample of the same
-workload on this host.
+Prints one JSON line: plain throughput in MPixel/s (value), the gated
+points, the roofline of the refinement kernel (HBM-bound: there is no dense
+contraction on the sweep), and the CPU oracle timed on sampled tiles of the
+same slide on this host.
 """
 from __future__ import annotations
 
@@ -71,15 +74,32 @@ def workload(name: str):
 PYRAMID_MIN_JOBS = 128   # from this many images or tiles the refinement kernel builds the pyramids
 
 
-def stage_alg_bytes(W, H, rep, pyramid: bool) -> int:
-    """Algorithmic bytes of the stages of one image or tile: with pyramid,
-    the block-sum pyramid (built inside the refinement kernel) reads the RGB
-    pixels once (3 B per pixel) and writes 8 B per block of every stage with
-    B >= 2; per stage the label map is written
-    once and read once by the boundary scan (8 B per block); every block
-    visit reads its 3x3 label window (36 B) and its colour sum (8 B packed,
-    3 B at B = 1); every commit writes a label (4 B) and reads the sum
-    again.  Per-superpixel statistics count zero (on chip, or a small set)."""
+def stage_bytes(W, H, rep, pyramid: bool) -> int:
+    """Algorithmic bytes of the stages of one image or tile: the traffic the
+    method cannot avoid, from its per-stage counters.  With the block-sum
+    pyramid built inside the launch, the RGB pixels are read once (3 B per
+    pixel).  Each stage scans its label map once for the boundary blocks
+    (4 B per block; a gated stage with nothing to do reads nothing); each
+    block visit reads the block's colour sum (6 B: three 16-bit channels);
+    each commit writes a label (4 B) and moves the size, colour and position
+    sums of two superpixels (96 B: 2 x 6 words of 8 B)."""
+    total = 3 * W * H if pyramid else 0
+    for r in rep:
+        B = r["block"]
+        nb = -(-W // B) * -(-H // B)
+        if r["active"] or r["sweeps"]:
+            total += 4 * nb
+        total += 6 * r["active"] + (4 + 96) * r["commits"]
+    return total
+
+
+def stage_bytes_window(W, H, rep, pyramid: bool) -> int:
+    """A second, larger byte model of the same stages, closer to what the
+    kernel reads: with the pyramid, 3 B per pixel read plus 8 B per block of
+    every stage with B >= 2 written; per stage 8 B per block (the label map
+    written once and scanned once); per block visit its whole 3x3 label
+    window (36 B) and its packed colour sum (8 B; 3 B at B = 1); per commit a
+    label (4 B) and the sum again; statistics on chip (0 B)."""
     total = 3 * W * H if pyramid else 0
     for r in rep:
         B = r["block"]
@@ -91,25 +111,35 @@ def stage_alg_bytes(W, H, rep, pyramid: bool) -> int:
     return total
 
 
-def refine_alg_bytes(imgs, reports) -> float:
+def refine_alg_bytes(imgs, reports, model=stage_bytes) -> float:
     """Algorithmic bytes of one refinement launch over whole images: the
     stages' bytes plus the final pixel labels written once (4 B per pixel)."""
     total = 0
     for img, rep in zip(imgs, reports):
         H, W = img.shape[:2]
-        total += 4 * W * H + stage_alg_bytes(W, H, rep, len(imgs) >= PYRAMID_MIN_JOBS)
+        total += 4 * W * H + model(W, H, rep, len(imgs) >= PYRAMID_MIN_JOBS)
     return float(total)
 
 
-def tiles_alg_bytes(W, H, tiles, reports) -> float:
+def tiles_alg_bytes(W, H, tiles, reports, model=stage_bytes) -> float:
     """As refine_alg_bytes for the tiles of a slide: the stages run over each
     tile's extended rectangle (core plus halo), the final labels are written
     for the core pixels only, so once per slide pixel."""
     total = 4 * W * H
     for t, rep in zip(tiles, reports):
         x0, y0, x1, y1 = t["ext"]
-        total += stage_alg_bytes(x1 - x0, y1 - y0, rep, len(tiles) >= PYRAMID_MIN_JOBS)
+        total += model(x1 - x0, y1 - y0, rep, len(tiles) >= PYRAMID_MIN_JOBS)
     return float(total)
+
+
+def host_cpu() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def profile_traffic(kernel: str, wl: str, src_hash: str):
@@ -173,7 +203,8 @@ def cpu_baseline(imgs, p, sample: int):
         px += img.shape[0] * img.shape[1]
     dt = time.perf_counter() - t0
     out = {"value": round(px / dt / 1e6, 4), "unit": "MPixel/s", "cores": 1, "kind": "oracle",
-           "sample": "%d of the %d images (%d px), single-threaded, %.1f s" % (n, len(imgs), px, dt)}
+           "sample": "%d of the %d images (%d px), single-threaded, %.1f s" % (n, len(imgs), px, dt),
+           "host_cpu": host_cpu()}
     if not p.get("merge"):
         # the oracle's sequential FIFO-queue schedule (the paper's queue read
         # literally) on the same sample: context for the synchronous one
@@ -184,15 +215,99 @@ def cpu_baseline(imgs, p, sample: int):
     return out
 
 
+def _oracle_tile_worker(sub, p, barrier, results):
+    """One process of the multi-core CPU baseline on slide tiles: waits for
+    the other processes, then times the oracle on its tile (wall clock)."""
+    import oracle
+    barrier.wait(timeout=300)
+    t0 = time.time()
+    oracle.segment(sub, p)
+    results.put((t0, time.time()))
+
+
+def cpu_baseline_tiles(rgb, W, H, p, lay, n_single: int = 8):
+    """The oracle on sampled tiles of the slide, each an independent image
+    over its core plus halo as in the launch: single-threaded over n_single
+    tiles spread over the slide (the first and last tile, the rest evenly
+    between them), as a slide rate of core pixels per second (the slide
+    takes 768 / n_single times their time); and one distinct tile per core
+    the box grants (at most 16) in independent processes, as a multi-core
+    host rate.  Generation and copies are outside the timed regions."""
+    import multiprocessing as mp
+    import numpy as np
+    import oracle
+    oracle.build()
+
+    def tile_case(i):
+        t = lay[i]
+        ex0, ey0, ex1, ey1 = t["ext"]
+        cx0, cy0, cx1, cy1 = t["core"]
+        sub = np.ascontiguousarray(rgb[ey0:ey1, ex0:ex1].cpu().numpy())
+        return sub, dict(p, K=0, gx=t["gx"], gy=t["gy"]), (cx1 - cx0) * (cy1 - cy0)
+
+    idx = sorted({int(round(x)) for x in np.linspace(0, len(lay) - 1, n_single)})
+    cases = [tile_case(i) for i in idx]
+    t0 = time.perf_counter()
+    for sub, pt, _ in cases:
+        oracle.segment(sub, pt)
+    dt = time.perf_counter() - t0
+    core = sum(c[2] for c in cases)
+    ext = sum(c[0].shape[0] * c[0].shape[1] for c in cases)
+    out = {"value": round(core / dt / 1e6, 4), "unit": "MPixel/s", "cores": 1, "kind": "oracle",
+           "sample": "%d of the %d tiles (indices %s; %.1f MPixel of core, %.1f with halos), single-threaded, "
+                     "%.1f s; the whole slide would take %.0f s at this rate"
+                     % (len(idx), len(lay), idx, core / 1e6, ext / 1e6, dt, dt * W * H / core),
+           "host_cpu": host_cpu()}
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    midx = sorted({int(round(x)) for x in np.linspace(1, len(lay) - 2, cores)})
+    mcases = [tile_case(i) for i in midx]
+    ctx = mp.get_context("spawn")
+    barrier, results = ctx.Barrier(len(mcases)), ctx.Queue()
+    procs = [ctx.Process(target=_oracle_tile_worker, args=(sub, pt, barrier, results)) for sub, pt, _ in mcases]
+    for pr in procs:
+        pr.start()
+    got = [results.get(timeout=900) for _ in procs]
+    for pr in procs:
+        pr.join()
+    wall = max(g[1] for g in got) - min(g[0] for g in got)
+    mcore = sum(c[2] for c in mcases)
+    out["multicore"] = {"value": round(mcore / wall / 1e6, 4), "unit": "MPixel/s", "cores": len(mcases),
+                        "kind": "oracle",
+                        "sample": "%d distinct tiles (%.1f MPixel of core), one per process, %.1f s"
+                                  % (len(mcases), mcore / 1e6, wall)}
+    return out
+
+
+def timed_steps(ctx, step, args):
+    """W untimed warm-up steps (plus one untimed call that tunes the launch
+    shape when the autotuner is on and W = 0), then K steps back to back
+    (launches queue while the GPU works) between two synchronisations.
+    Returns the wall time per step, the refinement kernel's duration in each
+    of the K timed steps (HIP events the library records on its stream, read
+    after the timed region), and whether a tuning call was added."""
+    import torch
+    tune_call = args.warmup == 0 and not args.no_autotune
+    for _ in range(args.warmup + (1 if tune_call else 0)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    return dt, ctx.timing_history(args.steps), tune_call
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batch", choices=["batch", "single256", "he4096", "he8192", "slide", "slide65k",
-                                                             "roi"])
+    ap.add_argument("--workload", default="slide65k", choices=["batch", "single256", "he4096", "he8192", "slide",
+                                                                "slide65k", "roi"])
     ap.add_argument("--gated", action="store_true",
-                    help="H&E workloads: also train the gate and time the gated path")
+                    help="he4096 and slide: also train the gate and time the gated path (slide65k: always)")
+    ap.add_argument("--no-gated", action="store_true", help="slide65k: the plain path only")
     ap.add_argument("--gate-rule", default="both", choices=["either", "both"])
     ap.add_argument("--save-gate", default=None, help="write the trained gate network to this .npz file")
     ap.add_argument("--gate-level", type=int, default=3, choices=[1, 2, 3],
@@ -217,6 +332,8 @@ def main():
                     help="only run a plain 1 GiB device copy three times (scales the HBM "
                          "byte counters of rocprofv3 --pmc)")
     args = ap.parse_args()
+    if args.steps < 1 or args.warmup < 0:
+        raise SystemExit("--steps must be >= 1 and --warmup >= 0")
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the refinement path runs on a single MI355X "
@@ -268,23 +385,9 @@ def main():
         else:
             ctx.segment_batch(rgbs, p, labels=labels, report=False)
 
-    # with the autotuner on, the first call of a shape tunes: never timed
-    for _ in range(max(args.warmup, 0 if args.no_autotune else 1)):
-        step()
-    torch.cuda.synchronize()
-    # the timed steps run back to back (launches queue while the GPU works)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    dt, refine_ms, tune_call = timed_steps(ctx, step, args)
+    dt *= args.steps
     print("bench: timed %d steps in %.3f s" % (args.steps, dt), file=sys.stderr, flush=True)
-    # kernel durations (HIP events on the library's stream) from the same
-    # steps once more: reading them waits for each step
-    refine_ms = []
-    for _ in range(args.steps):
-        step()
-        refine_ms.append(ctx.last_timings()["refine_ms"])
     tm = ctx.last_timings()
     shape = {"threads": tm["threads"], "stats_lds": tm["stats_lds"], "pyramid_in_launch": tm["pyramid"],
              "workgroups_per_image": tm["workgroups"], "autotuned": not args.no_autotune}
@@ -300,6 +403,7 @@ def main():
     ms_step = dt * 1e3 / args.steps
     avg_refine = sum(refine_ms) / len(refine_ms)
     alg = refine_alg_bytes(imgs, reps)
+    alg_w = refine_alg_bytes(imgs, reps, stage_bytes_window)
     achieved = alg / (avg_refine * 1e-3) / 1e9
     src_hash = kernel_source_hash()
     traffic = profile_traffic(kname, args.workload + ("_merge" if args.merge else ""), src_hash)
@@ -328,9 +432,13 @@ def main():
             "traffic": traffic,
             "alg_bytes_per_launch": alg,
             "avg_launch_ms": round(avg_refine, 4),
+            "launches_timed": len(refine_ms),
+            "window_model": {"alg_bytes_per_launch": alg_w,
+                             "frac": round(alg_w / (avg_refine * 1e-3) / 1e9 / HBM_PEAK_GBS, 6)},
             "source_hash": src_hash,
         },
         "launch_shape": shape,
+        "autotune_call": tune_call,
     }
     if args.merge:
         # what the merges did: superpixels merged away, and how many of the
@@ -383,75 +491,104 @@ def train_gate(ctx, rule: str, n_tiles: int, seed: int = 0, gate_level: int = 3,
                "train_s": round(time.perf_counter() - t0, 3)}
 
 
+def roofline(kname, alg, alg_w, launch_ms, traffic=None):
+    """Roofline of the refinement kernel: algorithmic bytes per launch over
+    its mean HIP-event duration against the HBM peak; the window model's
+    figures beside it."""
+    avg = sum(launch_ms) / len(launch_ms)
+    achieved = alg / (avg * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic, "alg_bytes_per_launch": alg,
+            "avg_launch_ms": round(avg, 4), "launches_timed": len(launch_ms),
+            "window_model": {"alg_bytes_per_launch": alg_w,
+                             "frac": round(alg_w / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 6)}}
+
+
 def bench_gated(args, ctx, rgb, labels, plain, W, H, dt_plain):
-    """The learned gate on the same image: the gated schedule (the plain
-    one with the single-pixel stage as its own, gated level), thresholds
-    from 'nothing refined past the gate point' to 'everything', and the one
-    calibrated on held-out tiles for boundary recall >= 0.99."""
+    """The learned gate on the same image or slide: the gated schedule (the
+    plain one with the single-pixel stage as its own, gated level), at the
+    thresholds calibrated on held-out tiles for boundary recall >= 0.99 and
+    >= 0.995 against the plain labels, beside the two references without a
+    network decision: nothing refined past the gate point (the schedule
+    stopped before the gated stage) and everything refined (the gate's
+    overhead)."""
     import torch
     from paper_1704_02083_amd import gate, metrics, params, rapid, synth_gpu
     w, info = train_gate(ctx, args.gate_rule, args.train_tiles, gate_level=args.gate_level, save=args.save_gate)
     print("bench: gate trained (%s)" % info, file=sys.stderr, flush=True)
-    if args.workload in ("slide", "slide65k"):
+    slide = args.workload in ("slide", "slide65k")
+    if slide:
         pg = params.gated(2048, 2048, 4096, rule=args.gate_rule, gate_level=args.gate_level)
         lay = rapid.tile_layout(W, H, 2048, 64, 32)
 
-        def run(th, report=False):
-            _, reps = ctx.segment_slide(rgb, pg, tile=2048, halo=64, cell=32, labels=labels, w_bf16=w, thresh=th,
-                                        report=report)
-            return tiles_alg_bytes(W, H, lay, reps) if report else None
+        def run(th):
+            ctx.segment_slide(rgb, pg, tile=2048, halo=64, cell=32, labels=labels, w_bf16=w, thresh=th)
+
+        def report_run(th):
+            _, reps, _, g = ctx.segment_slide(rgb, pg, tile=2048, halo=64, cell=32, labels=labels, w_bf16=w,
+                                              thresh=th, report=True, features=True)
+            return tiles_alg_bytes(W, H, lay, reps), tiles_alg_bytes(W, H, lay, reps, stage_bytes_window), g
     else:
         pg = params.gated(W, H, 16384, rule=args.gate_rule, gate_level=args.gate_level)
 
-        def run(th, report=False):
-            _, reps, _, _ = ctx.segment_gated([rgb], pg, w, th, labels=[labels], report=report)
-            return refine_alg_bytes([rgb], reps) if report else None
+        def run(th):
+            ctx.segment_gated([rgb], pg, w, th, labels=[labels], report=False)
+
+        def report_run(th):
+            _, reps, _, g = ctx.segment_gated([rgb], pg, w, th, labels=[labels], report=True)
+            return refine_alg_bytes([rgb], reps), refine_alg_bytes([rgb], reps, stage_bytes_window), g
     hold = [synth_gpu.he_slide(2048, 2048, seed=7100 + i, background=0.4, device="cuda") for i in range(4)]
-    crops = [(0, 0)] if args.workload == "he4096" else [(1000, 3000), (9000, 17000), (20000, 7000), (28000, 28000)]
+    crops = [(0, 0)] if not slide else [(1000, 3000), (9000, 17000), (20000, 7000), (28000, 28000)]
+    measured = {}
 
     def point(th):
-        alg = run(th, report=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(3):
-            run(th)
-        torch.cuda.synchronize()
-        dtg = (time.perf_counter() - t0) / 3
-        kms = []
-        for _ in range(3):
-            run(th)
-            kms.append(ctx.last_timings()["refine_ms"])
-        achieved = alg / (sum(kms) / len(kms) * 1e-3) / 1e9
+        if th in measured:
+            return dict(measured[th])
+        alg, alg_w, g = report_run(th)
+        marked = float(g.to(torch.float32).mean().item())
+        dt, ms, _ = timed_steps(ctx, lambda: run(th), args)
         ue = [metrics.undersegmentation_error(plain[y:y + 4096, x:x + 4096].cpu().numpy(),
                                               labels[y:y + 4096, x:x + 4096].cpu().numpy()) for y, x in crops]
-        return {"thresh": th, "MPixel/s": round(W * H / dtg / 1e6, 3), "ms": round(dtg * 1e3, 3),
-                "speedup": round(dt_plain / dtg, 4),
-                "k_refine_ms": round(sum(kms) / len(kms), 3), "alg_bytes_per_launch": alg,
-                "achieved_GBps": round(achieved, 3), "hbm_frac": round(achieved / HBM_PEAK_GBS, 6),
-                "br": round(gate.boundary_recall(ctx, plain, labels), 6),
-                "disagreement": round(float((plain != labels).float().mean().item()), 6),
-                "ue": round(float(sum(ue) / len(ue)), 6)}
+        kname = "k_refine" if slide else "gated launches"
+        r = {"thresh": th, "MPixel/s": round(W * H / dt / 1e6, 3), "ms_per_step": round(dt * 1e3, 3),
+             "speedup": round(dt_plain / dt, 4), "marked": round(marked, 6),
+             "br": round(gate.boundary_recall(ctx, plain, labels), 6),
+             "disagreement": round(float((plain != labels).float().mean().item()), 6),
+             "ue": round(float(sum(ue) / len(ue)), 6),
+             "roofline": roofline(kname, alg, alg_w, ms)}
+        measured[th] = r
+        print("bench: gated point thresh %g: %.1f MPixel/s, BR %.4f, marked %.4f"
+              % (th, r["MPixel/s"], r["br"], marked), file=sys.stderr, flush=True)
+        return dict(r)
 
-    curve = [point(th) for th in (1e9, 2.0, 1.0, 0.0, -1e9)]
     res = {"train": info, "rule": args.gate_rule,
            "schedule": "16 | 8,4 | 2 | 1, gate from level %d (%s)" % (
                args.gate_level, {3: "the 1-px stage", 2: "the 2-px and 1-px stages",
                                  1: "every stage after the 16-px one"}[args.gate_level]),
-           "curve": curve,
-           "note": "thresh 1e9 refines nothing past the gate point, -1e9 everything; br and disagreement "
-                   "over the whole image against the plain labels, ue on %d 4096x4096 crops" % len(crops)}
-    # thresholds calibrated on the held-out tiles: the largest (fewest
-    # superpixels refined) that keeps their mean boundary recall at 0.99, and
-    # at the stricter 0.995 where refining nothing is no longer enough
-    res["calibrated"] = []
+           "points": [], "references": []}
     for target in (0.99, 0.995):
         cal = gate.calibrate(ctx, hold, params.gated(2048, 2048, 4096, rule=args.gate_rule,
                                                      gate_level=args.gate_level), w, target,
                              candidates=[1e9, 4.0, 3.0, 2.0, 1.5, 1.0, 0.5, 0.0, -0.5, -1.0, -2.0, -1e9])
-        if cal is not None:
-            c = point(cal[0])
-            c["held_out"] = {k: round(v, 6) for k, v in cal[1].items()}
-            res["calibrated"].append(dict(c, target_br=target))
+        if cal is None:
+            res["points"].append({"target_br": target, "calibrated": None})
+            continue
+        c = point(cal[0])
+        c["target_br"] = target
+        c["held_out"] = {k: round(v, 6) for k, v in cal[1].items()}
+        # a threshold above every logit marks nothing: the target is then met
+        # by stopping before the gated stage, with no decision of the network
+        c["attribution"] = ("no network decision: nothing marked, the speedup is that of stopping before the "
+                            "gated stage" if c["held_out"]["marked"] == 0.0 else
+                            "network: the marked superpixels refine in the gated stage")
+        res["points"].append(c)
+    for name, th in (("nothing refined past the gate", 1e9), ("everything refined (gate overhead)", -1e9)):
+        r = point(th)
+        r["name"] = name
+        res["references"].append(r)
+    res["note"] = ("br and disagreement over the whole image against the plain labels, ue on %d 4096x4096 crops; "
+                   "marked = share of superpixels whose gate bit is set; each point timed over the same warm-up "
+                   "and step counts as the plain path" % len(crops))
     return res
 
 
@@ -484,14 +621,15 @@ def bench_roi(args):
     labs_g = [torch.empty((2048, 2048), dtype=torch.int32, device="cuda") for _ in rgbs]
     print("bench: roi classifier trained (accuracy %.4f)" % train_acc, file=sys.stderr, flush=True)
 
-    def timed(fn, steps=5):
-        fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
+    def timed(fn):
+        for _ in range(args.warmup):
             fn()
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps
 
     dt_p = timed(lambda: ctx.segment_batch(rgbs, p, labels=labs_p, report=False))
     holder = {}
@@ -514,8 +652,8 @@ def bench_roi(args):
         return round(sum(r[k] for r in rows) / len(rows), 5)
 
     out = {
-        "metric": METRIC, "value": round(pixels / dt_p / 1e6, 3), "unit": "MPixel/s", "n_gpus": 1, "steps": 5,
-        "warmup": 1, "ms_per_step": round(dt_p * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": round(pixels / dt_p / 1e6, 3), "unit": "MPixel/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt_p * 1e3, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": "16 RGB uint8 2048x2048 synthetic H&E tiles (40% background) in one launch, "
                                "K=4096 each, three levels 16|8,4|2,1; region of interest = tissue",
@@ -537,11 +675,15 @@ def bench_roi(args):
 
 
 def bench_he(args):
-    """H&E workloads: one 4096^2 image or a 32768^2 slide; plain, and gated
-    when asked."""
+    """H&E workloads: the 65536 x 49152 slide (default), the 32768^2 slide,
+    or one 4096^2 or 8192^2 image; plain, and gated (the 65536 x 49152 slide
+    unless --no-gated; the 4096^2 image and the 32768^2 slide with
+    --gated)."""
     import torch
-    from paper_1704_02083_amd import metrics, rapid, synth_gpu
+    from paper_1704_02083_amd import rapid, synth_gpu
     _, p, desc = workload(args.workload)
+    slide = args.workload in ("slide", "slide65k")
+    gated = args.gated or (args.workload == "slide65k" and not args.no_gated and args.grain == 1)
     if args.grain > 1:
         # drop the stages finer than the grain (levels keep their factor)
         lv = [(f, [b for b in st if b * f >= args.grain]) for f, st in p["levels"]]
@@ -549,46 +691,29 @@ def bench_he(args):
         desc += ", grain %d (stages of effective block size >= %d only)" % (args.grain, args.grain)
         if args.gated:
             raise SystemExit("--grain applies to the plain path only")
+    if gated and args.workload == "he8192":
+        raise SystemExit("--gated applies to he4096, slide and slide65k")
     ctx = rapid.Context(0, timing=True, autotune=not args.no_autotune)
-    if args.workload in ("slide", "slide65k"):
+    if slide:
         W, H, seed = (32768, 32768, 4) if args.workload == "slide" else (65536, 49152, 5)
         rgb = synth_gpu.he_slide(W, H, seed=seed, background=0.4, device="cuda", band=1024)
         labels = torch.empty((H, W), dtype=torch.int32, device="cuda")
+        lay = rapid.tile_layout(W, H, 2048, 64, 32)
 
-        def run(w=None, th=0.0):
-            ctx.segment_slide(rgb, p, tile=2048, halo=64, cell=32, labels=labels, w_bf16=w, thresh=th)
+        def run():
+            ctx.segment_slide(rgb, p, tile=2048, halo=64, cell=32, labels=labels)
     else:
-        if args.gated and args.workload != "he4096":
-            raise SystemExit("--gated applies to he4096, slide and slide65k")
         W = H = 8192 if args.workload == "he8192" else 4096
         rgb = synth_gpu.he_slide(W, H, seed=3, background=0.3, device="cuda")
         labels = torch.empty((H, W), dtype=torch.int32, device="cuda")
 
-        def run(w=None, th=0.0):
-            if w is None:
-                ctx.segment(rgb, p, labels=labels, report=False)
-            else:
-                ctx.segment_gated([rgb], p, w, th, labels=[labels], report=False)
+        def run():
+            ctx.segment(rgb, p, labels=labels, report=False)
     torch.cuda.synchronize()
     print("bench: %s generated" % args.workload, file=sys.stderr, flush=True)
 
-    def timed(fn, steps, warm):
-        for _ in range(warm):
-            fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            fn()
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
-        ref_ms = []
-        for _ in range(steps):
-            fn()
-            ref_ms.append(ctx.last_timings()["refine_ms"])
-        return dt, ref_ms
-
-    steps, warm = max(1, min(args.steps, 5)), max(0 if args.no_autotune else 1, min(args.warmup, 2))
-    dt, ref_ms = timed(lambda: run(), steps, warm)
+    dt, ref_ms, tune_call = timed_steps(ctx, run, args)
+    print("bench: plain, %d steps of %.3f ms" % (args.steps, dt * 1e3), file=sys.stderr, flush=True)
     tm = ctx.last_timings()
     shape = {"threads": tm["threads"], "stats_lds": tm["stats_lds"], "pyramid_in_launch": tm["pyramid"],
              "workgroups_per_image": tm["workgroups"], "autotuned": not args.no_autotune}
@@ -596,33 +721,35 @@ def bench_he(args):
     kname = "k_refine_mc" if tm["workgroups"] > 1 else "k_refine"
     plain = labels.clone()
     # per-stage counters of the same deterministic work, from one untimed call
-    if args.workload in ("slide", "slide65k"):
+    if slide:
         _, reps = ctx.segment_slide(rgb, p, tile=2048, halo=64, cell=32, labels=labels, report=True)
-        alg = tiles_alg_bytes(W, H, rapid.tile_layout(W, H, 2048, 64, 32), reps)
+        alg, alg_w = tiles_alg_bytes(W, H, lay, reps), tiles_alg_bytes(W, H, lay, reps, stage_bytes_window)
     else:
         _, r = ctx.segment(rgb, p, labels=labels, report=True)
-        alg = refine_alg_bytes([rgb], [r])
-    avg_refine = sum(ref_ms) / len(ref_ms)
-    achieved = alg / (avg_refine * 1e-3) / 1e9
+        alg, alg_w = refine_alg_bytes([rgb], [r]), refine_alg_bytes([rgb], [r], stage_bytes_window)
+    traffic = profile_traffic(kname, args.workload + ("_grain%d" % args.grain if args.grain > 1 else ""),
+                              kernel_source_hash())
     out = {
         "metric": METRIC, "value": round(W * H / dt / 1e6, 3), "unit": "MPixel/s", "n_gpus": 1,
-        "steps": steps, "warmup": warm, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": desc, "pixels": W * H, "path": "plain"},
-        "roofline": {"bound": "hbm", "kernel": kname, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "avg_launch_ms": round(avg_refine, 3), "achieved": round(achieved, 3),
-                     "frac": round(achieved / HBM_PEAK_GBS, 6),
-                     "traffic": profile_traffic(kname, args.workload + ("_grain%d" % args.grain if args.grain > 1
-                                                                      else ""), kernel_source_hash()),
-                     "alg_bytes_per_launch": alg},
+        "roofline": roofline(kname, alg, alg_w, ref_ms, traffic),
         "launch_shape": shape,
+        "autotune_call": tune_call,
     }
-    if args.gated:
+    if gated:
         out["gated"] = bench_gated(args, ctx, rgb, labels, plain, W, H, dt)
     if args.reuse_baseline:
         if args.workload != "he4096":
             raise SystemExit("--reuse-baseline applies to he4096")
         out["reuse"] = bench_reuse(ctx, rgb, p, plain)
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
+        if slide:
+            out["cpu_baseline"] = cpu_baseline_tiles(rgb, W, H, p, lay)
+        else:
+            out["cpu_baseline"] = cpu_baseline([rgb.cpu().numpy()], p, 1)
     ctx.close()
     print(json.dumps(out), flush=True)
 

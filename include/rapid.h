@@ -54,6 +54,12 @@ typedef struct rapid_state rapid_state;   /* opaque, library-owned */
 
 #define RAPID_CFG_TIMING 1   /* record HIP events around every kernel launch */
 #define RAPID_CFG_AUTOTUNE 2 /* tune the launch shape per problem shape (below) */
+/* Test hook: every cooperative launch (one image on many workgroups) that
+ * refines at least one stage starts with its abort word raised, so that every workgroup leaves the kernel at
+ * its first grid barrier, as when a barrier's bounded wait gives up.  Such
+ * a launch makes its call return RAPID_EDEVICE (a level-by-level state then
+ * stays at the level it had); the autotuner drops such candidates. */
+#define RAPID_CFG_TEST_ABORT 4
 
 /* rapid_params.gate_rule values */
 #define RAPID_GATE_EITHER 0
@@ -252,6 +258,15 @@ rapid_status rapid_state_import(rapid_ctx *ctx, rapid_state *st, int32_t next_le
  * RAPID_ESTATE when the context does not time or nothing ran yet. */
 rapid_status rapid_last_timings(rapid_ctx *ctx, rapid_timings *out);
 
+/* The refinement kernel durations (rapid_timings.refine_ms) of the last
+ * min(max_n, 128, timed calls so far) segmentation calls of a timing
+ * context, oldest first, into refine_ms (max_n floats); *n_out receives
+ * their number.  Each timed call records its HIP events in the next slot of
+ * a ring of 128, so calls queued back to back need one synchronisation
+ * (this call waits for the last).  RAPID_ESTATE when the context does not
+ * time or nothing ran yet. */
+rapid_status rapid_timing_history(rapid_ctx *ctx, float *refine_ms, int32_t max_n, int32_t *n_out);
+
 /* ---------------------------------------------------------------- gate
  * The prediction step of Algorithm RAPID: at the start of the gate level
  * every superpixel gets a feature vector x and a classifier decides
@@ -382,6 +397,19 @@ rapid_status rapid_slide_tiles(const rapid_slide *slide, int32_t *n_tiles);
  * order row-major. */
 rapid_status rapid_segment_slide(rapid_ctx *ctx, const rapid_slide *slide, const rapid_params *params,
                                  const rapid_gate_model *model, rapid_report *reports);
+
+/* A slide under the prediction step (Algorithm RAPID's gate, Eqs. (6)-(7)),
+ * as rapid_segment_slide with a model, one launch over all tiles, each tile
+ * deciding the gate bits of its own superpixels inside the launch.
+ * features_dev (nullable) receives the 16 features of every tile's
+ * superpixels, tile after tile in row-major tile order (the sum over tiles
+ * of gx*gy rows of 16 float32; a tile's rows in its own label order);
+ * gate_dev (nullable) the gate bytes in the same order.  model must not be
+ * NULL; a model with non-finite weights is refused as in
+ * rapid_segment_gated (the slide is segmented plain, RAPID_EGATE). */
+rapid_status rapid_segment_slide_gated(rapid_ctx *ctx, const rapid_slide *slide, const rapid_params *params,
+                                       const rapid_gate_model *model, float *features_dev, uint8_t *gate_dev,
+                                       rapid_report *reports);
 
 /* Grid of a target count (see rapid_params.K).  Host only, no device. */
 rapid_status rapid_grid(int32_t W, int32_t H, int32_t K, int32_t *gx, int32_t *gy);

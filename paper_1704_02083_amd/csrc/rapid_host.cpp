@@ -57,7 +57,15 @@ struct rapid_ctx {
     hipEvent_t jobs_copied = nullptr;
     bool timing = false;
     bool timed = false;
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    bool test_abort = false;   // RAPID_CFG_TEST_ABORT: cooperative launches start aborted
+    // timed calls use the event triples of a ring in turn, so that the
+    // kernel durations of up to TIMING_RING calls queued back to back can be
+    // read after one synchronisation; ev points at the current triple
+    static constexpr int TIMING_RING = 128;
+    hipEvent_t ring[TIMING_RING][3] = {};
+    int ring_pos = 0;
+    int64_t ring_count = 0;
+    hipEvent_t *ev = ring[0];
     float *part = nullptr;   // per-wave partial gradients of the gate network
     std::mutex mu;
 };
@@ -509,13 +517,31 @@ void cache_save(const rapid_ctx *ctx)
     std::rename(tmp.c_str(), ctx->cache_path.c_str());
 }
 
+// The next event triple of the timing ring for a timed call.
+void timing_next(rapid_ctx *ctx)
+{
+    if (ctx->ring_count > 0) ctx->ring_pos = (ctx->ring_pos + 1) % rapid_ctx::TIMING_RING;
+    ctx->ring_count++;
+    ctx->ev = ctx->ring[ctx->ring_pos];
+}
+
+// A cooperative launch whose grid barrier gave up left its workgroups
+// early, so its labels and statistics are not the method's: wait for it
+// and read its abort word (before a later launch clears it).
+rapid_status coop_status(rapid_ctx *ctx, const Job &J)
+{
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    uint32_t abort_w = 0;
+    HIPCHK(hipMemcpy(&abort_w, J.ctl + CTL_ABORT, 4, hipMemcpyDeviceToHost));
+    return abort_w ? RAPID_EDEVICE : RAPID_OK;
+}
+
 // Block sums (when the launch does not build the pyramid) and the
 // refinement launch with shape sh; jobs are on the device already.
-rapid_status launch_shape(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched &sc, int s_begin, int s_end,
-                          int flags, int32_t Kmax, int64_t nbF_max, bool gated, const LaunchShape &sh,
-                          hipEvent_t e0, hipEvent_t e1, hipEvent_t e2)
+rapid_status launch_shape(rapid_ctx *ctx, const Job *jobs, size_t n, const Job *jobs_dev, const Sched &sc,
+                          int s_begin, int s_end, int flags, int32_t Kmax, int64_t nbF_max, bool gated,
+                          const LaunchShape &sh, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2)
 {
-    const size_t n = jobs.size();
     if (e0) HIPCHK(hipEventRecord(e0, ctx->stream));
     if (flags & FLAG_INIT) {
         if (sh.pyramid) {
@@ -526,8 +552,9 @@ rapid_status launch_shape(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sc
                 const int B = sc.B[s];
                 if (B < 2) continue;
                 int64_t nb = 0;
-                for (const Job &J : jobs) nb = std::max<int64_t>(nb, (int64_t)((J.W + B - 1) / B) * ((J.H + B - 1) / B));
-                HIPCHK(launch_block_sums(ctx->jobs_dev, (int)n, s, B, nb, ctx->stream));
+                for (size_t j = 0; j < n; j++)
+                    nb = std::max<int64_t>(nb, (int64_t)((jobs[j].W + B - 1) / B) * ((jobs[j].H + B - 1) / B));
+                HIPCHK(launch_block_sums(jobs_dev, (int)n, s, B, nb, ctx->stream));
             }
         }
     }
@@ -540,15 +567,19 @@ rapid_status launch_shape(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sc
                      lp.gate_words, lp.total);
     if (sh.groups > 1) {
         // one image on many workgroups: its control words start at zero
+        // (the test hook raises the abort word of a launch that refines
+        // stages, so that every workgroup leaves at its first grid barrier)
         HIPCHK(hipMemsetAsync(jobs[0].ctl, 0, 4 * (size_t)CTL_WORDS, ctx->stream));
+        if (ctx->test_abort && s_end > s_begin)
+            HIPCHK(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(jobs[0].ctl + CTL_ABORT), 1, 1, ctx->stream));
         if (e1) HIPCHK(hipEventRecord(e1, ctx->stream));
-        HIPCHK(launch_refine_mc(ctx->jobs_dev, sh.groups, sc, s_begin, s_end, flags, ctx->lut_dev, sh.threads,
+        HIPCHK(launch_refine_mc(jobs_dev, sh.groups, sc, s_begin, s_end, flags, ctx->lut_dev, sh.threads,
                                 sh.solo, lp.gate_words, ctx->stream));
         if (e2) HIPCHK(hipEventRecord(e2, ctx->stream));
         return RAPID_OK;
     }
     if (e1) HIPCHK(hipEventRecord(e1, ctx->stream));
-    HIPCHK(launch_refine(ctx->jobs_dev, (int)n, sc, lp, s_begin, s_end, flags, ctx->lut_dev, sh.threads,
+    HIPCHK(launch_refine(jobs_dev, (int)n, sc, lp, s_begin, s_end, flags, ctx->lut_dev, sh.threads,
                          ctx->stream));
     if (e2) HIPCHK(hipEventRecord(e2, ctx->stream));
     return RAPID_OK;
@@ -664,17 +695,24 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
         best.ms = -1.0f;
         for (size_t ci = 0; ci < cand.size(); ci++) {
             LaunchShape c = cand[ci];
-            rapid_status r = launch_shape(ctx, jobs, sc, s_begin, s_end, flags, Kmax, nbF_max, gated, c,
-                                          ctx->tev[0], nullptr, ctx->tev[1]);
+            rapid_status r = launch_shape(ctx, jobs.data(), n, ctx->jobs_dev, sc, s_begin, s_end, flags, Kmax,
+                                          nbF_max, gated, c, ctx->tev[0], nullptr, ctx->tev[1]);
             if (r) return r;
             HIPCHK(hipEventSynchronize(ctx->tev[1]));
             HIPCHK(hipEventElapsedTime(&c.ms, ctx->tev[0], ctx->tev[1]));
+            // an aborted cooperative candidate is not a shape that works
+            if (c.groups > 1) {
+                r = coop_status(ctx, jobs[0]);
+                if (r == RAPID_EDEVICE) continue;
+                if (r) return r;
+            }
             if (best.ms < 0.0f || c.ms < best.ms) best = c;
             // a default one-workgroup launch more than twice as slow as the
             // best cooperative one: the other one-workgroup shapes (which
             // differ from it by far less) are not timed
             if (ci == n_coop && n_coop > 0 && c.ms > 2.0f * best.ms) break;
         }
+        if (best.ms < 0.0f) return RAPID_EDEVICE;   // every candidate aborted
         sh = best;
         ctx->tuned[key] = best;
         ctx->last_tuned = 1;
@@ -696,11 +734,16 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
     }
     sh.stats_lds = lds_residency(ctx->lds_limit, Kmax, gated, sh.stats_lds);
     ctx->last = sh;
-    rapid_status r = launch_shape(ctx, jobs, sc, s_begin, s_end, flags, Kmax, nbF_max, gated, sh,
+    if (ctx->timing) timing_next(ctx);
+    rapid_status r = launch_shape(ctx, jobs.data(), n, ctx->jobs_dev, sc, s_begin, s_end, flags, Kmax, nbF_max,
+                                  gated, sh,
                                   ctx->timing ? ctx->ev[0] : nullptr, ctx->timing ? ctx->ev[1] : nullptr,
                                   ctx->timing ? ctx->ev[2] : nullptr);
     if (r) return r;
     if (ctx->timing) ctx->timed = true;
+    // a cooperative launch returns only once it is known not to have
+    // aborted, reports asked for or not
+    if (sh.groups > 1) return coop_status(ctx, jobs[0]);
     return RAPID_OK;
 }
 
@@ -810,6 +853,7 @@ rapid_status rapid_init(const rapid_config *cfg, rapid_ctx **out)
         }
     }
     ctx->timing = (cfg->flags & RAPID_CFG_TIMING) != 0;
+    ctx->test_abort = (cfg->flags & RAPID_CFG_TEST_ABORT) != 0;
     ctx->autotune = (cfg->flags & RAPID_CFG_AUTOTUNE) != 0;
     ctx->arch = prop.gcnArchName;
     if (cfg->autotune_cache) {
@@ -817,8 +861,12 @@ rapid_status rapid_init(const rapid_config *cfg, rapid_ctx **out)
         cache_load(ctx);
     }
     if (ctx->timing)
-        for (int i = 0; i < 3; i++)
-            if (hipEventCreate(&ctx->ev[i]) != hipSuccess) { delete ctx; return RAPID_EDEVICE; }
+        for (int j = 0; j < rapid_ctx::TIMING_RING; j++)
+            for (int i = 0; i < 3; i++)
+                if (hipEventCreate(&ctx->ring[j][i]) != hipSuccess) {
+                    rapid_destroy(ctx);
+                    return RAPID_EDEVICE;
+                }
     uint32_t lut[8];
     build_simple_lut(lut);
     if (hipMalloc(&ctx->lut_dev, sizeof lut) != hipSuccess) { delete ctx; return RAPID_ENOMEM; }
@@ -843,8 +891,9 @@ void rapid_destroy(rapid_ctx *ctx)
     (void)hipFree(ctx->part);
     if (ctx->jobs_pinned) (void)hipHostFree(ctx->jobs_pinned);
     if (ctx->jobs_copied) (void)hipEventDestroy(ctx->jobs_copied);
-    for (int i = 0; i < 3; i++)
-        if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+    for (int j = 0; j < rapid_ctx::TIMING_RING; j++)
+        for (int i = 0; i < 3; i++)
+            if (ctx->ring[j][i]) (void)hipEventDestroy(ctx->ring[j][i]);
     for (int i = 0; i < 2; i++)
         if (ctx->tev[i]) (void)hipEventDestroy(ctx->tev[i]);
     delete ctx;
@@ -863,6 +912,21 @@ rapid_status rapid_last_timings(rapid_ctx *ctx, rapid_timings *out)
     out->pyramid = ctx->last.pyramid;
     out->tuned = ctx->last_tuned;
     out->workgroups = ctx->last.groups;
+    return RAPID_OK;
+}
+
+rapid_status rapid_timing_history(rapid_ctx *ctx, float *refine_ms, int32_t max_n, int32_t *n_out)
+{
+    if (!ctx || !refine_ms || max_n < 0 || !n_out) return RAPID_EINVAL;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (!ctx->timing || !ctx->timed) return RAPID_ESTATE;
+    const int64_t n = std::min<int64_t>({(int64_t)max_n, ctx->ring_count, (int64_t)rapid_ctx::TIMING_RING});
+    HIPCHK(hipEventSynchronize(ctx->ev[2]));
+    for (int64_t i = 0; i < n; i++) {
+        const int slot = (int)((ctx->ring_pos - (n - 1 - i) + rapid_ctx::TIMING_RING) % rapid_ctx::TIMING_RING);
+        HIPCHK(hipEventElapsedTime(&refine_ms[i], ctx->ring[slot][1], ctx->ring[slot][2]));
+    }
+    *n_out = (int32_t)n;
     return RAPID_OK;
 }
 
@@ -1130,8 +1194,9 @@ rapid_status rapid_slide_tiles(const rapid_slide *sl, int32_t *n_tiles)
     return RAPID_OK;
 }
 
-rapid_status rapid_segment_slide(rapid_ctx *ctx, const rapid_slide *sl, const rapid_params *params,
-                                 const rapid_gate_model *model, rapid_report *reports)
+static rapid_status slide_impl(rapid_ctx *ctx, const rapid_slide *sl, const rapid_params *params,
+                               const rapid_gate_model *model, float *features_dev, uint8_t *gate_dev,
+                               rapid_report *reports)
 {
     int32_t nt;
     rapid_status r = rapid_slide_tiles(sl, &nt);
@@ -1170,8 +1235,22 @@ rapid_status rapid_segment_slide(rapid_ctx *ctx, const rapid_slide *sl, const ra
         ti.gid_y0 = ey0 / c;
         ti.gid_w = gid_w;
     }
-    if (model) return gated_impl(ctx, imgs.data(), nt, params, model, nullptr, nullptr, reports, info.data());
+    if (model) return gated_impl(ctx, imgs.data(), nt, params, model, features_dev, gate_dev, reports, info.data());
     return segment_impl(ctx, imgs.data(), nt, params, nullptr, reports, info.data());
+}
+
+rapid_status rapid_segment_slide(rapid_ctx *ctx, const rapid_slide *sl, const rapid_params *params,
+                                 const rapid_gate_model *model, rapid_report *reports)
+{
+    return slide_impl(ctx, sl, params, model, nullptr, nullptr, reports);
+}
+
+rapid_status rapid_segment_slide_gated(rapid_ctx *ctx, const rapid_slide *sl, const rapid_params *params,
+                                       const rapid_gate_model *model, float *features_dev, uint8_t *gate_dev,
+                                       rapid_report *reports)
+{
+    if (!model) return RAPID_EINVAL;
+    return slide_impl(ctx, sl, params, model, features_dev, gate_dev, reports);
 }
 
 rapid_status rapid_state_create(rapid_ctx *ctx, const rapid_image *img, const rapid_params *params,

@@ -33,6 +33,7 @@ class RapidError(RuntimeError):
 
 CFG_TIMING = 1
 CFG_AUTOTUNE = 2
+CFG_TEST_ABORT = 4
 
 
 class Config(C.Structure):
@@ -121,6 +122,7 @@ _lib.rapid_status_str.restype = C.c_char_p
 _lib.rapid_simple_lut.argtypes = [C.POINTER(C.c_uint32)]
 _lib.rapid_check_params.argtypes = [C.c_int32, C.c_int32, C.POINTER(Params), C.POINTER(C.c_int32)]
 _lib.rapid_last_timings.argtypes = [_P, C.POINTER(Timings)]
+_lib.rapid_timing_history.argtypes = [_P, C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]
 _lib.rapid_segment_gated.argtypes = [_P, C.POINTER(Image), C.c_int32, C.POINTER(Params),
                                      C.POINTER(GateModel), _P, _P, C.POINTER(Report)]
 _lib.rapid_state_track.argtypes = [_P, _P, _P]
@@ -135,6 +137,8 @@ _lib.rapid_gate_train.argtypes = [_P, _P, _P, C.c_int64, C.POINTER(TrainCfg), _P
 _lib.rapid_slide_tiles.argtypes = [C.POINTER(Slide), C.POINTER(C.c_int32)]
 _lib.rapid_segment_slide.argtypes = [_P, C.POINTER(Slide), C.POINTER(Params), C.POINTER(GateModel),
                                      C.POINTER(Report)]
+_lib.rapid_segment_slide_gated.argtypes = [_P, C.POINTER(Slide), C.POINTER(Params), C.POINTER(GateModel),
+                                           _P, _P, C.POINTER(Report)]
 
 EXPORTED = ["rapid_init", "rapid_destroy", "rapid_segment", "rapid_segment_batch",
             "rapid_state_create", "rapid_refine_level", "rapid_state_export",
@@ -142,7 +146,8 @@ EXPORTED = ["rapid_init", "rapid_destroy", "rapid_segment", "rapid_segment_batch
             "rapid_check_params", "rapid_last_timings", "rapid_segment_gated",
             "rapid_state_track", "rapid_state_features", "rapid_mlp_forward", "rapid_mlp_grad",
             "rapid_gate_train", "rapid_slide_tiles", "rapid_segment_slide", "rapid_boundary_miss",
-            "rapid_state_import", "rapid_gate"]
+            "rapid_state_import", "rapid_gate", "rapid_segment_slide_gated",
+            "rapid_timing_history"]
 
 
 def _check(rc: int, where: str):
@@ -244,7 +249,7 @@ class Context:
     """rapid_init / rapid_destroy around one device and stream."""
 
     def __init__(self, device: int = 0, stream=None, timing: bool = False, autotune: bool = False,
-                 autotune_cache: str | None = None):
+                 autotune_cache: str | None = None, test_abort: bool = False):
         import torch
         self.device = device
         if stream is None:
@@ -252,7 +257,8 @@ class Context:
         self.stream = stream
         self._cache = autotune_cache.encode() if autotune_cache else None
         cfg = Config(ABI_VERSION, device, C.c_void_p(stream.cuda_stream),
-                     (CFG_TIMING if timing else 0) | (CFG_AUTOTUNE if autotune else 0), 0, self._cache)
+                     (CFG_TIMING if timing else 0) | (CFG_AUTOTUNE if autotune else 0) |
+                     (CFG_TEST_ABORT if test_abort else 0), 0, self._cache)
         h = _P()
         _check(_lib.rapid_init(C.byref(cfg), C.byref(h)), "rapid_init")
         self._h = h
@@ -319,7 +325,12 @@ class Context:
 
     # rapid_segment_slide
     def segment_slide(self, rgb, params: dict, tile: int = 2048, halo: int = 64, cell: int = 32,
-                      labels=None, w_bf16=None, thresh: float = 0.0, report: bool = False):
+                      labels=None, w_bf16=None, thresh: float = 0.0, report: bool = False,
+                      features: bool = False):
+        """rapid_segment_slide (plain, or gated with w_bf16); with features
+        (gated only) rapid_segment_slide_gated, and the result gains the
+        feature rows (sum of tile K, 16) and gate bytes of every tile's
+        superpixels in tile order."""
         import torch
         H, W = int(rgb.shape[0]), int(rgb.shape[1])
         assert rgb.is_cuda and rgb.dtype == torch.uint8 and rgb.stride(1) == 3 and rgb.stride(2) == 1
@@ -331,6 +342,15 @@ class Context:
         p = make_params(dict(params, K=0, gx=1, gy=1))
         model = GateModel(w_bf16.data_ptr(), thresh) if w_bf16 is not None else None
         reps = (Report * nt)() if report else None
+        if features:
+            assert model is not None, "features come from the gated route"
+            Kt = sum(t["gx"] * t["gy"] for t in tile_layout(W, H, tile, halo, cell))
+            X = torch.empty((Kt, N_FEATURES), dtype=torch.float32, device=rgb.device)
+            g = torch.empty(Kt, dtype=torch.uint8, device=rgb.device)
+            _check(_lib.rapid_segment_slide_gated(self._h, C.byref(sl), C.byref(p), C.byref(model),
+                                                  C.c_void_p(X.data_ptr()), C.c_void_p(g.data_ptr()), reps),
+                   "rapid_segment_slide_gated")
+            return labels, ([r.stages() for r in reps] if reps is not None else None), X, g
         _check(_lib.rapid_segment_slide(self._h, C.byref(sl), C.byref(p),
                                         C.byref(model) if model is not None else None, reps),
                "rapid_segment_slide")
@@ -390,6 +410,14 @@ class Context:
         return {"block_sums_ms": float(t.block_sums_ms), "refine_ms": float(t.refine_ms),
                 "threads": int(t.threads), "stats_lds": int(t.stats_lds), "pyramid": int(t.pyramid),
                 "tuned": int(t.tuned), "workgroups": int(t.workgroups)}
+
+    def timing_history(self, n: int) -> list:
+        """rapid_timing_history: refinement kernel durations (ms) of the last
+        n timed calls (at most 128), oldest first."""
+        buf = (C.c_float * max(n, 1))()
+        got = C.c_int32()
+        _check(_lib.rapid_timing_history(self._h, buf, n, C.byref(got)), "rapid_timing_history")
+        return [float(buf[i]) for i in range(got.value)]
 
     def state(self, rgb, params: dict) -> "State":
         return State(self, rgb, params)

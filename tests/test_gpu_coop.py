@@ -364,3 +364,77 @@ def test_coop_sweep_cap_unconverged_stages(gpu_lib, max_sweeps):
             assert (got == ref).all() and rep == ref_rep, (so, max_sweeps)
         finally:
             c.close()
+
+
+def test_coop_abort_is_reported(gpu_lib, tmp_path):
+    """A cooperative launch whose grid barrier gives up (forced from the host:
+    the test hook raises the abort word before the launch, so every
+    workgroup leaves at its first grid barrier) makes rapid_segment,
+    rapid_refine_level and the gated route return RAPID_EDEVICE whether or
+    not reports are asked for; a level-by-level state stays at its level;
+    the autotuner drops the aborted candidates and keeps a one-workgroup
+    shape, whose labels are the oracle's."""
+    import torch
+    img = synth.he_tile(256, 192, seed=71)
+    p = params.default_params(256, 192, 48, levels=params.THREE_LEVEL)
+    rgb = torch.from_numpy(img).cuda()
+    with _shape(16, -1):
+        c = gpu_lib.Context(0, timing=True, test_abort=True)
+    try:
+        for rep in (True, False):
+            _say("case: forced abort, rapid_segment, report=%s" % rep)
+            with pytest.raises(gpu_lib.RapidError) as e:
+                c.segment(rgb, p, report=rep)
+            assert e.value.code == -3
+        _say("case: forced abort, level by level")
+        st = c.state(rgb, p)
+        with pytest.raises(gpu_lib.RapidError) as e:
+            st.refine_level(0, report=False)
+        assert e.value.code == -3
+        # the state did not advance: level 1 is still out of order
+        with pytest.raises(gpu_lib.RapidError) as e:
+            st.refine_level(1, report=False)
+        assert e.value.code == -4
+        st.close()
+    finally:
+        c.close()
+    # the gated route of separate launches for a large image
+    _dev, _, _, _rand_model = _gate_helpers()
+    big = synth.he_tile(1024, 1024, seed=33)
+    pg = params.default_params(1024, 1024, 4096, levels=params.THREE_LEVEL, gate_level=1)
+    _, wb = _rand_model(23)
+    with _shape(16, -1):
+        c = gpu_lib.Context(0, test_abort=True)
+    try:
+        for rep in (True, False):
+            _say("case: forced abort, gated large image, report=%s" % rep)
+            with pytest.raises(gpu_lib.RapidError) as e:
+                c.segment_gated([_dev(big)], pg, _dev(wb), 0.0, report=rep)
+            assert e.value.code == -3
+    finally:
+        c.close()
+    # the autotuner: every cooperative candidate aborts, a one-workgroup
+    # shape is chosen and its labels are the oracle's
+    ref, _, ref_rep = oracle.segment(img, p)
+    cache = str(tmp_path / "tune.json")
+    _say("case: forced abort, autotuner")
+    c = gpu_lib.Context(0, timing=True, autotune=True, autotune_cache=cache, test_abort=True)
+    try:
+        lab, rep = c.segment(rgb, p)
+        torch.cuda.synchronize()
+        t = c.last_timings()
+        assert t["tuned"] == 1 and t["workgroups"] == 1
+        assert (lab.cpu().numpy() == ref).all() and rep == ref_rep
+    finally:
+        c.close()
+    # and the same context without the hook runs the image cooperatively
+    with _shape(16, -1):
+        c = gpu_lib.Context(0, timing=True)
+    try:
+        _say("case: no abort after the forced ones")
+        lab, rep = c.segment(rgb, p)
+        torch.cuda.synchronize()
+        assert c.last_timings()["workgroups"] == 16
+        assert (lab.cpu().numpy() == ref).all() and rep == ref_rep
+    finally:
+        c.close()

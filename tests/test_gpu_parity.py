@@ -300,3 +300,29 @@ def test_int64_and_fp64_energy_paths(ctx):
     got, rep = _gpu_segment(ctx, img, p)
     ref, _, ref_rep = oracle.segment(img, p)
     _assert_same(got, rep, ref, ref_rep, "int64/fp64 paths")
+
+
+def test_timing_history_of_back_to_back_calls(gpu_lib):
+    """rapid_timing_history returns one refinement-kernel duration per timed
+    call queued back to back (oldest first), the last equal to
+    rapid_last_timings; at most the ring's 128."""
+    import torch
+    img = synth.voronoi_blur(256, 256, regions=24, seed=1)
+    p = params.config1()
+    rgb = torch.from_numpy(img).cuda()
+    c = gpu_lib.Context(0, timing=True)
+    try:
+        lab = torch.empty((256, 256), dtype=torch.int32, device="cuda")
+        for _ in range(5):
+            c.segment(rgb, p, labels=lab, report=False)
+        h = c.timing_history(8)
+        assert len(h) == 5 and all(x > 0 for x in h)
+        assert h[-1] == c.last_timings()["refine_ms"]
+        for _ in range(130):
+            c.segment(rgb, p, labels=lab, report=False)
+        h = c.timing_history(200)
+        assert len(h) == 128 and all(x > 0 for x in h)
+        ref, _, _ = oracle.segment(img, p)
+        assert (lab.cpu().numpy() == ref).all()
+    finally:
+        c.close()
