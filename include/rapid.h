@@ -223,6 +223,26 @@ rapid_status rapid_segment(rapid_ctx *ctx, const rapid_image *img, const rapid_p
 rapid_status rapid_segment_batch(rapid_ctx *ctx, const rapid_image *imgs, int32_t n,
                                  const rapid_params *params, rapid_report *reports);
 
+/* rapid_segment for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same segmentation, labels and report as rapid_segment (gate_dev: the
+ * caller's gate bits or NULL), with every byte of scratch in a fixed
+ * library-owned device array of RAPID_NOALLOC_SCRATCH_BYTES per GPU (held
+ * from the library's loading until the process ends; its address is taken
+ * once per device by rapid_init).  The call itself allocates nothing: no
+ * hipMalloc, hipFree or allocating library routine.  It runs the image on
+ * one workgroup in the default launch shape (no autotuning, no cooperative
+ * launch); the image's scratch (about 25 bytes per finest block plus 150
+ * bytes per superpixel) must fit the array, else RAPID_EINVAL and nothing
+ * is queued.  Every call on one GPU uses that GPU's single array: calls that
+ * overlap on one GPU (other streams, contexts or threads) race and give
+ * undefined results; calls ordered on one stream do not.  The array keeps
+ * the last call's contents; each call initialises what it reads.  When a
+ * report is requested the call synchronises the stream. */
+#define RAPID_NOALLOC_SCRATCH_BYTES 67108864   /* 64 MiB */
+rapid_status rapid_segment_noalloc(rapid_ctx *ctx, const rapid_image *img, const rapid_params *params,
+                                   const uint8_t *gate_dev, rapid_report *report);
+
 /* Level-by-level use (the outer loop of Algorithm RAPID).  state_create
  * computes the grid labels and the statistics once (first level, Sec. 3.2);
  * each rapid_refine_level call runs every stage of one level, in order

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librapid.so")
-SOURCES = ["rapid_kernels.hip", "rapid_gate.hip", "rapid_state.hip", "rapid_host.cpp"]
+SOURCES = ["rapid_kernels.hip", "rapid_gate.hip", "rapid_state.hip", "rapid_noalloc.hip", "rapid_host.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

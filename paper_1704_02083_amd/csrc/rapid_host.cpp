@@ -67,6 +67,7 @@ struct rapid_ctx {
     int64_t ring_count = 0;
     hipEvent_t *ev = ring[0];
     float *part = nullptr;   // per-wave partial gradients of the gate network
+    char *scratch = nullptr; // this device's copy of the fixed scratch (rapid_segment_noalloc)
     std::mutex mu;
 };
 
@@ -876,6 +877,9 @@ rapid_status rapid_init(const rapid_config *cfg, rapid_ctx **out)
         delete ctx;
         return RAPID_EDEVICE;
     }
+    // the fixed scratch of rapid_segment_noalloc on this device (its address
+    // only; a failed lookup leaves that entry point unusable, not the others)
+    if (noalloc_scratch(ctx->device, &ctx->scratch) != hipSuccess) ctx->scratch = nullptr;
     *out = ctx;
     return RAPID_OK;
 }
@@ -1096,6 +1100,57 @@ rapid_status rapid_segment_batch(rapid_ctx *ctx, const rapid_image *imgs, int32_
                                  const rapid_params *params, rapid_report *reports)
 {
     return segment_impl(ctx, imgs, n, params, nullptr, reports);
+}
+
+rapid_status rapid_segment_noalloc(rapid_ctx *ctx, const rapid_image *img, const rapid_params *params,
+                                   const uint8_t *gate_dev, rapid_report *report)
+{
+    if (!ctx || !img || !params) return RAPID_EINVAL;
+    rapid_status r;
+    if ((r = check_image(img, true))) return r;
+    Sched sc;
+    if ((r = make_sched(params, &sc, nullptr))) return r;
+    if (!gate_dev) sc.gate_stage = sc.n_stages;
+    int32_t gx, gy;
+    if ((r = image_grid(img, params, sc, &gx, &gy))) return r;
+    const int32_t K = gx * gy;
+    const bool gated = gate_dev != nullptr && sc.gate_stage < sc.n_stages;
+    if (gated && ((int64_t)K + 31) / 32 > MAX_GATE_WORDS) return RAPID_EINVAL;
+    const Layout L = plan(img->W, img->H, K, sc);
+    if (L.bytes > NOALLOC_SCRATCH_BYTES - NOALLOC_JOB_BYTES) return RAPID_EINVAL;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (!ctx->scratch) return RAPID_EDEVICE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return RAPID_EDEVICE;
+    Job J;
+    fill_job(J, ctx->scratch + NOALLOC_JOB_BYTES, L, img, gx, gy, gate_dev);
+    if (sc.B[sc.n_stages - 1] == 1 && img->label_stride == img->W) J.lab[(sc.n_stages - 1) & 1] = img->labels_dev;
+    set_exactness(sc, img->W, img->H);
+    Job *jd = reinterpret_cast<Job *>(ctx->scratch);
+    HIPCHK(launch_store_job(J, jd, ctx->stream));
+    // the default one-workgroup shape; the block sums in their own launches
+    LaunchShape sh;
+    sh.threads = ctx->threads;
+    sh.stats_lds = lds_residency(ctx->lds_limit, K, gated, 1);
+    sh.pyramid = 0;
+    sh.groups = 1;
+    const int Bf = sc.B[sc.n_stages - 1];
+    const int64_t nbF = (int64_t)((img->W + Bf - 1) / Bf) * ((img->H + Bf - 1) / Bf);
+    ctx->last = sh;
+    ctx->last_tuned = 0;
+    if (ctx->timing) timing_next(ctx);
+    if ((r = launch_shape(ctx, &J, 1, jd, sc, 0, sc.n_stages, FLAG_INIT | FLAG_OUT, K, nbF, gated, sh,
+                          ctx->timing ? ctx->ev[0] : nullptr, ctx->timing ? ctx->ev[1] : nullptr,
+                          ctx->timing ? ctx->ev[2] : nullptr)))
+        return r;
+    if (ctx->timing) ctx->timed = true;
+    if (report) {
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        std::memset(report, 0, sizeof *report);
+        report->K = K;
+        report->n_stages = sc.n_stages;
+        HIPCHK(hipMemcpy(report->stage, J.rep, sizeof(rapid_stage_report) * sc.n_stages, hipMemcpyDeviceToHost));
+    }
+    return RAPID_OK;
 }
 
 static rapid_status gated_impl(rapid_ctx *ctx, const rapid_image *imgs, int32_t n,

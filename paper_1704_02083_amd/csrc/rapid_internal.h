@@ -122,6 +122,16 @@ enum { CTL_BAR = 0, CTL_ABORT = 32, CTL_CNT = 64, CTL_NPROP = 96, CTL_NCHG = 98,
 // merge on underflow: neighbour slots per asker
 constexpr int MERGE_NB = 8;
 
+// rapid_segment_noalloc: the fixed device scratch per GPU, the job record in
+// its first NOALLOC_JOB_BYTES, the image's scratch layout after it.
+// noalloc_scratch: the calling thread's current device's copy (taken once
+// per device); launch_store_job: writes a job record on the stream.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)RAPID_NOALLOC_SCRATCH_BYTES;
+constexpr size_t NOALLOC_JOB_BYTES = 4096;
+static_assert(sizeof(Job) <= NOALLOC_JOB_BYTES, "job record must fit its slot");
+hipError_t noalloc_scratch(int device, char **out);
+hipError_t launch_store_job(const Job &j, Job *dst, hipStream_t stream);
+
 hipError_t launch_block_sums(const Job *jobs_dev, int n_jobs, int s, int B, int64_t max_nb, hipStream_t stream);
 hipError_t launch_expand(const int32_t *L, int W, int H, int B, int32_t *out, int64_t stride,
                          hipStream_t stream);

@@ -110,6 +110,7 @@ _lib.rapid_destroy.restype = None
 _lib.rapid_segment.argtypes = [_P, C.POINTER(Image), C.POINTER(Params), _P, C.POINTER(Report)]
 _lib.rapid_segment_batch.argtypes = [_P, C.POINTER(Image), C.c_int32, C.POINTER(Params),
                                      C.POINTER(Report)]
+_lib.rapid_segment_noalloc.argtypes = [_P, C.POINTER(Image), C.POINTER(Params), _P, C.POINTER(Report)]
 _lib.rapid_state_create.argtypes = [_P, C.POINTER(Image), C.POINTER(Params), C.POINTER(_P)]
 _lib.rapid_refine_level.argtypes = [_P, _P, C.c_int32, _P, C.POINTER(Report)]
 _lib.rapid_state_export.argtypes = [_P, _P, _P, _P]
@@ -146,7 +147,7 @@ EXPORTED = ["rapid_init", "rapid_destroy", "rapid_segment", "rapid_segment_batch
             "rapid_check_params", "rapid_last_timings", "rapid_segment_gated",
             "rapid_state_track", "rapid_state_features", "rapid_mlp_forward", "rapid_mlp_grad",
             "rapid_gate_train", "rapid_slide_tiles", "rapid_segment_slide", "rapid_boundary_miss",
-            "rapid_state_import", "rapid_gate", "rapid_segment_slide_gated",
+            "rapid_state_import", "rapid_gate", "rapid_segment_slide_gated", "rapid_segment_noalloc",
             "rapid_timing_history"]
 
 
@@ -286,6 +287,21 @@ class Context:
         g = None if gate is None else C.c_void_p(gate.data_ptr())
         _check(_lib.rapid_segment(self._h, C.byref(im), C.byref(p), g,
                                   C.byref(rep) if rep is not None else None), "rapid_segment")
+        return labels, (rep.stages() if rep is not None else None)
+
+    # rapid_segment_noalloc: as segment, with the library's fixed scratch
+    # (the caller passes the output labels to allocate nothing at all)
+    def segment_noalloc(self, rgb, params: dict, gate=None, labels=None, report: bool = True):
+        import torch
+        H, W = int(rgb.shape[0]), int(rgb.shape[1])
+        if labels is None:
+            labels = torch.empty((H, W), dtype=torch.int32, device=rgb.device)
+        im = _image(rgb, labels)
+        p = make_params(params)
+        rep = Report() if report else None
+        g = None if gate is None else C.c_void_p(gate.data_ptr())
+        _check(_lib.rapid_segment_noalloc(self._h, C.byref(im), C.byref(p), g,
+                                          C.byref(rep) if rep is not None else None), "rapid_segment_noalloc")
         return labels, (rep.stages() if rep is not None else None)
 
     # rapid_segment_batch
