@@ -61,6 +61,10 @@ typedef struct rapid_state rapid_state;   /* opaque, library-owned */
  * stays at the level it had); the autotuner drops such candidates. */
 #define RAPID_CFG_TEST_ABORT 4
 
+/* rapid_params.gate_features values */
+#define RAPID_FEATURES_LEARNED 0
+#define RAPID_FEATURES_ROI 1
+
 /* rapid_params.gate_rule values */
 #define RAPID_GATE_EITHER 0
 #define RAPID_GATE_BOTH 1
@@ -136,6 +140,25 @@ typedef struct {
  *             RAPID_GATE_DIFFER  g_a != g_k: g holds a predicted class and
  *                                only pairs across a class border refine,
  *                                as the paper's boundary superpixels.
+ *  gate_features which feature vector the prediction step computes per
+ *             superpixel (Eq. (6)):
+ *             RAPID_FEATURES_LEARNED the sixteen features of the learned
+ *                                gate (see rapid_gate_model),
+ *             RAPID_FEATURES_ROI the paper's four ROI features (Sec. 4):
+ *                                x0 absolute brightness (mean of the three
+ *                                channel means) / 255; x1 comparative
+ *                                brightness: x0 minus the mean brightness of
+ *                                the 4-adjacent superpixels weighted by the
+ *                                shared pixel edges (their fixed-point means
+ *                                / 2^F), / 255; x2 extra-region
+ *                                dissimilarity: the edge-weighted rms
+ *                                distance of its fixed-point mean colour to
+ *                                its neighbours' / (255 2^F); x3 intra-region
+ *                                dissimilarity: sqrt of the mean channel
+ *                                variance of its pixels / 64; x4..x14 zero,
+ *                                x15 = 1.  x1 and x2 are 0 without
+ *                                neighbours.  A model must be trained on the
+ *                                feature vector it is used with.
  *  merge      0: plain size bounds.  1: merge on underflow (Sec. 3.1,
  *             Eqs. (4)-(5)): a superpixel that one of its blocks could not
  *             leave without going below min_size asks to merge; when a
@@ -166,7 +189,7 @@ typedef struct {
     int32_t max_sweeps;
     int32_t gate_rule;     /* RAPID_GATE_*: which pairs a gate lets move */
     int32_t merge;         /* 1: merge on underflow */
-    int32_t reserved;      /* 0 */
+    int32_t gate_features; /* RAPID_FEATURES_*: the prediction step's features */
     int64_t min_size, max_size;
     int64_t w_col, w_pos, w_bnd;
 } rapid_params;

@@ -119,6 +119,8 @@ def lib():
         L.orc_merge_cost.restype = C.c_int64
         L.orc_features.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, P, C.c_int32, P, P,
                                    C.c_int32, C.c_int32, C.c_int32, P]
+        L.orc_roi_features.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, P, P, C.c_int32, C.c_int32,
+                                       C.c_int32, P]
     return _lib
 
 
@@ -257,6 +259,21 @@ def features(rgb: np.ndarray, labels: np.ndarray, B: int, stats: np.ndarray,
                             gx, gy, F, _ptr(out))
     if rc < 0:
         raise RuntimeError("orc_features failed rc=%d" % rc)
+    return out
+
+
+def roi_features(rgb: np.ndarray, labels: np.ndarray, stats: np.ndarray, gx: int, gy: int,
+                 F: int = 4) -> np.ndarray:
+    """The paper's four ROI features per superpixel in 16-wide rows (see
+    orc_roi_features)."""
+    rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    stats = np.ascontiguousarray(stats, dtype=np.int64)
+    H, W, _ = rgb.shape
+    out = np.empty((gx * gy, 16), np.float32)
+    rc = lib().orc_roi_features(_ptr(rgb), W, H, 3 * W, _ptr(labels), _ptr(stats), gx, gy, F, _ptr(out))
+    if rc < 0:
+        raise RuntimeError("orc_roi_features failed rc=%d" % rc)
     return out
 
 

@@ -1281,3 +1281,86 @@ int orc_features(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
     free(Q); free(bl); free(ced); free(cmax); free(cmin); free(cm);
     return ORC_OK;
 }
+
+/* The paper's four ROI features of every superpixel (Sec. 4: the feature
+ * vector F in R^4 of absolute and comparative brightness, extra-region and
+ * intra-region dissimilarity), in the 16-wide row layout of orc_features:
+ *   0  absolute brightness: the mean of the three channel means, / 255;
+ *   1  comparative brightness: that brightness minus the mean brightness of
+ *      the superpixel's neighbours, one neighbour term per 4-adjacent pixel
+ *      pair across its border, each the neighbour's three fixed-point means
+ *      (round(2^F S / n), Eq. (1)'s means as the sweep keeps them) summed and
+ *      divided by 3 2^F; / 255; 0 without neighbours;
+ *   2  extra-region dissimilarity: the rms over those pixel pairs of the
+ *      distance between the two fixed-point mean colours, / (255 2^F); 0
+ *      without neighbours;
+ *   3  intra-region dissimilarity: sqrt of the mean over the three channels
+ *      of the pixel variance within the superpixel, / 64;
+ *   4..14 zero, 15 one; a superpixel with no pixels has all 16 zero.
+ * Plain pixel loops over the label map; stats is the K x 6 statistics. */
+int orc_roi_features(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
+                     const int32_t *labels, const int64_t *stats, int32_t gx, int32_t gy, int32_t F,
+                     float *out)
+{
+    int32_t K = gx * gy;
+    int64_t *Q = calloc(3 * (int64_t)K, sizeof(int64_t));
+    int64_t *pairs = calloc(K, sizeof(int64_t)), *dist2 = calloc(K, sizeof(int64_t));
+    int64_t *nbright = calloc(K, sizeof(int64_t));
+    int64_t *cm = malloc(sizeof(int64_t) * 3 * (K > 0 ? K : 1));
+    if (!Q || !pairs || !dist2 || !nbright || !cm) {
+        free(Q); free(pairs); free(dist2); free(nbright); free(cm);
+        return ORC_ENOMEM;
+    }
+    for (int32_t k = 0; k < K; k++) {
+        const int64_t n = stats[6 * (int64_t)k];
+        for (int ch = 0; ch < 3; ch++) cm[3 * k + ch] = n ? div_round(stats[6 * (int64_t)k + 1 + ch], n, F) : 0;
+    }
+    for (int32_t y = 0; y < H; y++)
+        for (int32_t x = 0; x < W; x++) {
+            const int32_t k = labels[(int64_t)y * W + x];
+            const uint8_t *px = rgb + (int64_t)y * stride + 3 * (int64_t)x;
+            for (int ch = 0; ch < 3; ch++) Q[3 * k + ch] += (int64_t)px[ch] * px[ch];
+            /* each 4-adjacent pixel pair once: the right and the lower one */
+            for (int d = 0; d < 2; d++) {
+                const int32_t xx = x + (d == 0), yy = y + (d == 1);
+                if (xx >= W || yy >= H) continue;
+                const int32_t j = labels[(int64_t)yy * W + xx];
+                if (j == k) continue;
+                int64_t d2 = 0;
+                for (int ch = 0; ch < 3; ch++) {
+                    const int64_t df = cm[3 * k + ch] - cm[3 * j + ch];
+                    d2 += df * df;
+                }
+                pairs[k] += 1;
+                pairs[j] += 1;
+                dist2[k] += d2;
+                dist2[j] += d2;
+                nbright[k] += cm[3 * j] + cm[3 * j + 1] + cm[3 * j + 2];
+                nbright[j] += cm[3 * k] + cm[3 * k + 1] + cm[3 * k + 2];
+            }
+        }
+    for (int32_t k = 0; k < K; k++) {
+        const int64_t *r = stats + 6 * (int64_t)k;
+        float *f = out + 16 * (int64_t)k;
+        for (int i = 0; i < 16; i++) f[i] = 0.0f;
+        if (r[0] == 0) continue;
+        const double n = (double)r[0];
+        const double bright = ((double)r[1] + (double)r[2] + (double)r[3]) / (3.0 * n);
+        double var = 0.0;
+        for (int ch = 0; ch < 3; ch++) {
+            const double mean = (double)r[1 + ch] / n;
+            const double v = (double)Q[3 * k + ch] / n - mean * mean;
+            var += v > 0.0 ? v : 0.0;
+        }
+        f[0] = (float)(bright / 255.0);
+        if (pairs[k]) {
+            const double nb = (double)nbright[k] / (3.0 * (double)pairs[k] * (double)(1 << F));
+            f[1] = (float)((bright - nb) / 255.0);
+            f[2] = (float)(sqrt((double)dist2[k] / (double)pairs[k]) / (255.0 * (double)(1 << F)));
+        }
+        f[3] = (float)(sqrt(var / 3.0) / 64.0);
+        f[15] = 1.0f;
+    }
+    free(Q); free(pairs); free(dist2); free(nbright); free(cm);
+    return ORC_OK;
+}

@@ -83,6 +83,9 @@ int64_t orc_merge_cost(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
 int orc_features(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
                  const int32_t *labels, int32_t B, const int64_t *stats, const int64_t *moved,
                  int32_t gx, int32_t gy, int32_t F, float *out);
+int orc_roi_features(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
+                     const int32_t *labels, const int64_t *stats, int32_t gx, int32_t gy, int32_t F,
+                     float *out);
 int orc_propose_class(const uint8_t *rgb, int32_t W, int32_t H, int64_t stride,
                       const orc_params *p, const int32_t *labels, int32_t K,
                       int32_t B, int32_t cls, const uint8_t *gate,

@@ -45,13 +45,13 @@ __global__ void k_feat_blocks(const Job *__restrict__ jobs, int B, int lab_buf)
     }
 }
 
-__global__ void k_feat_final(const Job *__restrict__ jobs, const int64_t *__restrict__ xoff, int F,
+__global__ void k_feat_final(const Job *__restrict__ jobs, const int64_t *__restrict__ xoff, int F, int fset,
                              float *__restrict__ X)
 {
     const Job &J = jobs[blockIdx.y];
     float *Xj = X + 16 * xoff[blockIdx.y];
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < J.K; k += gridDim.x * blockDim.x)
-        feat_final_sp(J, J.stats, J.facc, J.moved, k, F, Xj + 16 * (int64_t)k);
+        feat_final_sp(J, J.stats, J.facc, J.moved, k, F, fset, Xj + 16 * (int64_t)k);
 }
 
 // ------------------------------------------------------------ MLP forward
@@ -394,14 +394,14 @@ hipError_t launch_boundary_miss(const int32_t *ref, const int32_t *test, int W, 
     return hipGetLastError();
 }
 
-hipError_t launch_features(const Job *jobs_dev, int n_jobs, int B, int lab_buf, int F, int32_t Kmax,
+hipError_t launch_features(const Job *jobs_dev, int n_jobs, int B, int lab_buf, int F, int fset, int32_t Kmax,
                            int64_t max_nb, const int64_t *xoff_dev, float *X, hipStream_t stream)
 {
     unsigned gk = (unsigned)std::max<int64_t>(1, std::min<int64_t>((Kmax + 255) / 256, 1024));
     unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_nb + 255) / 256, 4096));
     hipLaunchKernelGGL(k_feat_init, dim3(gk, n_jobs), dim3(256), 0, stream, jobs_dev, F);
     hipLaunchKernelGGL(k_feat_blocks, dim3(gb, n_jobs), dim3(256), 0, stream, jobs_dev, B, lab_buf);
-    hipLaunchKernelGGL(k_feat_final, dim3(gk, n_jobs), dim3(256), 0, stream, jobs_dev, xoff_dev, F, X);
+    hipLaunchKernelGGL(k_feat_final, dim3(gk, n_jobs), dim3(256), 0, stream, jobs_dev, xoff_dev, F, fset, X);
     return hipGetLastError();
 }
 

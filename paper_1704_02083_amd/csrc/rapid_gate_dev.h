@@ -121,6 +121,8 @@ struct FeatAcc {
     int64_t q[3];    // pixel second moments per channel
     int64_t bl;      // boundary edge length (pixel edges to other labels)
     int64_t ed2;     // sum over those edges of length x squared mean distance
+    int64_t nbs;     // sum over those edges of length x the neighbour's three
+                     // fixed-point channel means
     uint64_t mx;     // largest squared mean distance to a neighbour
     uint64_t mn;     // smallest (UINT64_MAX: none)
 };
@@ -128,7 +130,7 @@ struct FeatAcc {
 __device__ __forceinline__ void feat_zero(FeatAcc &v)
 {
     v.q[0] = v.q[1] = v.q[2] = 0;
-    v.bl = v.ed2 = 0;
+    v.bl = v.ed2 = v.nbs = 0;
     v.mx = 0;
     v.mn = ~0ull;
 }
@@ -143,6 +145,7 @@ __device__ __forceinline__ void feat_flush(int64_t *__restrict__ facc, int32_t k
     if (v.bl) {
         atomicAdd(a + 3, (unsigned long long)v.bl);
         atomicAdd(a + 4, (unsigned long long)v.ed2);
+        atomicAdd(a + 5, (unsigned long long)v.nbs);
         atomicMax(a + 6, (unsigned long long)v.mx);
         atomicMin(a + 7, (unsigned long long)v.mn);
     }
@@ -209,13 +212,15 @@ __device__ __forceinline__ void feat_segment(const Job &J, const int32_t *row, c
             const int32_t j = nbr[d];
             if (j < 0 || j == k) continue;
             const int64_t e = d < 2 ? (y1 - y0) : (x1 - x0);
-            int64_t d2 = 0;
+            int64_t d2 = 0, bj = 0;
             for (int ch = 0; ch < 3; ch++) {
                 const int64_t df = (int64_t)fmean[3 * k + ch] - fmean[3 * j + ch];
                 d2 += df * df;
+                bj += fmean[3 * j + ch];
             }
             v.bl += e;
             v.ed2 += e * d2;
+            v.nbs += e * bj;
             v.mx = (uint64_t)d2 > v.mx ? (uint64_t)d2 : v.mx;
             v.mn = (uint64_t)d2 < v.mn ? (uint64_t)d2 : v.mn;
         }
@@ -225,16 +230,23 @@ __device__ __forceinline__ void feat_segment(const Job &J, const int32_t *row, c
     if (cur >= 0) sink(cur, v);
 }
 
-// Step C for superpixel k: the sixteen features (double arithmetic without
-// contraction, so that every value is the correctly rounded result of the
-// same expression on any IEEE machine):
+// Step C for superpixel k (double arithmetic without contraction, so that
+// every value is the correctly rounded result of the same expression on any
+// IEEE machine).  fset RAPID_FEATURES_LEARNED, the sixteen features of the
+// learned gate:
 //   0-2 mean colour / 255, 3-5 colour std / 64, 6 size / A, 7 boundary
 //   length / (4 sqrt A), 8 compactness bl^2 / (16 n), 9 centroid drift from
 //   the initial cell centre / sqrt A, 10-12 max / edge-weighted rms / min
 //   neighbour contrast / (255 2^F), 13 moved pixels / n, 14 max colour std
 //   / 64, 15 one.
+// fset RAPID_FEATURES_ROI, the paper's four ROI features (Sec. 4): 0
+// absolute brightness / 255, 1 comparative brightness (own minus the
+// edge-weighted neighbour brightness) / 255, 2 extra-region dissimilarity
+// (edge-weighted rms mean-colour distance to the neighbours) / (255 2^F),
+// 3 intra-region dissimilarity (sqrt of the mean channel variance) / 64,
+// 4-14 zero, 15 one.
 __device__ __forceinline__ void feat_final_sp(const Job &J, const int64_t *st, const int64_t *facc,
-                                              const int64_t *moved, int k, int F, float *f)
+                                              const int64_t *moved, int k, int F, int fset, float *f)
 {
 #pragma clang fp contract(off)
     const double A = (double)(((int64_t)J.W * J.H) / J.K);
@@ -247,6 +259,23 @@ __device__ __forceinline__ void feat_final_sp(const Job &J, const int64_t *st, c
         return;
     }
     const double n = (double)r[0];
+    if (fset == RAPID_FEATURES_ROI) {
+        const double br = ((double)r[1] + (double)r[2] + (double)r[3]) / (3.0 * n);
+        double var = 0.0;
+        for (int ch = 0; ch < 3; ch++) {
+            const double mu = (double)r[1 + ch] / n;
+            const double v = (double)a[ch] / n - mu * mu;
+            var += v > 0.0 ? v : 0.0;
+        }
+        const double bl = (double)a[3];
+        f[0] = (float)(br / 255.0);
+        f[1] = (float)(a[3] ? (br - (double)a[5] / (3.0 * bl * (double)(1 << F))) / 255.0 : 0.0);
+        f[2] = (float)(a[3] ? sqrt((double)a[4] / bl) / cs : 0.0);
+        f[3] = (float)(sqrt(var / 3.0) / 64.0);
+        for (int i = 4; i < 15; i++) f[i] = 0.0f;
+        f[15] = 1.0f;
+        return;
+    }
     double sd[3];
     for (int ch = 0; ch < 3; ch++) {
         double mu = (double)r[1 + ch] / n;

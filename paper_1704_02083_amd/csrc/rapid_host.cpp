@@ -192,8 +192,10 @@ rapid_status make_sched(const rapid_params *p, Sched *sc, int32_t level_first[RA
     if (p->frac_bits < 0 || p->frac_bits > 4 || p->max_sweeps < 1 || p->max_sweeps > (1 << 20)) return RAPID_EINVAL;
     if (p->gate_rule < RAPID_GATE_EITHER || p->gate_rule > RAPID_GATE_DIFFER) return RAPID_EINVAL;
     sc->gate_rule = p->gate_rule;
-    if ((p->merge != 0 && p->merge != 1) || p->reserved != 0) return RAPID_EINVAL;
+    if ((p->merge != 0 && p->merge != 1)) return RAPID_EINVAL;
     sc->merge = p->merge;
+    if (p->gate_features != RAPID_FEATURES_LEARNED && p->gate_features != RAPID_FEATURES_ROI) return RAPID_EINVAL;
+    sc->feat_set = p->gate_features;
     if (p->w_col < 0 || p->w_pos < 0 || p->w_bnd < 0 || p->min_size < 0 || p->max_size < 1)
         return RAPID_EINVAL;
     sc->F = p->frac_bits;
@@ -1190,7 +1192,8 @@ static rapid_status gated_impl(rapid_ctx *ctx, const rapid_image *imgs, int32_t 
         J.gate = nullptr;
         if ((r = run_jobs(ctx, b.jobs, b.sc, 0, gs, FLAG_INIT, b.Kmax, b.nbF_max))) return r;
         const LaunchShape first = ctx->last;
-        HIPCHK(launch_features(ctx->jobs_dev, 1, b.sc.B[gs - 1], (gs - 1) & 1, b.sc.F, J.K, b.max_nb[gs - 1],
+        HIPCHK(launch_features(ctx->jobs_dev, 1, b.sc.B[gs - 1], (gs - 1) & 1, b.sc.F, b.sc.feat_set, J.K,
+                               b.max_nb[gs - 1],
                                b.xoff_dev, b.X, ctx->stream));
         HIPCHK(launch_mlp_fwd(b.X, J.K, model->w_bf16_dev, model->thresh, nullptr, b.gates, ctx->stream));
         J.gate = b.gates;
@@ -1434,7 +1437,8 @@ rapid_status rapid_state_features(rapid_ctx *ctx, rapid_state *st, float *X_dev)
     HIPCHK(hipMemcpyAsync(st->job_dev, &st->job, sizeof(Job), hipMemcpyHostToDevice, ctx->stream));
     const int s = st->map_stage, B = st->sc.B[s];
     const int64_t nb = (int64_t)((st->W + B - 1) / B) * ((st->H + B - 1) / B);
-    HIPCHK(launch_features(st->job_dev, 1, B, s & 1, st->sc.F, st->job.K, nb, st->zero_dev, X_dev, ctx->stream));
+    HIPCHK(launch_features(st->job_dev, 1, B, s & 1, st->sc.F, st->sc.feat_set, st->job.K, nb, st->zero_dev, X_dev,
+                           ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return RAPID_OK;
 }

@@ -32,6 +32,7 @@ struct Sched {
     int32_t gate_stage;      // first stage refined under the gate
     int32_t gate_rule;       // RAPID_GATE_*
     int32_t merge;           // 1: merge on underflow
+    int32_t feat_set;        // RAPID_FEATURES_*: the gate's feature vector
     int32_t F, max_sweeps;
     int64_t min_size, max_size, w_col, w_pos, w_bnd;
     double d_wc, d_wp, d_wb, d_fs;   // w_col, w_pos, w_bnd 2^(2F), 2^(F+1) as doubles
@@ -157,7 +158,7 @@ constexpr int FACC = 8;
 // 32-bit words (16 bytes; two records per 32-byte sector)
 constexpr int MN_STRIDE = 4;
 
-hipError_t launch_features(const Job *jobs_dev, int n_jobs, int B, int lab_buf, int F, int32_t Kmax,
+hipError_t launch_features(const Job *jobs_dev, int n_jobs, int B, int lab_buf, int F, int fset, int32_t Kmax,
                            int64_t max_nb, const int64_t *xoff_dev, float *X, hipStream_t stream);
 hipError_t launch_mlp_fwd(const float *X, int64_t N, const uint16_t *P, float thresh, float *logits,
                           uint8_t *gate, hipStream_t stream);

@@ -576,7 +576,7 @@ __device__ __forceinline__ int merge_pass(const Job &J, int64_t *st, int32_t *mn
 
 // Accumulators of one superpixel in the LDS window of the gate point.
 struct WinAcc {
-    unsigned long long q[3], ed2;
+    unsigned long long q[3], ed2, nbs;
     unsigned bl, mx, mn, pad;
 };
 
@@ -600,6 +600,7 @@ struct WindowSink {
         if (v.bl) {
             atomicAdd(&w.bl, (unsigned)v.bl);
             atomicAdd(&w.ed2, (unsigned long long)v.ed2);
+            atomicAdd(&w.nbs, (unsigned long long)v.nbs);
             atomicMax(&w.mx, (unsigned)v.mx);
             atomicMin(&w.mn, (unsigned)v.mn);
         }
@@ -623,7 +624,7 @@ struct WindowSink {
 // squared mean distances fit 32 bits (F <= 4).  Falls back to the label
 // map in global memory when the LDS is too small.
 __device__ __attribute__((noinline)) void gate_point(const Job &J, const int64_t *st, int stage_q, int Bq, int F,
-                                                     const uint16_t *mlp_w, float thresh, char *lds,
+                                                     int fset, const uint16_t *mlp_w, float thresh, char *lds,
                                                      uint32_t lds_bytes, int tid, int nt)
 {
     const int K = J.K;
@@ -661,7 +662,7 @@ __device__ __attribute__((noinline)) void gate_point(const Job &J, const int64_t
     if (staged) {
         for (int e = tid; e < WR * J.gx; e += nt) {
             WinAcc &w = win[e];
-            w.q[0] = w.q[1] = w.q[2] = w.ed2 = 0;
+            w.q[0] = w.q[1] = w.q[2] = w.ed2 = w.nbs = 0;
             w.bl = w.mx = 0;
             w.mn = 0xFFFFFFFFu;
         }
@@ -698,10 +699,11 @@ __device__ __attribute__((noinline)) void gate_point(const Job &J, const int64_t
                     v.q[2] = (int64_t)w.q[2];
                     v.bl = w.bl;
                     v.ed2 = (int64_t)w.ed2;
+                    v.nbs = (int64_t)w.nbs;
                     v.mx = w.mx;
                     v.mn = w.mn;
                     feat_flush(J.facc, k, v);
-                    w.q[0] = w.q[1] = w.q[2] = w.ed2 = 0;
+                    w.q[0] = w.q[1] = w.q[2] = w.ed2 = w.nbs = 0;
                     w.bl = w.mx = 0;
                     w.mn = 0xFFFFFFFFu;
                 }
@@ -717,7 +719,7 @@ __device__ __attribute__((noinline)) void gate_point(const Job &J, const int64_t
         }
         wg_sync();
     }
-    for (int k = tid; k < K; k += nt) feat_final_sp(J, st, J.facc, J.moved, k, F, J.xrow + 16 * (int64_t)k);
+    for (int k = tid; k < K; k += nt) feat_final_sp(J, st, J.facc, J.moved, k, F, fset, J.xrow + 16 * (int64_t)k);
     wg_sync();
     const int lane = tid & 63;
     for (int t = tid >> 6; t < (K + 15) / 16; t += nt >> 6) {
@@ -958,8 +960,8 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
             // keeps its own means; the records are rebuilt afterwards).  A
             // larger band of the label map per pass means fewer passes.
             const uint32_t gp_off = SL == 1 ? lp.off_lists : 0u;
-            gate_point(J, st, s - 1, sc.B[s - 1], sc.F, sc.mlp_w, sc.mlp_thresh, smem + gp_off, lp.total - gp_off,
-                       tid, nt);
+            gate_point(J, st, s - 1, sc.B[s - 1], sc.F, sc.feat_set, sc.mlp_w, sc.mlp_thresh, smem + gp_off,
+                       lp.total - gp_off, tid, nt);
             if (SL == 2 || SL == 3)
                 for (int k = tid; k < K; k += nt) refresh_sp(st, mn, k, sc);
             if (SL == 3)   // the flow counters are zero between class phases

@@ -53,7 +53,7 @@ class Params(C.Structure):
         ("factor", C.c_int32 * MAX_LEVELS), ("n_stages", C.c_int32 * MAX_LEVELS),
         ("stages", (C.c_int32 * MAX_STAGES) * MAX_LEVELS),
         ("gate_level", C.c_int32), ("frac_bits", C.c_int32), ("max_sweeps", C.c_int32),
-        ("gate_rule", C.c_int32), ("merge", C.c_int32), ("reserved", C.c_int32),
+        ("gate_rule", C.c_int32), ("merge", C.c_int32), ("gate_features", C.c_int32),
         ("min_size", C.c_int64), ("max_size", C.c_int64),
         ("w_col", C.c_int64), ("w_pos", C.c_int64), ("w_bnd", C.c_int64),
     ]
@@ -157,6 +157,7 @@ def _check(rc: int, where: str):
 
 
 GATE_RULES = {"either": 0, "both": 1, "differ": 2}   # RAPID_GATE_*
+GATE_FEATURES = {"learned": 0, "roi": 1}              # RAPID_FEATURES_*
 
 
 def make_params(d: dict) -> Params:
@@ -176,6 +177,7 @@ def make_params(d: dict) -> Params:
     p.max_sweeps = int(d.get("max_sweeps", 64))
     p.gate_rule = GATE_RULES[d.get("gate_rule", "either")]
     p.merge = int(bool(d.get("merge", False)))
+    p.gate_features = GATE_FEATURES[d.get("gate_features", "learned")]
     p.min_size = int(d["min_size"])
     p.max_size = int(d["max_size"])
     p.w_col = int(d["w_col"])

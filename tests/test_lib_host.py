@@ -97,7 +97,8 @@ def test_slide_rejects(args):
         rapid.slide_tiles(*args)
 
 
-@pytest.mark.parametrize("field,value", [("merge", 2), ("merge", -1), ("reserved", 1), ("gate_rule", 3)])
+@pytest.mark.parametrize("field,value", [("merge", 2), ("merge", -1), ("gate_features", 2), ("gate_features", -1),
+                                         ("gate_rule", 3)])
 def test_check_params_rejects_bad_mode_fields(field, value):
     """Mode fields outside their range are refused, merge included."""
     import ctypes as C
@@ -106,4 +107,6 @@ def test_check_params_rejects_bad_mode_fields(field, value):
     k = C.c_int32(0)
     assert rapid._lib.rapid_check_params(256, 256, C.byref(p), C.byref(k)) == -1
     p = rapid.make_params(dict(params.config1(), merge=True))
+    assert rapid._lib.rapid_check_params(256, 256, C.byref(p), C.byref(k)) == 0 and k.value == 64
+    p = rapid.make_params(dict(params.config1(), gate_features="roi"))
     assert rapid._lib.rapid_check_params(256, 256, C.byref(p), C.byref(k)) == 0 and k.value == 64

@@ -186,3 +186,80 @@ def test_features_contrast_max_rms_min_by_hand():
         assert np.isclose(f[k, 7], bl / (4 * np.sqrt(200)), rtol=1e-6)
         assert np.isclose(f[k, 8], bl * bl / (16 * 200), rtol=1e-6)
     assert np.allclose(f[:, 3:6], 0) and np.allclose(f[:, 14], 0) and np.allclose(f[:, 15], 1)
+
+
+def _stats_of(img, lab, K):
+    """n, colour sums and coordinate sums per label, counted in numpy."""
+    H, W, _ = img.shape
+    ys, xs = np.mgrid[0:H, 0:W]
+    st = np.zeros((K, 6), np.int64)
+    for k in range(K):
+        m = lab == k
+        st[k] = [m.sum(), img[..., 0][m].sum(), img[..., 1][m].sum(), img[..., 2][m].sum(), xs[m].sum(), ys[m].sum()]
+    return st
+
+
+def test_roi_features_two_regions_by_hand():
+    """The paper's four ROI features (Sec. 4) on a 4x4 image, left half label
+    0 with rows alternating (10,20,30) / (14,20,30), right half label 1 of
+    (100,100,100); F = 4, so the fixed-point means are (192,320,480) and
+    (1600,1600,1600); four pixel pairs cross the border.  By hand:
+    brightness 62/3 and 100; each side's neighbour brightness is the other's;
+    the mean-colour distance is sqrt(1408^2 + 1280^2 + 1120^2) = 2208 fixed-
+    point units; label 0's channel variances are 4, 0, 0."""
+    img = np.zeros((4, 4, 3), np.uint8)
+    img[:, :2] = (10, 20, 30)
+    img[1::2, :2, 0] = 14
+    img[:, 2:] = 100
+    lab = np.zeros((4, 4), np.int32)
+    lab[:, 2:] = 1
+    f = oracle.roi_features(img, lab, _stats_of(img, lab, 2), 2, 1)
+    want0 = [62 / 3 / 255, (62 / 3 - 100) / 255, 2208 / 4080, np.sqrt(4 / 3) / 64]
+    want1 = [100 / 255, (100 - 62 / 3) / 255, 2208 / 4080, 0.0]
+    assert np.allclose(f[0, :4], want0, rtol=1e-6, atol=1e-7)
+    assert np.allclose(f[1, :4], want1, rtol=1e-6, atol=1e-7)
+    assert (f[:, 4:15] == 0).all() and (f[:, 15] == 1).all()
+
+
+def test_roi_features_edge_weighting_by_hand():
+    """Three labels on a 4x3 image whose border pixel pairs are unequal:
+        0 0 0 1
+        0 0 0 1
+        2 2 2 2
+    label 0 (40,40,40) meets label 1 (100,100,100) on 2 pixel pairs and
+    label 2 (mean (10,10,10), pixels alternating (8,10,12) / (12,10,8)) on 3;
+    labels 1 and 2 meet on 1.  Neighbour brightness of label 0 is
+    (2*100 + 3*10) / 5 = 46 (an unweighted mean would give 55, a size-
+    weighted one 40), of label 1 (2*40 + 1*10) / 3 = 30, of label 2
+    (3*40 + 1*100) / 4 = 55.  Label 0's rms distance is
+    sqrt((2*3*960^2 + 3*3*480^2) / 5) fixed-point units; label 2's channel
+    variances are 4, 0, 4."""
+    img = np.zeros((3, 4, 3), np.uint8)
+    img[:2, :3] = 40
+    img[:2, 3] = 100
+    img[2] = [(8, 10, 12), (12, 10, 8), (8, 10, 12), (12, 10, 8)]
+    lab = np.array([[0, 0, 0, 1], [0, 0, 0, 1], [2, 2, 2, 2]], np.int32)
+    f = oracle.roi_features(img, lab, _stats_of(img, lab, 3), 3, 1)
+    assert np.allclose(f[:, 0], [40 / 255, 100 / 255, 10 / 255], rtol=1e-6)
+    assert np.allclose(f[:, 1], [(40 - 46) / 255, (100 - 30) / 255, (10 - 55) / 255], rtol=1e-6, atol=1e-7)
+    rms0 = np.sqrt((2 * 3 * 960 ** 2 + 3 * 3 * 480 ** 2) / 5)
+    rms1 = np.sqrt((2 * 3 * 960 ** 2 + 1 * 3 * 1440 ** 2) / 3)
+    rms2 = np.sqrt((3 * 3 * 480 ** 2 + 1 * 3 * 1440 ** 2) / 4)
+    assert np.allclose(f[:, 2], np.array([rms0, rms1, rms2]) / 4080, rtol=1e-6)
+    assert np.allclose(f[:, 3], [0, 0, np.sqrt(8 / 3) / 64], rtol=1e-6, atol=1e-7)
+
+
+def test_roi_features_match_the_sixteen_on_shared_quantities():
+    """On a refined H&E state, the ROI features that the learned gate's
+    sixteen also measure agree with them: absolute brightness is the mean of
+    features 0-2, extra-region dissimilarity is feature 11, intra-region
+    dissimilarity is the quadratic mean of features 3-5 (same scales)."""
+    img = synth.he_tile(192, 128, seed=17)
+    p = params.default_params(192, 128, 24, levels=[(1, [16, 8, 4])])
+    lab, st, _ = oracle.segment(img, p)
+    gx, gy = oracle.grid(192, 128, 24)
+    f16 = oracle.features(img, lab, 4, st, None, gx, gy)
+    f4 = oracle.roi_features(img, lab, st, gx, gy)
+    assert np.allclose(f4[:, 0], f16[:, :3].mean(1), rtol=1e-5, atol=1e-6)
+    assert np.allclose(f4[:, 2], f16[:, 11], rtol=1e-5, atol=1e-6)
+    assert np.allclose(f4[:, 3], np.sqrt((f16[:, 3:6].astype(np.float64) ** 2).mean(1)), rtol=1e-5, atol=1e-6)
