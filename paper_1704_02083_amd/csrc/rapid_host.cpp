@@ -28,6 +28,8 @@ struct LaunchShape {
                        // a cooperative launch (state global, pyramid apart)
     int solo = -1;     // cooperative launch: sweeps with at most this many
                        // active blocks run on one workgroup (-1: never)
+    int wgs = 0;       // several jobs: workgroups of the persistent launch
+                       // over the job queue (0: as many as the chip holds)
     float ms = 0.0f;   // autotuner: time of the choice
 };
 
@@ -46,7 +48,7 @@ struct rapid_ctx {
     hipEvent_t tev[2] = {nullptr, nullptr};
     LaunchShape last;              // shape of the last refinement launch
     int last_tuned = 0;
-    bool shape_forced = false;     // RAPID_SHAPE=threads,stats_lds,pyramid fixes the shape
+    bool shape_forced = false;     // RAPID_SHAPE=threads,stats_lds,pyramid[,groups,solo,wgs] fixes the shape
     LaunchShape forced;
     // scratch pool for rapid_segment / rapid_segment_batch
     char *pool = nullptr;
@@ -54,6 +56,7 @@ struct rapid_ctx {
     Job *jobs_dev = nullptr;
     size_t jobs_cap = 0;
     Job *jobs_pinned = nullptr;
+    std::vector<int32_t> order;    // the job table's order (largest job first)
     hipEvent_t jobs_copied = nullptr;
     bool timing = false;
     bool timed = false;
@@ -582,7 +585,10 @@ rapid_status launch_shape(rapid_ctx *ctx, const Job *jobs, size_t n, const Job *
         return RAPID_OK;
     }
     if (e1) HIPCHK(hipEventRecord(e1, ctx->stream));
-    HIPCHK(launch_refine(jobs_dev, (int)n, sc, lp, s_begin, s_end, flags, ctx->lut_dev, sh.threads,
+    // several jobs: a persistent launch over the job queue that follows the
+    // job table (a word past its last entry)
+    uint32_t *queue = n > 1 ? reinterpret_cast<uint32_t *>(const_cast<Job *>(jobs_dev) + n) : nullptr;
+    HIPCHK(launch_refine(jobs_dev, (int)n, queue, sh.wgs, sc, lp, s_begin, s_end, flags, ctx->lut_dev, sh.threads,
                          ctx->stream));
     if (e2) HIPCHK(hipEventRecord(e2, ctx->stream));
     return RAPID_OK;
@@ -604,7 +610,8 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
             ctx->jobs_cap = 0;
         }
         size_t cap = std::max<size_t>(n, 64);
-        if (hipMalloc(&ctx->jobs_dev, cap * sizeof(Job)) != hipSuccess) return RAPID_ENOMEM;
+        // the job table, then the work queue's counter
+        if (hipMalloc(&ctx->jobs_dev, cap * sizeof(Job) + 256) != hipSuccess) return RAPID_ENOMEM;
         if (hipHostMalloc(&ctx->jobs_pinned, cap * sizeof(Job)) != hipSuccess) return RAPID_ENOMEM;
         ctx->jobs_cap = cap;
     }
@@ -615,7 +622,18 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
     if (gated && ((int64_t)Kmax + 31) / 32 > MAX_GATE_WORDS) return RAPID_EINVAL;
     // the previous upload from the staging buffer must have completed
     HIPCHK(hipEventSynchronize(ctx->jobs_copied));
-    std::memcpy(ctx->jobs_pinned, jobs.data(), n * sizeof(Job));
+    if (n > 1) {
+        // the queue hands the jobs out largest first (pixels, then index), so
+        // that the last ones to start are short
+        ctx->order.resize(n);
+        for (size_t j = 0; j < n; j++) ctx->order[j] = (int32_t)j;
+        std::stable_sort(ctx->order.begin(), ctx->order.end(), [&](int32_t x, int32_t y) {
+            return (int64_t)jobs[x].W * jobs[x].H > (int64_t)jobs[y].W * jobs[y].H;
+        });
+        for (size_t j = 0; j < n; j++) ctx->jobs_pinned[j] = jobs[ctx->order[j]];
+    } else {
+        std::memcpy(ctx->jobs_pinned, jobs.data(), n * sizeof(Job));
+    }
     HIPCHK(hipMemcpyAsync(ctx->jobs_dev, ctx->jobs_pinned, n * sizeof(Job), hipMemcpyHostToDevice,
                           ctx->stream));
     HIPCHK(hipEventRecord(ctx->jobs_copied, ctx->stream));
@@ -848,9 +866,10 @@ rapid_status rapid_init(const rapid_config *cfg, rapid_ctx **out)
     }
     if (const char *t = std::getenv("RAPID_SHAPE")) {
         LaunchShape f;
-        const int got = std::sscanf(t, "%d,%d,%d,%d,%d", &f.threads, &f.stats_lds, &f.pyramid, &f.groups, &f.solo);
+        const int got = std::sscanf(t, "%d,%d,%d,%d,%d,%d", &f.threads, &f.stats_lds, &f.pyramid, &f.groups, &f.solo,
+                                    &f.wgs);
         if (got >= 3 && f.threads >= 64 && f.threads <= 1024 && f.threads % 64 == 0 && f.groups >= 1 &&
-            f.groups <= 4096) {
+            f.groups <= 4096 && f.wgs >= 0) {
             ctx->forced = f;
             ctx->shape_forced = true;
         }

@@ -136,8 +136,11 @@ hipError_t launch_store_job(const Job &j, Job *dst, hipStream_t stream);
 hipError_t launch_block_sums(const Job *jobs_dev, int n_jobs, int s, int B, int64_t max_nb, hipStream_t stream);
 hipError_t launch_expand(const int32_t *L, int W, int H, int B, int32_t *out, int64_t stride,
                          hipStream_t stream);
-hipError_t launch_refine(const Job *jobs_dev, int n_jobs, const Sched &sc, const LdsPlan &lp,
-                         int s_begin, int s_end, int flags, const uint32_t *lut_dev, int threads,
+// launch_refine: queue (a device word, nullable) turns a launch of more
+// jobs than wgs workgroups (0: as many as the chip holds at once) into a
+// persistent launch over a work queue in jobs_dev order
+hipError_t launch_refine(const Job *jobs_dev, int n_jobs, uint32_t *queue, int wgs, const Sched &sc,
+                         const LdsPlan &lp, int s_begin, int s_end, int flags, const uint32_t *lut_dev, int threads,
                          hipStream_t stream);
 // one job on `groups` workgroups of a cooperative launch (no merge, not a
 // slide tile, gate bits from the caller or none: gate_words > 0 loads them);

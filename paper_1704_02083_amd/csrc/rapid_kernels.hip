@@ -843,9 +843,8 @@ __device__ __forceinline__ void propose_block(const Job &J, int s, int B, int32_
 // in LDS (the hot reads of P1) and the rest in global memory, 3 the means
 // records and the flow counters in LDS, the statistics in global memory.
 template <int SL, int GM, bool MERGE>
-__global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, Sched sc, LdsPlan lp,
-                                                  int s_begin, int s_end, int flags,
-                                                  const uint32_t *__restrict__ lut_g)
+__device__ __forceinline__ void refine_job(const Job &J, const Sched &sc, const LdsPlan &lp, int s_begin, int s_end,
+                                           int flags, const uint32_t *__restrict__ lut_g)
 {
     extern __shared__ __align__(16) char smem[];
     __shared__ uint32_t s_lut[8];
@@ -853,7 +852,6 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
     __shared__ int32_t s_nprop, s_nchg, s_nreq, s_merged, s_any;
     __shared__ unsigned long long s_ctr[6];   // active proposals commits skip_min skip_topo merges
 
-    const Job &J = jobs[blockIdx.x];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int W = J.W, H = J.H, K = J.K;
     int64_t *st;
@@ -1412,6 +1410,34 @@ __global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, S
     }
 }
 
+// The refinement launch over n_jobs images or tiles.  queue == nullptr: one
+// workgroup per job (workgroup b refines job b).  Otherwise a persistent
+// launch over a work queue: every workgroup takes its next job from the
+// queue counter (zeroed before the launch) until the jobs run out, so the
+// grid can be sized to what the chip holds at once and the host's job order
+// (largest first) is the order in which they start.  Every workgroup leaves
+// once the counter has passed n_jobs.
+template <int SL, int GM, bool MERGE>
+__global__ __launch_bounds__(1024) void k_refine(const Job *__restrict__ jobs, int n_jobs, uint32_t *queue, Sched sc,
+                                                  LdsPlan lp, int s_begin, int s_end, int flags,
+                                                  const uint32_t *__restrict__ lut_g)
+{
+    __shared__ int32_t s_job;
+    int job = blockIdx.x;
+    for (;;) {
+        if (queue) {
+            if (threadIdx.x == 0) s_job = (int32_t)atomicAdd(queue, 1u);
+            __syncthreads();
+            job = s_job;
+        }
+        if (job >= n_jobs) break;
+        refine_job<SL, GM, MERGE>(jobs[job], sc, lp, s_begin, s_end, flags, lut_g);
+        if (!queue) break;
+        // every lane is done with this job's LDS (and has read s_job)
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------- one image on many workgroups
 // k_refine_mc: the same stage loop, class phases and counters as k_refine,
 // for a single image whose class phases hold thousands of blocks.  G
@@ -1931,11 +1957,11 @@ hipError_t launch_expand(const int32_t *L, int W, int H, int B, int32_t *out, in
     return hipGetLastError();
 }
 
-hipError_t launch_refine(const Job *jobs_dev, int n_jobs, const Sched &sc, const LdsPlan &lp,
-                         int s_begin, int s_end, int flags, const uint32_t *lut_dev, int threads,
+hipError_t launch_refine(const Job *jobs_dev, int n_jobs, uint32_t *queue, int wgs, const Sched &sc,
+                         const LdsPlan &lp, int s_begin, int s_end, int flags, const uint32_t *lut_dev, int threads,
                          hipStream_t stream)
 {
-    typedef void (*Kern)(const Job *, Sched, LdsPlan, int, int, int, const uint32_t *);
+    typedef void (*Kern)(const Job *, int, uint32_t *, Sched, LdsPlan, int, int, int, const uint32_t *);
     // instantiations: where the per-superpixel state lives, gate mode, merge
     // on underflow
 #define RAPID_K(sl, gm) {k_refine<sl, gm, false>, k_refine<sl, gm, true>}
@@ -1949,8 +1975,31 @@ hipError_t launch_refine(const Job *jobs_dev, int n_jobs, const Sched &sc, const
     const Kern fn = table[lp.stats_lds][gm][sc.merge ? 1 : 0];
     hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp.total);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fn, dim3((unsigned)n_jobs), dim3(threads), lp.total, stream, jobs_dev, sc, lp, s_begin,
-                       s_end, flags, lut_dev);
+    // the persistent launch: wgs workgroups, or (wgs == 0) as many as the
+    // chip holds at once, when that is fewer than the jobs
+    int grid = n_jobs;
+    if (queue) {
+        if (wgs <= 0) {
+            // at least one workgroup per CU is resident; fewer jobs than CUs
+            // never need the queue, so only larger launches ask how many fit
+            int dev = 0, cus = 0;
+            if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+            if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+            wgs = std::max(1, cus);
+            if (n_jobs > wgs) {
+                int per_cu = 0;
+                if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, threads,
+                                                                      lp.total)) != hipSuccess)
+                    return e;
+                wgs *= std::max(1, per_cu);
+            }
+        }
+        grid = std::min(n_jobs, wgs);
+        if (grid == n_jobs) queue = nullptr;   // one workgroup per job: no queue
+        else if ((e = hipMemsetAsync(queue, 0, sizeof(uint32_t), stream)) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(threads), lp.total, stream, jobs_dev, n_jobs, queue, sc, lp,
+                       s_begin, s_end, flags, lut_dev);
     return hipGetLastError();
 }
 

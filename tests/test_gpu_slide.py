@@ -55,3 +55,41 @@ def test_slide_matches_tilewise_oracle(ctx, W, H, tile, halo):
     assert (exp >= 0).all()
     mism = int((got != exp).sum())
     assert mism == 0, "%d slide labels differ" % mism
+
+
+@pytest.mark.parametrize("wgs", [1, 3, 5])
+def test_persistent_queue_few_workgroups(gpu_lib, wgs):
+    """The refinement launch as a persistent kernel over its job queue with
+    fewer workgroups than tiles (RAPID_SHAPE's sixth field): each workgroup
+    refines tile after tile, largest first, and every tile still equals its
+    oracle run."""
+    import os
+    import torch
+    W, H, T, h = 1000, 700, 256, 64
+    old = os.environ.get("RAPID_SHAPE")
+    os.environ["RAPID_SHAPE"] = "1024,0,1,1,-1,%d" % wgs
+    try:
+        c = gpu_lib.Context(0, timing=True)
+    finally:
+        if old is None:
+            os.environ.pop("RAPID_SHAPE", None)
+        else:
+            os.environ["RAPID_SHAPE"] = old
+    try:
+        _say("case: slide %dx%d on %d persistent workgroups" % (W, H, wgs))
+        rgb = synth_gpu.he_slide(W, H, seed=4, device="cuda", band=256)
+        p = params.default_params(W, H, 1, levels=params.THREE_LEVEL)
+        p["min_size"], p["max_size"], p["w_col"], p["w_bnd"] = 64, 1536, 1024, 32 * 1024
+        labels, reps = c.segment_slide(rgb, p, tile=T, halo=h, cell=32, report=True)
+        torch.cuda.synchronize()
+        lay = rapid.tile_layout(W, H, T, h, 32)
+        exp = _expected(rgb.cpu().numpy(), p, lay, W, H)
+        assert (labels.cpu().numpy() == exp).all()
+        # the reports stay in tile order whatever order the queue ran them in
+        for t, rp in zip(lay, reps):
+            ex0, ey0, ex1, ey1 = t["ext"]
+            sub = np.ascontiguousarray(rgb[ey0:ey1, ex0:ex1].cpu().numpy())
+            _, _, ref_rep = oracle.segment(sub, _tile_params(p, t))
+            assert rp == ref_rep
+    finally:
+        c.close()
