@@ -404,26 +404,74 @@ rapid_status dev_err(hipError_t e) { return e == hipSuccess ? RAPID_OK : RAPID_E
 // bitmap and the changed list, each within a share of what remains.
 // Residency of the per-superpixel state that fits LDS beside the work
 // space, given the one asked for, falling back in the order 1 (statistics,
-// means, flow), 3 (means and flow), 2 (means), 0 (all in global memory).
-int lds_residency(size_t limit, int32_t Kmax, bool gated, int want)
+// means, flow), 4 (packed statistics and flow, where the launch allows the
+// packing), 3 (means and flow), 2 (means), 0 (all in global memory).
+int lds_residency(size_t limit, int32_t Kmax, bool gated, int want, bool packable)
 {
     const size_t gwords = gated ? ((size_t)Kmax + 31) / 32 : 0;
     const size_t base = 48 * 1024 + 4 * gwords;
     if (want == 1 && (size_t)Kmax * LDS_PER_SP + base <= limit) return 1;
-    if ((want == 1 || want == 3) && (size_t)Kmax * LDS_MEANS_FLOW_PER_SP + base <= limit) return 3;
+    if ((want == 1 || want == 4) && packable && (size_t)Kmax * LDS_PACKED_FLOW_PER_SP + base <= limit) return 4;
+    if ((want == 1 || want == 3 || want == 4) && (size_t)Kmax * LDS_MEANS_FLOW_PER_SP + base <= limit) return 3;
     if (want >= 1 && (size_t)Kmax * LDS_MEANS_PER_SP + base <= limit) return 2;
     return 0;
 }
 
-LdsPlan plan_lds(size_t limit, int32_t Kmax, int64_t nbF, bool gated, int want)
+inline int bit_length(uint64_t v) { return v ? 64 - __builtin_clzll(v) : 0; }
+
+// Packed statistics (residency 4) for a launch that starts from the grid:
+// n stays below nmax = the larger of max_size and the largest initial cell
+// (the size filter never lets a superpixel grow past max_size), so the
+// colour sums need 255 nmax < 2^21 and n, T_x <= nmax (W - 1) and
+// T_y <= nmax (H - 1) must share 64 bits.  Sets sc.pk_bn, sc.pk_bx and
+// returns true when every job allows it.
+bool set_packing(Sched &sc, const Job *jobs, size_t n, int flags)
+{
+    sc.pk_bn = sc.pk_bx = 0;
+    if (!(flags & FLAG_INIT) || sc.merge) return false;
+    int bn = 1, bx = 1, by = 1;
+    const int B0 = sc.B[0];
+    for (size_t j = 0; j < n; j++) {
+        const Job &J = jobs[j];
+        // the widest cell column and tallest cell row of the block-centre
+        // rule (a block's cell index never decreases along an axis)
+        auto widest = [B0](int64_t len, int64_t cells) {
+            int64_t best = 0, run = 0, cur = -1;
+            for (int64_t x0 = 0; x0 < len; x0 += B0) {
+                const int64_t w = std::min<int64_t>(B0, len - x0);
+                const int64_t c = ((2 * x0 + w) * cells) / (2 * len);
+                if (c != cur) {
+                    cur = c;
+                    run = 0;
+                }
+                run += w;
+                best = std::max(best, run);
+            }
+            return best;
+        };
+        const int64_t cell = widest(J.W, J.gx) * widest(J.H, J.gy);
+        const int64_t nmax = std::max<int64_t>(sc.max_size, cell);
+        if (nmax <= 0 || nmax >= ((int64_t)1 << 30) || 255 * nmax >= ((int64_t)1 << 21)) return false;
+        bn = std::max(bn, bit_length((uint64_t)nmax));
+        bx = std::max(bx, bit_length((uint64_t)nmax * (uint64_t)(J.W - 1)));
+        by = std::max(by, bit_length((uint64_t)nmax * (uint64_t)(J.H - 1)));
+    }
+    if (bn + bx + by > 64) return false;
+    sc.pk_bn = bn;
+    sc.pk_bx = bx;
+    return true;
+}
+
+LdsPlan plan_lds(size_t limit, int32_t Kmax, int64_t nbF, bool gated, int want, bool packable)
 {
     LdsPlan p;
     std::memset(&p, 0, sizeof p);
     auto a16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
     size_t off = 0;
     const size_t gwords = gated ? ((size_t)Kmax + 31) / 32 : 0;   // at most MAX_GATE_WORDS (run_jobs)
-    p.stats_lds = lds_residency(limit, Kmax, gated, want);
+    p.stats_lds = lds_residency(limit, Kmax, gated, want, packable);
     if (p.stats_lds == 1) off = a16((size_t)Kmax * LDS_PER_SP);
+    else if (p.stats_lds == 4) off = a16((size_t)Kmax * LDS_PACKED_FLOW_PER_SP);
     else if (p.stats_lds == 3) off = a16((size_t)Kmax * LDS_MEANS_FLOW_PER_SP);
     else if (p.stats_lds == 2) off = a16((size_t)Kmax * LDS_MEANS_PER_SP);
     p.gate_words = (int32_t)gwords;
@@ -564,7 +612,7 @@ rapid_status launch_shape(rapid_ctx *ctx, const Job *jobs, size_t n, const Job *
             }
         }
     }
-    LdsPlan lp = plan_lds(ctx->lds_limit, Kmax, nbF_max, gated, sh.stats_lds);
+    LdsPlan lp = plan_lds(ctx->lds_limit, Kmax, nbF_max, gated, sh.stats_lds, sc.pk_bn > 0);
     if (ctx->verbose)
         std::fprintf(stderr,
                      "rapid: threads %d, lds limit %zu, stats_lds %d, capl %d capp %d capx %d bm_words %d "
@@ -596,10 +644,12 @@ rapid_status launch_shape(rapid_ctx *ctx, const Job *jobs, size_t n, const Job *
 
 // follow: when the shape of an earlier launch spread the image over many
 // workgroups, this launch does too (where it may)
-rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched &sc, int s_begin,
+rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched &sc_in, int s_begin,
                       int s_end, int flags, int32_t Kmax, int64_t nbF_max, const LaunchShape *follow = nullptr)
 {
     size_t n = jobs.size();
+    Sched sc = sc_in;
+    const bool packable = set_packing(sc, jobs.data(), n, flags);
     if (n > ctx->jobs_cap) {
         if (ctx->jobs_dev) {
             HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -647,7 +697,7 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
         HIPCHK(max_coop_groups(1024, &coop_max));
     LaunchShape sh;
     sh.threads = ctx->threads;
-    sh.stats_lds = lds_residency(ctx->lds_limit, Kmax, gated, 1);
+    sh.stats_lds = lds_residency(ctx->lds_limit, Kmax, gated, 1, packable);
     sh.pyramid = (int)n >= PYRAMID_MIN_JOBS ? 1 : 0;
     if (coop_max > 1 && nbF_max >= ((int64_t)1 << 20) && (!ctx->threads_forced || ctx->threads == 1024)) {
         // untuned default for a single image of a million finest blocks or
@@ -691,16 +741,16 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
         const size_t n_coop = cand.size();
         LaunchShape dflt;   // the default one-workgroup shape
         dflt.threads = ctx->threads;
-        dflt.stats_lds = lds_residency(ctx->lds_limit, Kmax, gated, 1);
+        dflt.stats_lds = lds_residency(ctx->lds_limit, Kmax, gated, 1, packable);
         dflt.pyramid = (int)n >= PYRAMID_MIN_JOBS ? 1 : 0;
         cand.push_back(dflt);
         const int thr_all[3] = {256, 512, 1024};
-        const int res_all[4] = {1, 3, 2, 0};
+        const int res_all[5] = {1, 4, 3, 2, 0};
         for (int t = 0; t < 3; t++) {
             if (ctx->threads_forced && thr_all[t] != ctx->threads) continue;
-            for (int li = 0; li < 4; li++) {
+            for (int li = 0; li < 5; li++) {
                 const int l = res_all[li];
-                if (lds_residency(ctx->lds_limit, Kmax, gated, l) != l) continue;   // does not fit
+                if (lds_residency(ctx->lds_limit, Kmax, gated, l, packable) != l) continue;   // does not fit
                 for (int py = 1; py >= 0; py--) {
                     LaunchShape c;
                     c.threads = thr_all[t];
@@ -753,7 +803,7 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
             sh.groups = 1;
         }
     }
-    sh.stats_lds = lds_residency(ctx->lds_limit, Kmax, gated, sh.stats_lds);
+    sh.stats_lds = lds_residency(ctx->lds_limit, Kmax, gated, sh.stats_lds, packable);
     ctx->last = sh;
     if (ctx->timing) timing_next(ctx);
     rapid_status r = launch_shape(ctx, jobs.data(), n, ctx->jobs_dev, sc, s_begin, s_end, flags, Kmax, nbF_max,
@@ -1151,7 +1201,8 @@ rapid_status rapid_segment_noalloc(rapid_ctx *ctx, const rapid_image *img, const
     // the default one-workgroup shape; the block sums in their own launches
     LaunchShape sh;
     sh.threads = ctx->threads;
-    sh.stats_lds = lds_residency(ctx->lds_limit, K, gated, 1);
+    const bool packable = set_packing(sc, &J, 1, FLAG_INIT);
+    sh.stats_lds = lds_residency(ctx->lds_limit, K, gated, 1, packable);
     sh.pyramid = 0;
     sh.groups = 1;
     const int Bf = sc.B[sc.n_stages - 1];

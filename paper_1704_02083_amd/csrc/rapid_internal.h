@@ -34,6 +34,8 @@ struct Sched {
     int32_t merge;           // 1: merge on underflow
     int32_t feat_set;        // RAPID_FEATURES_*: the gate's feature vector
     int32_t F, max_sweeps;
+    int32_t pk_bn, pk_bx;    // residency 4: bits of n and of T_x in the packed
+                             // position word (T_y takes the bits above)
     int64_t min_size, max_size, w_col, w_pos, w_bnd;
     double d_wc, d_wp, d_wb, d_fs;   // w_col, w_pos, w_bnd 2^(2F), 2^(F+1) as doubles
     double d_wcfs, d_wpfs;           // w_col 2^(F+1), w_pos 2^(F+1)
@@ -54,7 +56,7 @@ struct Prop {
 // frontier rebuild is used when it covers the stage's blocks.
 struct LdsPlan {
     int32_t stats_lds;       // 0 global, 1 statistics, means, flow in LDS, 2 means in LDS,
-                             // 3 means and flow in LDS
+                             // 3 means and flow in LDS, 4 packed statistics and flow in LDS
     int32_t capl, capp, capx, bm_words;
     int32_t gate_words;      // LDS bitmap of the gate bits (0: no gate in this launch)
     uint32_t off_lists, off_props, off_chg, off_bm, off_gate;
@@ -182,5 +184,8 @@ constexpr size_t LDS_PER_SP = 6 * 8 + MN_STRIDE * 4 + 2 * 4;
 // when the flow counters join them
 constexpr size_t LDS_MEANS_PER_SP = MN_STRIDE * 4;
 constexpr size_t LDS_MEANS_FLOW_PER_SP = MN_STRIDE * 4 + 2 * 4;
+// ... and when the statistics, packed into two 64-bit words, live there with
+// the flow counters (residency 4; the means are computed where they are read)
+constexpr size_t LDS_PACKED_FLOW_PER_SP = 2 * 8 + 2 * 4;
 
 }  // namespace rapid

@@ -132,20 +132,16 @@ __device__ __forceinline__ int64_t block_energy(const int4 &lo, const int2 &hi, 
     return sc.w_col * e_col + sc.w_pos * e_pos + ((sc.w_bnd * (int64_t)bnd) << (2 * sc.F));
 }
 
-// Refresh superpixel k from its exact integer sums (st[k]): mn[k] holds its
-// means in fixed point, floor((2^(F+1) S + n) / (2 n)) (rounded half up),
-// and its size n -- the class-start snapshot every proposal and every
-// size-filter decision of the next class reads while the integer atomics of
-// that class update the sums.  The quotients use one reciprocal and an exact
-// correction step (all products stay below 2^53).
-__device__ __forceinline__ void refresh_sp(const int64_t *st, int32_t *mn, int k, const Sched &sc)
+// The fixed-point means of a superpixel with exact integer sums r = (n,
+// S_r, S_g, S_b, T_x, T_y): q[j] = floor((2^(F+1) S_j + n) / (2 n)) (rounded
+// half up; colour then position).  The quotients use one reciprocal and an
+// exact correction step (all products stay below 2^53).  A superpixel merged
+// away (n = 0, sums 0) gets means 0.
+__device__ __forceinline__ void fixed_means(const int64_t r[6], const Sched &sc, uint32_t q[5])
 {
-    const int64_t *r = st + 6 * (int64_t)k;
     const int64_t n = r[0];
-    // a superpixel merged away (n = 0, sums 0) gets means 0
     const double dd = (double)(2 * max(n, (int64_t)1)), dn0 = (double)n;
     const double rcp = 1.0 / dd;
-    uint32_t q[5];
 #pragma unroll
     for (int j = 0; j < 5; j++) {
         const double dn = fma((double)r[1 + j], sc.d_fs, dn0);   // 2^(F+1) S + n, exact
@@ -154,9 +150,73 @@ __device__ __forceinline__ void refresh_sp(const int64_t *st, int32_t *mn, int k
         else if ((v + 1.0) * dd <= dn) v += 1.0;
         q[j] = (uint32_t)v;
     }
-    const uint32_t un = (uint32_t)n;
+}
+
+// Refresh superpixel k from its exact integer sums (st[k]): mn[k] holds its
+// means in fixed point and its size n -- the class-start snapshot every
+// proposal and every size-filter decision of the next class reads while the
+// integer atomics of that class update the sums.
+__device__ __forceinline__ void refresh_sp(const int64_t *st, int32_t *mn, int k, const Sched &sc)
+{
+    const int64_t *r = st + 6 * (int64_t)k;
+    uint32_t q[5];
+    fixed_means(r, sc, q);
+    const uint32_t un = (uint32_t)r[0];
     reinterpret_cast<uint4 *>(mn)[k] =
         make_uint4(q[0] | (q[1] << 16), q[2] | ((un & 0xFFFFu) << 16), q[3] | ((un >> 16) << 17), q[4]);
+}
+
+// Packed statistics (residency 4): superpixel k's six sums in two 64-bit
+// words, w0 = S_r | S_g << 21 | S_b << 42 and w1 = n | T_x << bn | T_y <<
+// (bn + bx), with bn, bx from the host, which checked that every field
+// stays non-negative and below its width between class phases (n below the
+// larger of the maximum size and the largest initial cell).  The words are
+// sums of the fields' place values, so signed deltas add exactly modulo
+// 2^64 in any order, whatever the intermediate carries.
+__device__ __forceinline__ void pk_add(unsigned long long *w, int64_t dn, int64_t dr, int64_t dg, int64_t db,
+                                       int64_t dx, int64_t dy, const Sched &sc)
+{
+    const unsigned long long c =
+        (unsigned long long)dr + ((unsigned long long)dg << 21) + ((unsigned long long)db << 42);
+    const unsigned long long p = (unsigned long long)dn + ((unsigned long long)dx << sc.pk_bn) +
+                                 ((unsigned long long)dy << (sc.pk_bn + sc.pk_bx));
+    atomicAdd(w, c);
+    atomicAdd(w + 1, p);
+}
+
+__device__ __forceinline__ void pk_unpack(const unsigned long long *w, int64_t r[6], const Sched &sc)
+{
+    const unsigned long long w0 = w[0], w1 = w[1];
+    r[1] = (int64_t)(w0 & 0x1FFFFFull);
+    r[2] = (int64_t)((w0 >> 21) & 0x1FFFFFull);
+    r[3] = (int64_t)(w0 >> 42);
+    r[0] = (int64_t)(w1 & ((1ull << sc.pk_bn) - 1));
+    r[4] = (int64_t)((w1 >> sc.pk_bn) & ((1ull << sc.pk_bx) - 1));
+    r[5] = (int64_t)(w1 >> (sc.pk_bn + sc.pk_bx));
+}
+
+__device__ __forceinline__ int64_t pk_size(const unsigned long long *pk, int k, const Sched &sc)
+{
+    return (int64_t)(pk[2 * (int64_t)k + 1] & ((1ull << sc.pk_bn) - 1));
+}
+
+// The means record (unpacked as load_mn gives it) of superpixel k from its
+// packed statistics.
+__device__ __forceinline__ void pk_means(const unsigned long long *pk, int k, const Sched &sc, int4 &lo, int2 &hi)
+{
+    int64_t r[6];
+    pk_unpack(pk + 2 * (int64_t)k, r, sc);
+    uint32_t q[5];
+    fixed_means(r, sc, q);
+    lo = make_int4((int)q[0], (int)q[1], (int)q[2], (int)q[3]);
+    hi = make_int2((int)q[4], (int)r[0]);
+}
+
+__device__ __forceinline__ void pk_store(unsigned long long *pk, int k, const int64_t *r, const Sched &sc)
+{
+    pk[2 * (int64_t)k] = (unsigned long long)r[1] | ((unsigned long long)r[2] << 21) | ((unsigned long long)r[3] << 42);
+    pk[2 * (int64_t)k + 1] = (unsigned long long)r[0] | ((unsigned long long)r[4] << sc.pk_bn) |
+                             ((unsigned long long)r[5] << (sc.pk_bn + sc.pk_bx));
 }
 
 // E' in fp64 from a means record: m A - <c', I> - <mu', P> + w_bnd 2^(2F) bnd
@@ -856,10 +916,18 @@ __device__ __forceinline__ void refine_job(const Job &J, const Sched &sc, const 
     const int W = J.W, H = J.H, K = J.K;
     int64_t *st;
     int32_t *mn, *fl;
+    unsigned long long *pk = nullptr;   // residency 4: packed statistics in LDS
     if (SL == 1) {
         st = reinterpret_cast<int64_t *>(smem);
         mn = reinterpret_cast<int32_t *>(st + 6 * (int64_t)K);   // K records of 16 bytes, 16-byte aligned
         fl = mn + MN_STRIDE * (int64_t)K;
+    } else if (SL == 4) {
+        // the sums in two words per superpixel, then the flow counters; no
+        // means records: the means are computed where they are read
+        st = J.stats;
+        mn = nullptr;
+        pk = reinterpret_cast<unsigned long long *>(smem);
+        fl = reinterpret_cast<int32_t *>(pk + 2 * (int64_t)K);
     } else if (SL == 2 || SL == 3) {
         st = J.stats;
         mn = reinterpret_cast<int32_t *>(smem);
@@ -915,7 +983,10 @@ __device__ __forceinline__ void refine_job(const Job &J, const Sched &sc, const 
         // the block-sum pyramid, grid initialisation (Algorithm RAPID,
         // first step) and the statistics, computed once for all levels
         // (Sec. 3.2)
-        for (int64_t i = tid; i < 6 * (int64_t)K; i += nt) st[i] = 0;
+        if (SL == 4)
+            for (int64_t i = tid; i < 2 * (int64_t)K; i += nt) pk[i] = 0;
+        else
+            for (int64_t i = tid; i < 6 * (int64_t)K; i += nt) st[i] = 0;
         if (flags & FLAG_PYRAMID) build_pyramid(J, sc, tid, nt);
         else wg_sync();
         const int B0 = sc.B[0];
@@ -930,19 +1001,26 @@ __device__ __forceinline__ void refine_job(const Job &J, const Sched &sc, const 
             L[i] = k;
             int64_t I[3];
             block_rgb(J, 0, B0, i, bx, by, I);
-            int64_t *r = st + 6 * (int64_t)k;
-            add64(r + 0, g.m);
-            add64(r + 1, I[0]);
-            add64(r + 2, I[1]);
-            add64(r + 3, I[2]);
-            add64(r + 4, g.px);
-            add64(r + 5, g.py);
+            if (SL == 4) {
+                pk_add(pk + 2 * (int64_t)k, g.m, I[0], I[1], I[2], g.px, g.py, sc);
+            } else {
+                int64_t *r = st + 6 * (int64_t)k;
+                add64(r + 0, g.m);
+                add64(r + 1, I[0]);
+                add64(r + 2, I[1]);
+                add64(r + 3, I[2]);
+                add64(r + 4, g.px);
+                add64(r + 5, g.py);
+            }
         }
     } else if (SL == 1) {
         for (int64_t i = tid; i < 6 * (int64_t)K; i += nt) st[i] = J.stats[i];
+    } else if (SL == 4) {
+        for (int k = tid; k < K; k += nt) pk_store(pk, k, J.stats + 6 * (int64_t)k, sc);
     }
     wg_sync();
-    for (int k = tid; k < K; k += nt) refresh_sp(st, mn, k, sc);
+    if (SL != 4)
+        for (int k = tid; k < K; k += nt) refresh_sp(st, mn, k, sc);
     wg_sync();
 
     int out_stage = s_end - 1;   // stage whose label map the output reads
@@ -958,11 +1036,23 @@ __device__ __forceinline__ void refine_job(const Job &J, const Sched &sc, const 
             // keeps its own means; the records are rebuilt afterwards).  A
             // larger band of the label map per pass means fewer passes.
             const uint32_t gp_off = SL == 1 ? lp.off_lists : 0u;
+            if (SL == 4) {
+                // the features read the sums from global memory; the gate
+                // point then borrows their LDS, and they come back after it
+                for (int k = tid; k < K; k += nt) {
+                    int64_t r[6];
+                    pk_unpack(pk + 2 * (int64_t)k, r, sc);
+                    for (int q = 0; q < 6; q++) J.stats[6 * (int64_t)k + q] = r[q];
+                }
+                wg_sync();
+            }
             gate_point(J, st, s - 1, sc.B[s - 1], sc.F, sc.feat_set, sc.mlp_w, sc.mlp_thresh, smem + gp_off,
                        lp.total - gp_off, tid, nt);
             if (SL == 2 || SL == 3)
                 for (int k = tid; k < K; k += nt) refresh_sp(st, mn, k, sc);
-            if (SL == 3)   // the flow counters are zero between class phases
+            if (SL == 4)
+                for (int k = tid; k < K; k += nt) pk_store(pk, k, J.stats + 6 * (int64_t)k, sc);
+            if (SL == 3 || SL == 4)   // the flow counters are zero between class phases
                 for (int64_t i = tid; i < 2 * (int64_t)K; i += nt) fl[i] = 0;
             // the frontier bitmap shares that LDS and must start the stage clear
             for (int i = tid; i < lp.bm_words; i += nt) l_bm[i] = 0;
@@ -1143,7 +1233,8 @@ __device__ __forceinline__ void refine_job(const Job &J, const Sched &sc, const 
                         m = g.m;
                         int4 ra;
                         int2 rb;
-                        load_mn(mn, a, ra, rb);
+                        if (SL == 4) pk_means(pk, a, sc, ra, rb);
+                        else load_mn(mn, a, ra, rb);
                         if ((int64_t)rb.y - g.m < sc.min_size) {
                             smin = true;
                             if (MERGE) merge_ask(J, a, &s_nreq);
@@ -1181,7 +1272,8 @@ __device__ __forceinline__ void refine_job(const Job &J, const Sched &sc, const 
                                         if (k == INT32_MAX || (u > 0 && k == cs[u - 1])) continue;
                                         int4 ka;
                                         int2 kb;
-                                        load_mn(mn, k, ka, kb);
+                                        if (SL == 4) pk_means(pk, k, sc, ka, kb);
+                                        else load_mn(mn, k, ka, kb);
                                         if ((int64_t)kb.y + g.m > sc.max_size) continue;
                                         int bnd = 0;
 #pragma unroll
@@ -1200,7 +1292,8 @@ __device__ __forceinline__ void refine_job(const Job &J, const Sched &sc, const 
                                         if (k == INT32_MAX || (u > 0 && k == cs[u - 1])) continue;
                                         int4 ka;
                                         int2 kb;
-                                        load_mn(mn, k, ka, kb);
+                                        if (SL == 4) pk_means(pk, k, sc, ka, kb);
+                                        else load_mn(mn, k, ka, kb);
                                         if ((int64_t)kb.y + g.m > sc.max_size) continue;
                                         int bnd = 0;
 #pragma unroll
@@ -1242,7 +1335,47 @@ __device__ __forceinline__ void refine_job(const Job &J, const Sched &sc, const 
                 // ---- P2: class-wide size filter, commit, stat moves.  Two
                 // lanes per proposal: lane 0 moves the block's sums out of the
                 // source a (and writes the label), lane 1 into the target k.
-                for (int e0 = 0; e0 < 2 * np; e0 += nt) {
+                if (SL == 4) {
+                    // packed statistics: every decision first, on the sizes
+                    // at class start (the moves below change them), kept in
+                    // the record's pad; the moves and the flow counters'
+                    // clearing follow, so no refresh pass is needed
+                    for (int e = tid; e < np; e += nt) {
+                        Prop *rp = e < capp ? l_props + e : g_props + e;
+                        const int32_t a = rp->a, k = rp->k;
+                        rp->pad = (pk_size(pk, a, sc) - fl[2 * a] >= sc.min_size &&
+                                   pk_size(pk, k, sc) + fl[2 * k + 1] <= sc.max_size)
+                                      ? 1
+                                      : 0;
+                    }
+                    wg_sync();
+                    for (int e0 = 0; e0 < 2 * np; e0 += nt) {
+                        const int e = (e0 + tid) >> 1, side = (e0 + tid) & 1;
+                        bool com = false;
+                        int32_t bi = 0;
+                        if (e < np) {
+                            const Prop rec = e < capp ? l_props[e] : g_props[e];
+                            bi = rec.bi;
+                            const int32_t sp = side ? rec.k : rec.a;
+                            com = rec.pad != 0;
+                            if (com) {
+                                const int bx = bi % nbx, by = bi / nbx;
+                                const Geo g = block_geo(bx, by, B, W, H);
+                                const int64_t sg = side ? 1 : -1;
+                                pk_add(pk + 2 * (int64_t)sp, sg * g.m, sg * (int64_t)(rec.I & 0x1FFFFFull),
+                                       sg * (int64_t)((rec.I >> 21) & 0x1FFFFFull), sg * (int64_t)(rec.I >> 42),
+                                       sg * g.px, sg * g.py, sc);
+                                if (mv)
+                                    atomicAdd(reinterpret_cast<unsigned long long *>(mv + sp), (unsigned long long)g.m);
+                                if (side == 0) L[bi] = rec.k;
+                            }
+                            fl[2 * sp + side] = 0;
+                        }
+                        int slot = wave_append(&s_nchg, com && side == 0);
+                        if (slot >= 0) list_put(l_chg, capx, J.changed, 0, slot, bi);
+                    }
+                }
+                for (int e0 = 0; SL != 4 && e0 < 2 * np; e0 += nt) {
                     const int e = (e0 + tid) >> 1, side = (e0 + tid) & 1;
                     bool com = false;
                     int32_t bi = 0;
@@ -1285,7 +1418,7 @@ __device__ __forceinline__ void refine_job(const Job &J, const Sched &sc, const 
                 // a proposal its source, lane 1 its target; a superpixel in
                 // several moves is refreshed several times with identical
                 // values) and clear the flow counters
-                for (int q = tid; q < 2 * np; q += nt) {
+                for (int q = tid; SL != 4 && q < 2 * np; q += nt) {
                     const int e = q >> 1, side = q & 1;
                     const Prop rec = e < capp ? l_props[e] : g_props[e];
                     const int32_t sp = side ? rec.k : rec.a;
@@ -1385,6 +1518,12 @@ __device__ __forceinline__ void refine_job(const Job &J, const Sched &sc, const 
     }
     if (SL == 1)
         for (int64_t i = tid; i < 6 * (int64_t)K; i += nt) J.stats[i] = st[i];
+    if (SL == 4)
+        for (int k = tid; k < K; k += nt) {
+            int64_t r[6];
+            pk_unpack(pk + 2 * (int64_t)k, r, sc);
+            for (int q = 0; q < 6; q++) J.stats[6 * (int64_t)k + q] = r[q];
+        }
     if ((flags & FLAG_OUT) && s_end > 0 && J.tile) {
         // slide tile: core pixels only, labels as slide-wide cell ids
         const int B = sc.B[out_stage];
@@ -1965,14 +2104,19 @@ hipError_t launch_refine(const Job *jobs_dev, int n_jobs, uint32_t *queue, int w
     // instantiations: where the per-superpixel state lives, gate mode, merge
     // on underflow
 #define RAPID_K(sl, gm) {k_refine<sl, gm, false>, k_refine<sl, gm, true>}
-    static const Kern table[4][3][2] = {
+    // residency 4 (packed statistics) has no merge on underflow
+#define RAPID_K4(gm) {k_refine<4, gm, false>, nullptr}
+    static const Kern table[5][3][2] = {
         {RAPID_K(0, GM_NONE), RAPID_K(0, GM_BITS), RAPID_K(0, GM_FUSED)},
         {RAPID_K(1, GM_NONE), RAPID_K(1, GM_BITS), RAPID_K(1, GM_FUSED)},
         {RAPID_K(2, GM_NONE), RAPID_K(2, GM_BITS), RAPID_K(2, GM_FUSED)},
-        {RAPID_K(3, GM_NONE), RAPID_K(3, GM_BITS), RAPID_K(3, GM_FUSED)}};
+        {RAPID_K(3, GM_NONE), RAPID_K(3, GM_BITS), RAPID_K(3, GM_FUSED)},
+        {RAPID_K4(GM_NONE), RAPID_K4(GM_BITS), RAPID_K4(GM_FUSED)}};
 #undef RAPID_K
+#undef RAPID_K4
     const int gm = (flags & FLAG_GATE) ? GM_FUSED : lp.gate_words > 0 ? GM_BITS : GM_NONE;
     const Kern fn = table[lp.stats_lds][gm][sc.merge ? 1 : 0];
+    if (!fn) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp.total);
     if (e != hipSuccess) return e;
     // the persistent launch: wgs workgroups, or (wgs == 0) as many as the
