@@ -81,6 +81,7 @@ struct rapid_state {
     int64_t *zero_dev = nullptr;   // a device 0 (row offset of the state's features)
     uint32_t *err_dev = nullptr;   // import: violation flag
     float *xbuf = nullptr;         // rapid_gate: feature rows when the caller passes none
+    bool imported = false;         // statistics or labels came from rapid_state_import
     char *mem = nullptr;
     Sched sc{};
     int32_t level_first[RAPID_MAX_LEVELS + 1] = {};
@@ -325,7 +326,7 @@ Layout plan(int32_t W, int32_t H, int32_t K, const Sched &sc, int moms_stage = -
     L.off_stamp = take(4 * nbF);
     L.off_stats = take(8 * 6 * (size_t)K);
     L.off_means = take(4 * MN_STRIDE * (size_t)K);
-    L.off_flow = take(4 * 2 * (size_t)K);
+    L.off_flow = take(4 * 4 * (size_t)K);
     L.off_rep = take(sizeof(rapid_stage_report) * MAXST);
     L.off_ctl = take(4 * (size_t)CTL_WORDS);
     L.off_fmean = take(4 * 3 * (size_t)K);
@@ -428,7 +429,7 @@ inline int bit_length(uint64_t v) { return v ? 64 - __builtin_clzll(v) : 0; }
 bool set_packing(Sched &sc, const Job *jobs, size_t n, int flags)
 {
     sc.pk_bn = sc.pk_bx = 0;
-    if (!(flags & FLAG_INIT) || sc.merge) return false;
+    if (!(flags & (FLAG_INIT | FLAG_OWN_STATS)) || sc.merge) return false;
     int bn = 1, bx = 1, by = 1;
     const int B0 = sc.B[0];
     for (size_t j = 0; j < n; j++) {
@@ -1272,7 +1273,7 @@ static rapid_status gated_impl(rapid_ctx *ctx, const rapid_image *imgs, int32_t 
         // covers both launches and the gate's launches between them
         const bool timing = ctx->timing;
         ctx->timing = false;
-        r = run_jobs(ctx, b.jobs, b.sc, gs, b.sc.n_stages, FLAG_OUT, b.Kmax, b.nbF_max, &first);
+        r = run_jobs(ctx, b.jobs, b.sc, gs, b.sc.n_stages, FLAG_OUT | FLAG_OWN_STATS, b.Kmax, b.nbF_max, &first);
         ctx->timing = timing;
         if (r) return r;
         if (timing) HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
@@ -1445,7 +1446,9 @@ rapid_status rapid_refine_level(rapid_ctx *ctx, rapid_state *st, int32_t level, 
     std::vector<Job> jobs(1, st->job);
     int Bf = sc.B[sc.n_stages - 1];
     int64_t nbF = (int64_t)((st->W + Bf - 1) / Bf) * ((st->H + Bf - 1) / Bf);
-    rapid_status r = run_jobs(ctx, jobs, sc, s0, s1, 0, st->job.K, nbF);
+    // statistics this library made from the grid keep the grid's bounds
+    // (packed statistics allowed); imported ones need not
+    rapid_status r = run_jobs(ctx, jobs, sc, s0, s1, st->imported ? 0 : FLAG_OWN_STATS, st->job.K, nbF);
     if (r) return r;
     st->next_level = level + 1;
     st->map_stage = s1 - 1;
@@ -1526,6 +1529,7 @@ rapid_status rapid_state_import(rapid_ctx *ctx, rapid_state *st, int32_t next_le
     const int s = next_level == 0 ? 0 : st->level_first[next_level] - 1;
     const int B = st->sc.B[s];
     int32_t *L = st->job.lab[s & 1];
+    st->imported = true;
     HIPCHK(hipMemsetAsync(st->err_dev, 0, 4, ctx->stream));
     HIPCHK(launch_import_labels(labels_dev, st->W, st->W, st->H, B, st->job.K, L, st->err_dev, ctx->stream));
     if (stats_dev) {

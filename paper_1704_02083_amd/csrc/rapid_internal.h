@@ -17,7 +17,10 @@ constexpr int MAX_GATE_WORDS = 8192;
 // (features, network, gate bits) and track moved pixels before it;
 // FLAG_PYRAMID: with FLAG_INIT, each workgroup builds its job's block-sum
 // pyramid (else separate launches have).
-enum { FLAG_INIT = 1, FLAG_OUT = 2, FLAG_GATE = 4, FLAG_PYRAMID = 8 };
+// FLAG_OWN_STATS: without FLAG_INIT, the statistics at the launch's start
+// were made by this library from the grid (not imported), so their bounds
+// are those of a launch from the image.
+enum { FLAG_INIT = 1, FLAG_OUT = 2, FLAG_GATE = 4, FLAG_PYRAMID = 8, FLAG_OWN_STATS = 16 };
 
 // jobs from which the refinement launch builds the block-sum pyramids itself
 constexpr int PYRAMID_MIN_JOBS = 128;
@@ -79,7 +82,8 @@ struct Job {
     int32_t *stamp;          // per block visit stamp (when the LDS bitmap is too small)
     int64_t *stats;          // K x 6 int64: n, S_r, S_g, S_b, T_x, T_y
     int32_t *means;          // K records of MN_STRIDE words (global working set)
-    int32_t *flow;           // K x 2 out/in (global working set)
+    int32_t *flow;           // K x 2 out/in (global working set), twice
+                             // (the cooperative kernel alternates buffers)
     rapid_stage_report *rep; // per stage
     const uint8_t *gate;     // K bytes or null
     // optional tracking (null: off)

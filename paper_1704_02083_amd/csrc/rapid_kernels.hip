@@ -797,12 +797,16 @@ __device__ __attribute__((noinline)) void gate_point(const Job &J, const int64_t
 // source and its distinct 4-neighbour labels that stay within the maximum
 // size (Eq. (3); ties keep the source or the smaller label).  Reads the
 // class-start state only.
+template <bool PK>
 __device__ __forceinline__ void propose_block(const Job &J, int s, int B, int32_t bi, int nbx, int nby, int W,
                                               int H, const int32_t *L, const int32_t *mn, const uint32_t *s_lut,
                                               const Sched &sc, const GateView &gv, bool use_f64, int32_t &a,
                                               int32_t &best, int64_t &m, uint64_t &Ipk, bool &prop, bool &smin,
-                                              bool &stopo)
+                                              bool &stopo, int64_t &na, int64_t &nk)
 {
+    // PK: mn holds the packed statistics (two words per superpixel) and the
+    // means are computed from them
+    const unsigned long long *pk = reinterpret_cast<const unsigned long long *>(mn);
     const int bx = bi % nbx, by = bi / nbx;
     const bool hw = bx > 0, he = bx + 1 < nbx, hn = by > 0, hs = by + 1 < nby;
     // every global load of the block at once: its label,
@@ -825,7 +829,10 @@ __device__ __forceinline__ void propose_block(const Job &J, int s, int B, int32_
     m = g.m;
     int4 ra;
     int2 rb;
-    load_mn(mn, a, ra, rb);
+    if (PK) pk_means(pk, a, sc, ra, rb);
+    else load_mn(mn, a, ra, rb);
+    na = rb.y;
+    nk = 0;
     if ((int64_t)rb.y - g.m < sc.min_size) {
         smin = true;
     } else {
@@ -862,7 +869,8 @@ __device__ __forceinline__ void propose_block(const Job &J, int s, int B, int32_
                     if (k == INT32_MAX || (u > 0 && k == cs[u - 1])) continue;
                     int4 ka;
                     int2 kb;
-                    load_mn(mn, k, ka, kb);
+                    if (PK) pk_means(pk, k, sc, ka, kb);
+                    else load_mn(mn, k, ka, kb);
                     if ((int64_t)kb.y + g.m > sc.max_size) continue;
                     int bnd = 0;
 #pragma unroll
@@ -871,6 +879,7 @@ __device__ __forceinline__ void propose_block(const Job &J, int s, int B, int32_
                     if (ek < estar) {
                         estar = ek;
                         best = k;
+                        nk = kb.y;
                     }
                 }
             } else {
@@ -881,7 +890,8 @@ __device__ __forceinline__ void propose_block(const Job &J, int s, int B, int32_
                     if (k == INT32_MAX || (u > 0 && k == cs[u - 1])) continue;
                     int4 ka;
                     int2 kb;
-                    load_mn(mn, k, ka, kb);
+                    if (PK) pk_means(pk, k, sc, ka, kb);
+                    else load_mn(mn, k, ka, kb);
                     if ((int64_t)kb.y + g.m > sc.max_size) continue;
                     int bnd = 0;
 #pragma unroll
@@ -890,6 +900,7 @@ __device__ __forceinline__ void propose_block(const Job &J, int s, int B, int32_
                     if (ek < estar) {
                         estar = ek;
                         best = k;
+                        nk = kb.y;
                     }
                 }
             }
@@ -1651,7 +1662,12 @@ __device__ __forceinline__ void class_push_wg(bool e, int cls, int32_t v, int32_
         if (!grid_sync(ctl, bar, &s_ok)) return;   \
     } while (0)
 
-template <int GM>
+// PK: packed statistics (two words per superpixel in J.means, updated with
+// device-scope atomics; the means are computed where they are read), the
+// flow counters and the proposal counter double-buffered by class phase, so
+// that a class fitting one pass needs two grid barriers instead of three
+// and no refresh pass.
+template <int GM, bool PK>
 __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs, Sched sc, int s_begin, int s_end,
                                                     int flags, const uint32_t *__restrict__ lut_g, int64_t solo_max)
 {
@@ -1670,6 +1686,7 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
     const int W = J.W, H = J.H, K = J.K;
     int64_t *const st = J.stats;
     int32_t *const mn = J.means, *const fl = J.flow;
+    unsigned long long *const pk = reinterpret_cast<unsigned long long *>(J.means);
     uint32_t *const ctl = J.ctl;
     unsigned long long *const ctr = reinterpret_cast<unsigned long long *>(ctl + CTL_CTR);
     Prop *const props = J.props;
@@ -1683,7 +1700,7 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
     if (tid < 8) s_lut[tid] = lut_g[tid];
     if (tid < 9) l_cnt[tid] = 0;
     if (tid < 2) s_skip[tid] = 0;
-    for (int64_t i = gt; i < 2 * (int64_t)K; i += gn) fl[i] = 0;
+    for (int64_t i = gt; i < (PK ? 4 : 2) * (int64_t)K; i += gn) fl[i] = 0;
     if (s_end > s_begin) {
         // visit stamps are unique per (stage, sweep) of this launch
         const int Bf = sc.B[s_end - 1];
@@ -1692,7 +1709,10 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
     }
     if (flags & FLAG_INIT) {
         // grid initialisation and statistics (Algorithm RAPID, first step)
-        for (int64_t i = gt; i < 6 * (int64_t)K; i += gn) st[i] = 0;
+        if (PK)
+            for (int64_t i = gt; i < 2 * (int64_t)K; i += gn) pk[i] = 0;
+        else
+            for (int64_t i = gt; i < 6 * (int64_t)K; i += gn) st[i] = 0;
         MC_SYNC();
         const int B0 = sc.B[0];
         const int nbx = (W + B0 - 1) / B0, nby = (H + B0 - 1) / B0;
@@ -1706,18 +1726,31 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
             L[i] = k;
             int64_t I[3];
             block_rgb(J, 0, B0, i, bx, by, I);
-            int64_t *r = st + 6 * (int64_t)k;
-            add64(r + 0, g.m);
-            add64(r + 1, I[0]);
-            add64(r + 2, I[1]);
-            add64(r + 3, I[2]);
-            add64(r + 4, g.px);
-            add64(r + 5, g.py);
+            if (PK) {
+                pk_add(pk + 2 * (int64_t)k, g.m, I[0], I[1], I[2], g.px, g.py, sc);
+            } else {
+                int64_t *r = st + 6 * (int64_t)k;
+                add64(r + 0, g.m);
+                add64(r + 1, I[0]);
+                add64(r + 2, I[1]);
+                add64(r + 3, I[2]);
+                add64(r + 4, g.px);
+                add64(r + 5, g.py);
+            }
         }
+    } else if (PK) {
+        for (int64_t k = gt; k < K; k += gn) pk_store(pk, (int)k, st + 6 * k, sc);
     }
     MC_SYNC();
-    for (int64_t k = gt; k < K; k += gn) refresh_sp(st, mn, (int)k, sc);
-    MC_SYNC();
+    if (!PK) {
+        for (int64_t k = gt; k < K; k += gn) refresh_sp(st, mn, (int)k, sc);
+        MC_SYNC();
+    }
+    // PK: the phases of a sweep alternate between two flow buffers and two
+    // proposal counters; a lane clears the flows of its last one-pass
+    // proposal at the start of the next phase that runs, or at the sweep's
+    // end
+    int32_t pend_a = -1, pend_k = -1;
 
     // Class counts are double-buffered: the sweep reads cnt[par] while the
     // frontier rebuild fills cnt[par ^ 1]; the changed-block counter of a
@@ -1813,6 +1846,7 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
             // workgroup barriers; the other workgroups wait at its end.
             const bool solo = tot <= solo_max;
             const int64_t first = solo ? 0 : wg0, step = solo ? (int64_t)nt : gn;
+            uint32_t cph = 0;   // PK: phases run so far in this sweep
 #define SW_SYNC()              \
     do {                       \
         if (solo)              \
@@ -1833,6 +1867,24 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
                     const int ncls = ctl_read(cnt, c);   // stable during the sweep
                     if (ncls == 0) continue;
                     const int32_t *llst = J.lists + c * capg;
+                    // PK: this phase's flow buffer and proposal counter; the
+                    // previous phase's counter and this lane's flows in the
+                    // other buffer are cleared (their readers passed a
+                    // barrier since, or read a counter that stayed 0; their
+                    // next writers come after this phase's first barrier)
+                    const uint32_t pb = cph & 1;
+                    int32_t *const flc = PK ? fl + 2 * (int64_t)K * pb : fl;
+                    const int nprop_w = PK ? CTL_NPROP + (int)pb : CTL_NPROP;
+                    if (PK) {
+                        if (cph > 0 && gt == 0) ctl[CTL_NPROP + (pb ^ 1)] = 0;
+                        if (pend_a >= 0) {
+                            int32_t *const flo = fl + 2 * (int64_t)K * (pb ^ 1);
+                            flo[2 * (int64_t)pend_a] = 0;
+                            flo[2 * (int64_t)pend_k + 1] = 0;
+                            pend_a = -1;
+                        }
+                        cph++;
+                    }
                     if (ncls <= step) {
                         // One pass: every lane keeps its block's proposal in
                         // registers through P2 and P3 (no proposal records;
@@ -1842,10 +1894,11 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
                         int32_t bi = 0, a = 0, best = 0;
                         int64_t m = 0;
                         uint64_t Ipk = 0;
+                        int64_t na = 0, nk = 0;   // class-start sizes of a and best
                         if (e < ncls) {
                             bi = llst[e];
-                            propose_block(J, s, B, bi, nbx, nby, W, H, L, mn, s_lut, sc, gv, use_f64, a, best, m, Ipk,
-                                          prop, smin, stopo);
+                            propose_block<PK>(J, s, B, bi, nbx, nby, W, H, L, mn, s_lut, sc, gv, use_f64, a, best, m,
+                                              Ipk, prop, smin, stopo, na, nk);
                         }
                         n_smin += smin;
                         n_stopo += stopo;
@@ -1855,30 +1908,37 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
                         }
                         const uint64_t pm = __ballot(prop);
                         if (pm != 0 && lane_id() == __ffsll((unsigned long long)pm) - 1)
-                            atomicAdd(&ctl[CTL_NPROP], (uint32_t)__popcll(pm));
+                            atomicAdd(&ctl[nprop_w], (uint32_t)__popcll(pm));
                         if (prop) {
-                            atomicAdd(&fl[2 * (int64_t)a], (int32_t)m);
-                            atomicAdd(&fl[2 * (int64_t)best + 1], (int32_t)m);
+                            atomicAdd(&flc[2 * (int64_t)a], (int32_t)m);
+                            atomicAdd(&flc[2 * (int64_t)best + 1], (int32_t)m);
                         }
                         SW_SYNC();
-                        const int np = ctl_read(ctl, CTL_NPROP);
+                        const int np = ctl_read(ctl, nprop_w);
                         if (np == 0) continue;   // uniform
                         // ---- P2: size filter on the class-wide flows, commit
                         // (both sides of the move in one lane)
                         bool com = false;
                         if (prop) {
-                            com = mn_size(mn, a) - fl[2 * (int64_t)a] >= sc.min_size &&
-                                  mn_size(mn, best) + fl[2 * (int64_t)best + 1] <= sc.max_size;
+                            com = PK ? (na - flc[2 * (int64_t)a] >= sc.min_size &&
+                                        nk + flc[2 * (int64_t)best + 1] <= sc.max_size)
+                                     : (mn_size(mn, a) - fl[2 * (int64_t)a] >= sc.min_size &&
+                                        mn_size(mn, best) + fl[2 * (int64_t)best + 1] <= sc.max_size);
                             if (com) {
                                 const Geo g = block_geo(bi % nbx, bi / nbx, B, W, H);
                                 const int64_t d[6] = {g.m, (int64_t)(Ipk & 0x1FFFFFull),
                                                       (int64_t)((Ipk >> 21) & 0x1FFFFFull), (int64_t)(Ipk >> 42),
                                                       g.px, g.py};
-                                int64_t *ra = st + 6 * (int64_t)a, *rk = st + 6 * (int64_t)best;
+                                if (PK) {
+                                    pk_add(pk + 2 * (int64_t)a, -d[0], -d[1], -d[2], -d[3], -d[4], -d[5], sc);
+                                    pk_add(pk + 2 * (int64_t)best, d[0], d[1], d[2], d[3], d[4], d[5], sc);
+                                } else {
+                                    int64_t *ra = st + 6 * (int64_t)a, *rk = st + 6 * (int64_t)best;
 #pragma unroll
-                                for (int q = 0; q < 6; q++) {
-                                    add64(ra + q, -d[q]);
-                                    add64(rk + q, d[q]);
+                                    for (int q = 0; q < 6; q++) {
+                                        add64(ra + q, -d[q]);
+                                        add64(rk + q, d[q]);
+                                    }
                                 }
                                 if (mv) {
                                     atomicAdd(reinterpret_cast<unsigned long long *>(mv + a), (unsigned long long)g.m);
@@ -1890,6 +1950,16 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
                         }
                         const int slot = wave_append(nchg, com);
                         if (slot >= 0) J.changed[slot] = bi;
+                        if (PK) {
+                            // no refresh: the next phase computes the means
+                            if (prop) {
+                                pend_a = a;
+                                pend_k = best;
+                            }
+                            if (gt == 0) ctr[1] += (unsigned long long)np;
+                            SW_SYNC();
+                            continue;
+                        }
                         SW_SYNC();
                         // ---- P3: refresh the moved superpixels, clear the
                         // flow counters
@@ -1916,10 +1986,11 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
                         int32_t bi = 0, a = 0, best = 0;
                         int64_t m = 0;
                         uint64_t Ipk = 0;
+                        int64_t na = 0, nk = 0;
                         if (e < ncls) {
                             bi = llst[e];
-                            propose_block(J, s, B, bi, nbx, nby, W, H, L, mn, s_lut, sc, gv, use_f64, a, best, m, Ipk,
-                                          prop, smin, stopo);
+                            propose_block<PK>(J, s, B, bi, nbx, nby, W, H, L, mn, s_lut, sc, gv, use_f64, a, best, m,
+                                              Ipk, prop, smin, stopo, na, nk);
                         }
                         n_smin += smin;
                         n_stopo += stopo;
@@ -1927,7 +1998,7 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
                             J.involved[a] = 1;
                             J.involved[best] = 1;
                         }
-                        const int slot = wave_append(reinterpret_cast<int32_t *>(ctl + CTL_NPROP), prop);
+                        const int slot = wave_append(reinterpret_cast<int32_t *>(ctl + nprop_w), prop);
                         if (slot >= 0) {
                             Prop rec;
                             rec.bi = bi;
@@ -1936,13 +2007,55 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
                             rec.pad = 0;
                             rec.I = Ipk;
                             props[slot] = rec;
-                            atomicAdd(&fl[2 * (int64_t)a], (int32_t)m);
-                            atomicAdd(&fl[2 * (int64_t)best + 1], (int32_t)m);
+                            atomicAdd(&flc[2 * (int64_t)a], (int32_t)m);
+                            atomicAdd(&flc[2 * (int64_t)best + 1], (int32_t)m);
                         }
                     }
                     SW_SYNC();
-                    const int np = ctl_read(ctl, CTL_NPROP);
+                    const int np = ctl_read(ctl, nprop_w);
                     if (np == 0) continue;   // uniform
+                    if (PK) {
+                        // every decision on the class-start sizes first, then
+                        // the moves (packed, device-scope atomics), the label
+                        // writes and the flows' clearing
+                        for (int64_t e = first + tid; e < np; e += step) {
+                            const int32_t a = props[e].a, k = props[e].k;
+                            props[e].pad = (pk_size(pk, a, sc) - flc[2 * (int64_t)a] >= sc.min_size &&
+                                            pk_size(pk, k, sc) + flc[2 * (int64_t)k + 1] <= sc.max_size)
+                                               ? 1
+                                               : 0;
+                        }
+                        SW_SYNC();
+                        for (int64_t e0 = first; e0 < 2 * (int64_t)np; e0 += step) {
+                            const int64_t q = e0 + tid;
+                            const int e = (int)(q >> 1), side = (int)(q & 1);
+                            bool com = false;
+                            int32_t bi = 0;
+                            if (e < np) {
+                                const Prop rec = props[e];
+                                bi = rec.bi;
+                                const int32_t sp = side ? rec.k : rec.a;
+                                com = rec.pad != 0;
+                                if (com) {
+                                    const Geo g = block_geo(bi % nbx, bi / nbx, B, W, H);
+                                    const int64_t sg = side ? 1 : -1;
+                                    pk_add(pk + 2 * (int64_t)sp, sg * g.m, sg * (int64_t)(rec.I & 0x1FFFFFull),
+                                           sg * (int64_t)((rec.I >> 21) & 0x1FFFFFull), sg * (int64_t)(rec.I >> 42),
+                                           sg * g.px, sg * g.py, sc);
+                                    if (mv)
+                                        atomicAdd(reinterpret_cast<unsigned long long *>(mv + sp),
+                                                  (unsigned long long)g.m);
+                                    if (side == 0) L[bi] = rec.k;
+                                }
+                                flc[2 * (int64_t)sp + side] = 0;
+                            }
+                            const int slot = wave_append(nchg, com && side == 0);
+                            if (slot >= 0) J.changed[slot] = bi;
+                        }
+                        if (gt == 0) ctr[1] += (unsigned long long)np;
+                        SW_SYNC();
+                        continue;
+                    }
                     // ---- P2: class-wide size filter, commit, statistic
                     // moves (lane 0 of a proposal: source side and label
                     // write, lane 1 target side)
@@ -1996,6 +2109,20 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
                         ctl[CTL_NPROP] = 0;
                     }
                     SW_SYNC();
+                }
+                if (PK) {
+                    // the sweep's last phase: its flows and counters clear
+                    // before the next sweep (the barrier below orders them)
+                    if (pend_a >= 0) {
+                        int32_t *const flo = fl + 2 * (int64_t)K * ((cph - 1) & 1);
+                        flo[2 * (int64_t)pend_a] = 0;
+                        flo[2 * (int64_t)pend_k + 1] = 0;
+                        pend_a = -1;
+                    }
+                    if (gt == 0) {
+                        ctl[CTL_NPROP] = 0;
+                        ctl[CTL_NPROP + 1] = 0;
+                    }
                 }
                 SW_SYNC();
                 const int commits = ctl_read(ctl, CTL_NCHG + par);
@@ -2060,6 +2187,12 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
             for (int i = 0; i < 6; i++) ctr[i] = 0;
         }
     }
+    if (PK)   // the statistics out in their six-word layout
+        for (int64_t k = gt; k < K; k += gn) {
+            int64_t r[6];
+            pk_unpack(pk + 2 * k, r, sc);
+            for (int q = 0; q < 6; q++) st[6 * k + q] = r[q];
+        }
     if ((flags & FLAG_OUT) && s_end > 0) {
         const int B = sc.B[s_end - 1];
         const int nbx = (W + B - 1) / B;
@@ -2154,7 +2287,11 @@ hipError_t launch_refine_mc(const Job *jobs_dev, int groups, const Sched &sc, in
     Sched sc_arg = sc;
     void *args[] = {(void *)&jobs_dev, (void *)&sc_arg, (void *)&s_begin, (void *)&s_end, (void *)&flags,
                     (void *)&lut_dev, (void *)&solo_max};
-    const void *fn = gate_words > 0 ? (const void *)k_refine_mc<GM_BITS> : (const void *)k_refine_mc<GM_NONE>;
+    const bool pk = sc.pk_bn > 0;
+    const void *fn = gate_words > 0 ? (pk ? (const void *)k_refine_mc<GM_BITS, true>
+                                          : (const void *)k_refine_mc<GM_BITS, false>)
+                                    : (pk ? (const void *)k_refine_mc<GM_NONE, true>
+                                          : (const void *)k_refine_mc<GM_NONE, false>);
     return hipLaunchCooperativeKernel(fn, dim3((unsigned)groups), dim3((unsigned)threads), args,
                                       4 * (size_t)gate_words, stream);
 }
@@ -2169,10 +2306,15 @@ hipError_t max_coop_groups(int threads, int *out)
         return hipSuccess;
     }
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    // the instantiation that holds the most registers and LDS sets the bound
+    int per_cu_pk = 0;
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_refine_mc<GM_BITS>, threads,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_refine_mc<GM_BITS, false>, threads,
                                                          4 * MAX_GATE_WORDS);
-    *out = e == hipSuccess ? cus * per_cu : 0;
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_pk, (const void *)k_refine_mc<GM_BITS, true>,
+                                                         threads, 4 * MAX_GATE_WORDS);
+    *out = e == hipSuccess ? cus * std::min(per_cu, per_cu_pk) : 0;
     return e;
 }
 
