@@ -80,11 +80,13 @@ typedef struct {
      * problem shape (images, largest W, H and superpixel count, schedule,
      * gate and merge modes) runs its launch once per candidate shape --
      * workgroup size 256, 512 or 1024; per-superpixel state all in LDS,
-     * the means records and flow counters, only the means records, or
-     * nothing in LDS (as far as they fit); block-sum pyramid inside the
-     * launch or in separate launches; and, for a single image without gate
-     * or merge, the image spread over 8 .. 128 workgroups of a cooperative
-     * launch, with small sweeps on the whole grid or on one workgroup --
+     * the statistics packed with the flow counters (where the size bounds
+     * allow the packing), the means records and flow counters, only the
+     * means records, or nothing in LDS (as far as they fit); block-sum
+     * pyramid inside the launch or in separate launches; and, for a single
+     * image without merge, the image spread over 8 .. 128 workgroups of a
+     * cooperative launch, with small sweeps on the whole grid or on one
+     * workgroup --
      * and keeps the fastest (without tuning, a single image whose finest
      * stage has 2^20 blocks or more runs on 64 workgroups, sweeps of at
      * most 16384 active blocks on one); later calls of that
@@ -103,14 +105,14 @@ typedef struct {
     float block_sums_ms;   /* block-sum launches before the refinement
                               kernel (0 when that kernel builds the
                               pyramids itself)                        */
-    float refine_ms;       /* the refinement kernel (all stages); a gated
-                              single image run as separate launches: from
-                              the first refinement launch to the end of
-                              the last, the gate's launches included  */
+    float refine_ms;       /* the refinement kernel (all stages, and the
+                              gate point of a gated call)             */
     int32_t threads;       /* launch shape of that call: workgroup size, */
     int32_t stats_lds;     /* per-superpixel state: 1 all in LDS, 3 the
-                              means records and flow counters in LDS, 2
-                              the means records in LDS, 0 all global,   */
+                              means records and flow counters in LDS, 4
+                              the packed statistics and flow counters in
+                              LDS, 2 the means records in LDS, 0 all
+                              global,                                   */
     int32_t pyramid;       /* pyramid inside the refinement launch (1)   */
     int32_t tuned;         /* 1 when this call ran the autotuner         */
     int32_t workgroups;    /* workgroups per image: 1, or the size of the
@@ -338,12 +340,10 @@ typedef struct {
  * of 16 floats); gate_dev (nullable) the gate bits in the same order.
  * gate_level must be in [1, n_levels).  A model with non-finite weights is
  * refused: the images are segmented plain and RAPID_EGATE is returned.
- * Several images, or a single small one, run as one launch that decides the
- * gate inside; a single image of at least 2^20 pixels (or any single image
- * when RAPID_SHAPE asks for several workgroups per image) runs as the
- * levels before the gate, the feature and network launches, and the gated
- * levels, so that its refinement launches can spread over many
- * workgroups.  Both routes decide the same bits and labels. */
+ * Every call is one refinement launch that decides the gate inside (one
+ * workgroup per image, or a single image spread over the workgroups of a
+ * cooperative launch, which computes the features and the network across
+ * them); every launch shape decides the same bits and labels. */
 rapid_status rapid_segment_gated(rapid_ctx *ctx, const rapid_image *imgs, int32_t n,
                                  const rapid_params *params, const rapid_gate_model *model,
                                  float *features_dev, uint8_t *gate_dev, rapid_report *reports);

@@ -692,10 +692,9 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
     // launch shape: the tuned one for this problem shape, else the default
     // (enough jobs to fill the chip: the pyramid inside the launch)
     // a single image may spread over the workgroups of a cooperative launch
-    // (no merge, not a slide tile, no gate evaluated inside the launch)
+    // (no merge, not a slide tile)
     int coop_max = 0;
-    if (n == 1 && !sc.merge && !jobs[0].tile && !(flags & FLAG_GATE))
-        HIPCHK(max_coop_groups(1024, &coop_max));
+    if (n == 1 && !sc.merge && !jobs[0].tile) HIPCHK(max_coop_groups(1024, &coop_max));
     LaunchShape sh;
     sh.threads = ctx->threads;
     sh.stats_lds = lds_residency(ctx->lds_limit, Kmax, gated, 1, packable);
@@ -1245,46 +1244,12 @@ static rapid_status gated_impl(rapid_ctx *ctx, const rapid_image *imgs, int32_t 
     if (r) return r;
     b.sc.mlp_w = model->w_bf16_dev;
     b.sc.mlp_thresh = model->thresh;
-    int coop_max = 0;
-    if (n == 1 && !tiles && !b.sc.merge) HIPCHK(max_coop_groups(1024, &coop_max));
-    // separate launches for a large image, or when a fixed launch shape
-    // spreads images over many workgroups
-    const bool large = (int64_t)imgs[0].W * imgs[0].H >= ((int64_t)1 << 20);
-    if (coop_max > 1 && (ctx->shape_forced ? ctx->forced.groups > 1 : large)) {
-        // A large single image: the levels before the gate, then the
-        // features and the network's decision (Eq. (6)) in launches of
-        // their own, then the levels under the gate (Eq. (7)); both
-        // refinement launches may spread over many workgroups.  The gate
-        // bits equal those of the single launch below (same features).
-        Job &J = b.jobs[0];
-        const int gs = b.sc.gate_stage;
-        HIPCHK(hipMemsetAsync(J.moved, 0, 8 * (size_t)J.K, ctx->stream));
-        HIPCHK(hipMemsetAsync(b.xoff_dev, 0, 8, ctx->stream));
-        J.gate = nullptr;
-        if ((r = run_jobs(ctx, b.jobs, b.sc, 0, gs, FLAG_INIT, b.Kmax, b.nbF_max))) return r;
-        const LaunchShape first = ctx->last;
-        HIPCHK(launch_features(ctx->jobs_dev, 1, b.sc.B[gs - 1], (gs - 1) & 1, b.sc.F, b.sc.feat_set, J.K,
-                               b.max_nb[gs - 1],
-                               b.xoff_dev, b.X, ctx->stream));
-        HIPCHK(launch_mlp_fwd(b.X, J.K, model->w_bf16_dev, model->thresh, nullptr, b.gates, ctx->stream));
-        J.gate = b.gates;
-        J.moved = nullptr;
-        // the timings keep the first launch's start: the refinement time then
-        // covers both launches and the gate's launches between them
-        const bool timing = ctx->timing;
-        ctx->timing = false;
-        r = run_jobs(ctx, b.jobs, b.sc, gs, b.sc.n_stages, FLAG_OUT | FLAG_OWN_STATS, b.Kmax, b.nbF_max, &first);
-        ctx->timing = timing;
-        if (r) return r;
-        if (timing) HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
-    } else {
-        // one launch: the levels before the gate, then in every workgroup
-        // the features of its superpixels and the network's decision
-        // (Eq. (6)), then the finer levels under the gate (Eq. (7))
-        if ((r = run_jobs(ctx, b.jobs, b.sc, 0, b.sc.n_stages, FLAG_INIT | FLAG_OUT | FLAG_GATE, b.Kmax,
-                          b.nbF_max)))
-            return r;
-    }
+    // one launch: the levels before the gate, then the features of the
+    // superpixels and the network's decision (Eq. (6)), then the finer levels
+    // under the gate (Eq. (7)); a single image may spread over the workgroups
+    // of a cooperative launch, which runs the gate point across them
+    if ((r = run_jobs(ctx, b.jobs, b.sc, 0, b.sc.n_stages, FLAG_INIT | FLAG_OUT | FLAG_GATE, b.Kmax, b.nbF_max)))
+        return r;
     if (features_dev)
         HIPCHK(hipMemcpyAsync(features_dev, b.X, 4 * 16 * (size_t)b.Ktot, hipMemcpyDeviceToDevice, ctx->stream));
     if (gate_dev)

@@ -1657,6 +1657,44 @@ __device__ __forceinline__ void class_push_wg(bool e, int cls, int32_t v, int32_
     if (e) glob[cls * capg + l_base[cls] + slot] = v;
 }
 
+// The gate point of a cooperative launch (one image on G workgroups,
+// Algorithm RAPID's prediction step before the gated level): the features of
+// every superpixel on the labels of stage stage_q (the statistics in their
+// six-word layout in J.stats), then the network's decision (Eq. (6)) into
+// J.gate_out, each pass spread over the grid and closed by a grid barrier.
+// Returns false when a barrier gave up (the caller leaves the kernel).
+// Kept out of line so that the sweep's registers do not carry it.
+__device__ __forceinline__ bool gate_point_mc(const Job &J, const Sched &sc, int stage_q, int64_t gt,
+                                                         int64_t gn, uint32_t *ctl, uint32_t &bar, int32_t *s_ok)
+{
+    const int K = J.K, F = sc.F;
+    const int Bq = sc.B[stage_q];
+    const int nbxq = (J.W + Bq - 1) / Bq, nbyq = (J.H + Bq - 1) / Bq;
+    const int32_t *Lq = J.lab[stage_q & 1];
+    const uint32_t *moms = (J.moms && J.moms_stage == stage_q) ? J.moms : nullptr;
+    for (int64_t k = gt; k < K; k += gn) feat_init_sp(J.stats, J.fmean, J.facc, (int)k, F);
+    if (!grid_sync(ctl, bar, s_ok)) return false;
+    const int spr = (nbxq + FEAT_SEG - 1) / FEAT_SEG;
+    for (int64_t g = gt; g < (int64_t)spr * nbyq; g += gn) {
+        const int by = (int)(g / spr), bx0 = (int)(g % spr) * FEAT_SEG;
+        const int32_t *row = Lq + (int64_t)by * nbxq;
+        feat_segment(J, row, by > 0 ? row - nbxq : nullptr, by + 1 < nbyq ? row + nbxq : nullptr, Bq, nbxq, by, bx0,
+                     min(bx0 + FEAT_SEG, nbxq), moms, J.fmean, GlobalSink{J.facc});
+    }
+    if (!grid_sync(ctl, bar, s_ok)) return false;
+    for (int64_t k = gt; k < K; k += gn)
+        feat_final_sp(J, J.stats, J.facc, J.moved, (int)k, F, sc.feat_set, J.xrow + 16 * k);
+    if (!grid_sync(ctl, bar, s_ok)) return false;
+    // one wave per 16 superpixels (the wave index is uniform in a wave)
+    const int lane = (int)(threadIdx.x & 63);
+    for (int64_t t = gt >> 6; t < ((int64_t)K + 15) / 16; t += gn >> 6) {
+        const int64_t n = 16 * t + (lane & 15);
+        const float z = mlp_logit(sc.mlp_w, load_x(J.xrow, n, K, lane >> 4), lane);
+        if (lane < 16 && n < K) J.gate_out[n] = z >= sc.mlp_thresh ? 1 : 0;
+    }
+    return grid_sync(ctl, bar, s_ok);
+}
+
 #define MC_SYNC()                                  \
     do {                                           \
         if (!grid_sync(ctl, bar, &s_ok)) return;   \
@@ -1701,6 +1739,8 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
     if (tid < 9) l_cnt[tid] = 0;
     if (tid < 2) s_skip[tid] = 0;
     for (int64_t i = gt; i < (PK ? 4 : 2) * (int64_t)K; i += gn) fl[i] = 0;
+    if (GM == GM_FUSED)   // pixels moved before the gate point, a feature
+        for (int64_t i = gt; i < K; i += gn) J.moved[i] = 0;
     if (s_end > s_begin) {
         // visit stamps are unique per (stage, sweep) of this launch
         const int Bf = sc.B[s_end - 1];
@@ -1762,8 +1802,21 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
         const int64_t nb = (int64_t)nbx * nby;
         int32_t *L = J.lab[s & 1];
         const bool use_f64 = sc.f64[s] != 0;
-        int64_t *const mv = J.moved;
-        if (GM == GM_BITS && J.gate && s >= sc.gate_stage) {
+        int64_t *const mv = (GM == GM_FUSED && s >= sc.gate_stage) ? nullptr : J.moved;
+        if (GM == GM_FUSED && s == sc.gate_stage && s > 0) {
+            // the prediction step inside the launch: features on the
+            // previous stage's labels, then the network's gate bits
+            if (PK) {
+                for (int64_t k = gt; k < K; k += gn) {
+                    int64_t r[6];
+                    pk_unpack(pk + 2 * k, r, sc);
+                    for (int q = 0; q < 6; q++) st[6 * k + q] = r[q];
+                }
+                MC_SYNC();
+            }
+            if (!gate_point_mc(J, sc, s - 1, gt, gn, ctl, bar, &s_ok)) return;
+        }
+        if (GM != GM_NONE && J.gate && s >= sc.gate_stage) {
             if (!gate_loaded) {
                 // first gated stage: every workgroup its own copy of the bits
                 // (read-only; the grid barrier below orders it before use)
@@ -2288,10 +2341,12 @@ hipError_t launch_refine_mc(const Job *jobs_dev, int groups, const Sched &sc, in
     void *args[] = {(void *)&jobs_dev, (void *)&sc_arg, (void *)&s_begin, (void *)&s_end, (void *)&flags,
                     (void *)&lut_dev, (void *)&solo_max};
     const bool pk = sc.pk_bn > 0;
-    const void *fn = gate_words > 0 ? (pk ? (const void *)k_refine_mc<GM_BITS, true>
-                                          : (const void *)k_refine_mc<GM_BITS, false>)
-                                    : (pk ? (const void *)k_refine_mc<GM_NONE, true>
-                                          : (const void *)k_refine_mc<GM_NONE, false>);
+    typedef void (*Kern)(const Job *, Sched, int, int, int, const uint32_t *, int64_t);
+    static const Kern table[3][2] = {{k_refine_mc<GM_NONE, false>, k_refine_mc<GM_NONE, true>},
+                                     {k_refine_mc<GM_BITS, false>, k_refine_mc<GM_BITS, true>},
+                                     {k_refine_mc<GM_FUSED, false>, k_refine_mc<GM_FUSED, true>}};
+    const int gm = (flags & FLAG_GATE) ? GM_FUSED : gate_words > 0 ? GM_BITS : GM_NONE;
+    const void *fn = (const void *)table[gm][pk ? 1 : 0];
     return hipLaunchCooperativeKernel(fn, dim3((unsigned)groups), dim3((unsigned)threads), args,
                                       4 * (size_t)gate_words, stream);
 }
@@ -2307,14 +2362,15 @@ hipError_t max_coop_groups(int threads, int *out)
     }
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     // the instantiation that holds the most registers and LDS sets the bound
-    int per_cu_pk = 0;
-    if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_refine_mc<GM_BITS, false>, threads,
-                                                         4 * MAX_GATE_WORDS);
-    if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_pk, (const void *)k_refine_mc<GM_BITS, true>,
-                                                         threads, 4 * MAX_GATE_WORDS);
-    *out = e == hipSuccess ? cus * std::min(per_cu, per_cu_pk) : 0;
+    const void *fns[4] = {(const void *)k_refine_mc<GM_BITS, false>, (const void *)k_refine_mc<GM_BITS, true>,
+                          (const void *)k_refine_mc<GM_FUSED, false>, (const void *)k_refine_mc<GM_FUSED, true>};
+    per_cu = 1 << 30;
+    for (int i = 0; i < 4 && e == hipSuccess; i++) {
+        int pc = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, fns[i], threads, 4 * MAX_GATE_WORDS);
+        per_cu = std::min(per_cu, pc);
+    }
+    *out = e == hipSuccess ? cus * per_cu : 0;
     return e;
 }
 
