@@ -275,12 +275,11 @@ def test_coop_gated_nothing_marked(gpu_lib, rule):
 
 
 def test_coop_gated_large_image(gpu_lib):
-    """A 1024^2 H&E image with K = 4096, gated at the second level, takes
-    the route of separate launches without being asked to (it is large;
-    the autotuner picks the shape of the levels before the gate, the gated
-    levels follow it): labels and counters against the oracle under the
-    GPU's bits, and features, bits and labels against the single-launch
-    route's."""
+    """A 1024^2 H&E image with K = 4096, gated at the second level, spreads
+    over a cooperative launch without being asked to (it is large; the
+    autotuner picks the shape, and the gate point runs across the grid):
+    labels and counters against the oracle under the GPU's bits, and
+    features, bits and labels against the one-workgroup launch's."""
     _dev, _, _, _rand_model = _gate_helpers()
     img = synth.he_tile(1024, 1024, seed=33)
     p = params.default_params(1024, 1024, 4096, levels=params.THREE_LEVEL, gate_level=1)
@@ -398,7 +397,7 @@ def test_coop_abort_is_reported(gpu_lib, tmp_path):
         st.close()
     finally:
         c.close()
-    # the gated route of separate launches for a large image
+    # a gated large image on a cooperative launch (gate point across the grid)
     _dev, _, _, _rand_model = _gate_helpers()
     big = synth.he_tile(1024, 1024, seed=33)
     pg = params.default_params(1024, 1024, 4096, levels=params.THREE_LEVEL, gate_level=1)

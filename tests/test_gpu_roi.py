@@ -3,8 +3,8 @@ Sec. 4 (absolute and comparative brightness, extra- and intra-region
 dissimilarity; gate_features "roi") feed the classifier of Eq. (6), and past
 the gate level only pairs of superpixels of different predicted classes
 refine (Eq. (7), rule "differ").  On every route that decides a gate (the
-level-by-level state, one fused launch, separate launches for a large
-image, a slide's tiles) the features equal the oracle's within 1e-6, the
+level-by-level state, one fused launch, a large image spread over a
+cooperative launch, a slide's tiles) the features equal the oracle's within 1e-6, the
 bits equal the oracle network's decision wherever its logit is 1e-2 clear
 of the threshold, and the labels equal the oracle run under the GPU's bits;
 a classifier trained on the four features finds the tissue."""
@@ -104,10 +104,10 @@ def test_roi_gate_fused_launch(ctx, W, H, K, seed):
     assert (lab2.cpu().numpy() == labs[0].cpu().numpy()).all()
 
 
-def test_roi_gate_large_image_separate_launches(ctx):
-    """A 1024^2 image takes the route of separate launches (stand-alone
-    feature kernels between two refinement launches): the ROI features and
-    bits equal the single fused launch's, and the labels the oracle's."""
+def test_roi_gate_large_image_cooperative(ctx):
+    """A 1024^2 image spreads over the workgroups of one cooperative launch,
+    which decides the gate point across the grid: the ROI features, bits and
+    labels equal the oracle's and those of the same image on one workgroup."""
     import os
     img = synth.he_tile(1024, 1024, seed=33)
     p = _roi_params(1024, 1024, 4096)
@@ -115,7 +115,7 @@ def test_roi_gate_large_image_separate_launches(ctx):
     theta, wb = _rand_model(34)
     z, _ = mlp.forward(theta.astype(np.float64), _oracle_roi_features(img, p, gx, gy).astype(np.float64), bf16=True)
     thresh = float(np.median(z))
-    _say("case: roi gate 1024^2 separate launches, thresh %.4f" % thresh)
+    _say("case: roi gate 1024^2 cooperative launch, thresh %.4f" % thresh)
     labs, _, X, g = ctx.segment_gated([_dev(img)], p, _dev(wb), thresh, features=True)
     g = g.cpu().numpy()
     _check(img, p, X.cpu().numpy(), g, labs[0].cpu().numpy(), theta, thresh, gx, gy)
