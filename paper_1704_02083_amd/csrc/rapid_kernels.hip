@@ -920,7 +920,12 @@ __device__ __forceinline__ void refine_job(const Job &J, const Sched &sc, const 
     extern __shared__ __align__(16) char smem[];
     __shared__ uint32_t s_lut[8];
     __shared__ int32_t s_cnt[9];
-    __shared__ int32_t s_nprop, s_nchg, s_nreq, s_merged, s_any;
+    // proposal counters of the class phases, used by turns: a class with no
+    // proposal goes on to the next class's P1 without another barrier, so
+    // that phase appends to the other counter while slower waves may still
+    // read this one
+    __shared__ int32_t s_nprop[2];
+    __shared__ int32_t s_nchg, s_nreq, s_merged, s_any;
     __shared__ unsigned long long s_ctr[6];   // active proposals commits skip_min skip_topo merges
 
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -966,7 +971,7 @@ __device__ __forceinline__ void refine_job(const Job &J, const Sched &sc, const 
 
     if (tid < 8) s_lut[tid] = lut_g[tid];
     if (tid == 0) {
-        s_nprop = 0;
+        s_nprop[0] = s_nprop[1] = 0;
         s_nchg = 0;
         s_nreq = 0;
     }
@@ -1206,9 +1211,12 @@ __device__ __forceinline__ void refine_job(const Job &J, const Sched &sc, const 
                 s_ctr[0] += (unsigned long long)tot;
             }
             wg_sync();
+            int turn = 0;   // alternates with every class phase that runs P1
             for (int c = 0; c < 9; c++) {
                 const int ncls = s_cnt[c];
                 if (ncls == 0) continue;
+                int32_t *const nprop = &s_nprop[turn];
+                turn ^= 1;
                 const int32_t *llst = l_lists + c * capl;
                 // ---- P1: propose from the class-start state
                 for (int e0 = 0; e0 < ncls; e0 += nt) {
@@ -1326,7 +1334,7 @@ __device__ __forceinline__ void refine_job(const Job &J, const Sched &sc, const 
                         J.involved[a] = 1;
                         J.involved[best] = 1;
                     }
-                    int slot = wave_append(&s_nprop, prop);
+                    int slot = wave_append(nprop, prop);
                     if (slot >= 0) {
                         Prop rec;
                         rec.bi = bi;
@@ -1341,7 +1349,7 @@ __device__ __forceinline__ void refine_job(const Job &J, const Sched &sc, const 
                     }
                 }
                 wg_sync();
-                const int np = s_nprop;
+                const int np = *nprop;
                 if (np == 0) continue;   // uniform: nothing proposed in this class
                 // ---- P2: class-wide size filter, commit, stat moves.  Two
                 // lanes per proposal: lane 0 moves the block's sums out of the
@@ -1437,9 +1445,11 @@ __device__ __forceinline__ void refine_job(const Job &J, const Sched &sc, const 
                     if (rec.pad) refresh_sp(st, mn, sp, sc);
                 }
                 // every thread read np before the P2 barrier: safe to reset
+                // (the other counter is zero: its phase either proposed
+                // nothing or was reset the same way)
                 if (tid == 0) {
                     s_ctr[1] += (unsigned long long)np;
-                    s_nprop = 0;
+                    *nprop = 0;
                 }
                 wg_sync();
             }
@@ -1899,7 +1909,7 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
             // workgroup barriers; the other workgroups wait at its end.
             const bool solo = tot <= solo_max;
             const int64_t first = solo ? 0 : wg0, step = solo ? (int64_t)nt : gn;
-            uint32_t cph = 0;   // PK: phases run so far in this sweep
+            uint32_t cph = 0;   // class phases run so far in this sweep
 #define SW_SYNC()              \
     do {                       \
         if (solo)              \
@@ -1920,23 +1930,26 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
                     const int ncls = ctl_read(cnt, c);   // stable during the sweep
                     if (ncls == 0) continue;
                     const int32_t *llst = J.lists + c * capg;
-                    // PK: this phase's flow buffer and proposal counter; the
-                    // previous phase's counter and this lane's flows in the
-                    // other buffer are cleared (their readers passed a
-                    // barrier since, or read a counter that stayed 0; their
-                    // next writers come after this phase's first barrier)
+                    // This phase's proposal counter (and, PK, flow buffer);
+                    // the previous phase's counter (and this lane's flows in
+                    // the other buffer) are cleared: their readers passed a
+                    // barrier since, or read a counter that stayed 0 and went
+                    // on without one, and their next writers come after this
+                    // phase's first barrier.  A phase that proposes nothing
+                    // is followed by the next phase's P1 without a barrier,
+                    // so the two must not share a counter.
                     const uint32_t pb = cph & 1;
                     int32_t *const flc = PK ? fl + 2 * (int64_t)K * pb : fl;
-                    const int nprop_w = PK ? CTL_NPROP + (int)pb : CTL_NPROP;
+                    const int nprop_w = CTL_NPROP + (int)pb;
+                    if (cph > 0 && gt == 0) ctl[CTL_NPROP + (pb ^ 1)] = 0;
+                    cph++;
                     if (PK) {
-                        if (cph > 0 && gt == 0) ctl[CTL_NPROP + (pb ^ 1)] = 0;
                         if (pend_a >= 0) {
                             int32_t *const flo = fl + 2 * (int64_t)K * (pb ^ 1);
                             flo[2 * (int64_t)pend_a] = 0;
                             flo[2 * (int64_t)pend_k + 1] = 0;
                             pend_a = -1;
                         }
-                        cph++;
                     }
                     if (ncls <= step) {
                         // One pass: every lane keeps its block's proposal in
@@ -2027,7 +2040,7 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
                         // every lane read np before the P2 barrier: safe to reset
                         if (gt == 0) {
                             ctr[1] += (unsigned long long)np;
-                            ctl[CTL_NPROP] = 0;
+                            ctl[nprop_w] = 0;
                         }
                         SW_SYNC();
                         continue;
@@ -2159,23 +2172,21 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
                     // every lane read np before the P2 barrier: safe to reset
                     if (gt == 0) {
                         ctr[1] += (unsigned long long)np;
-                        ctl[CTL_NPROP] = 0;
+                        ctl[nprop_w] = 0;
                     }
                     SW_SYNC();
                 }
-                if (PK) {
-                    // the sweep's last phase: its flows and counters clear
-                    // before the next sweep (the barrier below orders them)
-                    if (pend_a >= 0) {
-                        int32_t *const flo = fl + 2 * (int64_t)K * ((cph - 1) & 1);
-                        flo[2 * (int64_t)pend_a] = 0;
-                        flo[2 * (int64_t)pend_k + 1] = 0;
-                        pend_a = -1;
-                    }
-                    if (gt == 0) {
-                        ctl[CTL_NPROP] = 0;
-                        ctl[CTL_NPROP + 1] = 0;
-                    }
+                // the sweep's last phase: its counters (and, PK, flows) clear
+                // before the next sweep (the barrier below orders them)
+                if (PK && pend_a >= 0) {
+                    int32_t *const flo = fl + 2 * (int64_t)K * ((cph - 1) & 1);
+                    flo[2 * (int64_t)pend_a] = 0;
+                    flo[2 * (int64_t)pend_k + 1] = 0;
+                    pend_a = -1;
+                }
+                if (gt == 0) {
+                    ctl[CTL_NPROP] = 0;
+                    ctl[CTL_NPROP + 1] = 0;
                 }
                 SW_SYNC();
                 const int commits = ctl_read(ctl, CTL_NCHG + par);
