@@ -85,8 +85,8 @@ typedef struct {
      * means records, or nothing in LDS (as far as they fit); block-sum
      * pyramid inside the launch or in separate launches; and, for a single
      * image without merge, the image spread over 8 .. 128 workgroups of a
-     * cooperative launch, with small sweeps on the whole grid or on one
-     * workgroup --
+     * cooperative launch (which builds its pyramid over its own grid), with
+     * small sweeps on the whole grid or on one workgroup --
      * and keeps the fastest (without tuning, a single image whose finest
      * stage has 2^20 blocks or more runs on 64 workgroups, sweeps of at
      * most 16384 active blocks on one); later calls of that
@@ -232,7 +232,8 @@ typedef struct {
  * rapid_timings.stats_lds when it fits, pyramid inside the launch, g
  * workgroups per image where a single plain image may spread over a
  * cooperative launch, whose sweeps with at most s active blocks run on one
- * workgroup) and bypasses the autotuner. */
+ * workgroup; a cooperative launch builds the pyramid itself whatever p says)
+ * and bypasses the autotuner. */
 rapid_status rapid_init(const rapid_config *cfg, rapid_ctx **out);
 void rapid_destroy(rapid_ctx *ctx);   /* NULL-safe; waits for queued work */
 

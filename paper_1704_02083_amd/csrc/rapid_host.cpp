@@ -599,7 +599,8 @@ rapid_status launch_shape(rapid_ctx *ctx, const Job *jobs, size_t n, const Job *
 {
     if (e0) HIPCHK(hipEventRecord(e0, ctx->stream));
     if (flags & FLAG_INIT) {
-        if (sh.pyramid) {
+        // a cooperative launch always builds its pyramid over its grid
+        if (sh.pyramid || sh.groups > 1) {
             flags |= FLAG_PYRAMID;
         } else {
             // chip-wide launches, one per stage with B >= 2
@@ -733,7 +734,7 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
                     LaunchShape c;
                     c.threads = 1024;
                     c.stats_lds = 0;
-                    c.pyramid = 0;
+                    c.pyramid = 1;
                     c.groups = g;
                     c.solo = solo_all[so];
                     cand.push_back(c);
@@ -802,11 +803,11 @@ rapid_status run_jobs(rapid_ctx *ctx, const std::vector<Job> &jobs, const Sched 
     }
     if (sh.groups > 1) {
         // the cooperative shape where this call allows it (state global,
-        // pyramid in separate launches), else one workgroup per job
+        // pyramid inside the launch), else one workgroup per job
         sh.groups = std::min(sh.groups, coop_max);
         if (sh.groups > 1) {
             sh.stats_lds = 0;
-            sh.pyramid = 0;
+            sh.pyramid = 1;
         } else {
             sh.groups = 1;
         }

@@ -352,9 +352,12 @@ __global__ void k_block_sums(const Job *__restrict__ jobs, int s, int B)
 // The pyramid of the schedule (Sec. 3.2's levels as exact box sums) for
 // every stage with B >= 2: the finest such stage from the pixels, each
 // coarser one as the sum of its children in the next finer stage (block
-// sizes divide each other; packed fields add without carries).  Ends with a
-// workgroup barrier.
-__device__ void build_pyramid(const Job &J, const Sched &sc, int tid, int nt)
+// sizes divide each other; packed fields add without carries).  Lanes tid
+// of nt share the work; sync() separates the levels and ends the build (a
+// workgroup barrier on one workgroup, a grid barrier on a cooperative
+// launch, which returns false when the barrier gave up).
+template <class Sync>
+__device__ __forceinline__ bool build_pyramid(const Job &J, const Sched &sc, int tid, int nt, Sync sync)
 {
     int sf = -1;
     for (int s = 0; s < sc.n_stages; s++)
@@ -363,7 +366,7 @@ __device__ void build_pyramid(const Job &J, const Sched &sc, int tid, int nt)
         if (J.moms && J.moms_stage == sf) sums_from_pixels<true, true>(J, sf, sc.B[sf], tid, nt);
         else sums_from_pixels<true, false>(J, sf, sc.B[sf], tid, nt);
         for (int s = sf - 1; s >= 0; s--) {
-            __syncthreads();
+            if (!sync()) return false;
             const int B = sc.B[s], Bc = sc.B[s + 1], r = B / Bc;
             const int nbx = (J.W + B - 1) / B, nby = (J.H + B - 1) / B;
             const int nbxc = (J.W + Bc - 1) / Bc, nbyc = (J.H + Bc - 1) / Bc;
@@ -380,7 +383,7 @@ __device__ void build_pyramid(const Job &J, const Sched &sc, int tid, int nt)
         if (J.moms && J.moms_stage >= 0 && J.moms_stage < sf)
             sums_from_pixels<false, true>(J, J.moms_stage, sc.B[J.moms_stage], tid, nt);
     }
-    __syncthreads();
+    return sync();
 }
 
 // ------------------------------------------------------------- k_expand
@@ -1003,7 +1006,11 @@ __device__ __forceinline__ void refine_job(const Job &J, const Sched &sc, const 
             for (int64_t i = tid; i < 2 * (int64_t)K; i += nt) pk[i] = 0;
         else
             for (int64_t i = tid; i < 6 * (int64_t)K; i += nt) st[i] = 0;
-        if (flags & FLAG_PYRAMID) build_pyramid(J, sc, tid, nt);
+        if (flags & FLAG_PYRAMID)
+            build_pyramid(J, sc, tid, nt, []() {
+                __syncthreads();
+                return true;
+            });
         else wg_sync();
         const int B0 = sc.B[0];
         const int nbx = (W + B0 - 1) / B0, nby = (H + B0 - 1) / B0;
@@ -1763,7 +1770,13 @@ __global__ __launch_bounds__(1024) void k_refine_mc(const Job *__restrict__ jobs
             for (int64_t i = gt; i < 2 * (int64_t)K; i += gn) pk[i] = 0;
         else
             for (int64_t i = gt; i < 6 * (int64_t)K; i += gn) st[i] = 0;
-        MC_SYNC();
+        // the block-sum pyramid over the whole grid, its levels separated
+        // by grid barriers, so that the image takes this one launch
+        if (flags & FLAG_PYRAMID) {
+            if (!build_pyramid(J, sc, (int)gt, (int)gn, [&]() { return grid_sync(ctl, bar, &s_ok); })) return;
+        } else {
+            MC_SYNC();
+        }
         const int B0 = sc.B[0];
         const int nbx = (W + B0 - 1) / B0, nby = (H + B0 - 1) / B0;
         int32_t *L = J.lab[0];

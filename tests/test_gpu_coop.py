@@ -23,8 +23,9 @@ def _say(*a):
 @contextlib.contextmanager
 def _shape(groups, solo=-1):
     """Contexts created inside use one image on `groups` workgroups of 1024
-    lanes (state in global memory, block sums in separate launches), sweeps
-    with at most `solo` active blocks on one workgroup."""
+    lanes (state in global memory, the block-sum pyramid built over the grid
+    inside the launch), sweeps with at most `solo` active blocks on one
+    workgroup."""
     old = os.environ.get("RAPID_SHAPE")
     os.environ["RAPID_SHAPE"] = "1024,0,0,%d,%d" % (groups, solo)
     try:
@@ -77,7 +78,9 @@ def test_coop_small_cases_bit_exact(gpu_lib):
             for (W, H, K, _, _, seed), (img, p), (ref, ref_rep) in zip(CASES, imgs, refs):
                 _say("case: coop G=%d S=%d %dx%d K=%d seed=%d" % (g, so, W, H, K, seed))
                 got, rep = _run(c, img, p)
-                assert c.last_timings()["workgroups"] == g
+                tm = c.last_timings()
+                assert tm["workgroups"] == g
+                assert tm["pyramid"] == 1   # the whole image in one launch
                 mism = int((got != ref).sum())
                 assert mism == 0, "G=%d %dx%d: %d labels differ" % (g, W, H, mism)
                 assert rep == ref_rep, "G=%d %dx%d: stage counters differ" % (g, W, H)
@@ -289,6 +292,8 @@ def test_coop_gated_large_image(gpu_lib):
         _say("case: coop gated 1024^2 K=4096")
         labs, reps, X, gb = c.segment_gated([_dev(img)], p, _dev(wb), 0.0, features=True)
         t = c.last_timings()
+        if t["workgroups"] > 1:
+            assert t["pyramid"] == 1   # pyramid, levels and gate point: one launch
         gbits = gb.cpu().numpy()
         ref, _, ref_rep = oracle.segment(img, p, gate=gbits)
         assert (labs[0].cpu().numpy() == ref).all()

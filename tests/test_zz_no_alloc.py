@@ -77,3 +77,48 @@ def test_noalloc_matches_segment(gpu_lib):
         assert (out == -7).all()
     finally:
         c.close()
+
+
+def test_noalloc_replays_from_a_hip_graph(gpu_lib):
+    """rapid_segment_noalloc without a report queues kernels only (no
+    allocation, no memset node, no synchronisation), so a caller can capture
+    it in a HIP graph: captured once, the graph replays on new images copied
+    into the captured input between replays (eager work and synchronisation
+    in between), and every replay gives the labels of an eager call and of
+    the oracle."""
+    import torch
+    s = torch.cuda.Stream()
+    c = gpu_lib.Context(0, stream=s)
+    try:
+        W, H, K = 256, 192, 48
+        p = params.default_params(W, H, K, levels=params.THREE_LEVEL)
+        imgs = [synth.voronoi_blur(W, H, regions=14, seed=900 + i) for i in range(4)]
+        rgb = torch.from_numpy(imgs[0]).cuda()
+        out = torch.full((H, W), -7, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        # an eager call first loads the kernels and sets their LDS limits
+        with torch.cuda.stream(s):
+            c.segment_noalloc(rgb, p, labels=out, report=False)
+        s.synchronize()
+        g = torch.cuda.CUDAGraph()
+        _say("case: noalloc graph capture %dx%d K=%d" % (W, H, K))
+        with torch.cuda.graph(g, stream=s):
+            c.segment_noalloc(rgb, p, labels=out, report=False)
+        for i in (1, 2, 0, 3):
+            _say("case: noalloc graph replay, image %d" % i)
+            rgb.copy_(torch.from_numpy(imgs[i]))
+            out.fill_(-7)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            eager = torch.full((H, W), -5, dtype=torch.int32, device="cuda")
+            with torch.cuda.stream(s):
+                c.segment(rgb, p, labels=eager, report=False)
+            s.synchronize()
+            assert (got == eager.cpu().numpy()).all(), "replay %d differs from the eager call" % i
+            ref, _, _ = oracle.segment(imgs[i], p)
+            assert (got == ref).all(), "replay %d differs from the oracle" % i
+        del g
+    finally:
+        c.close()
