@@ -300,6 +300,14 @@ __device__ __forceinline__ void wg_sync()
     __syncthreads();
 }
 
+// Whole-map passes of one workgroup (pyramid, stage split, output) take
+// several elements per lane and pass and issue all their loads before using
+// any: one element per lane and pass would wait for one memory round trip
+// per element.
+constexpr int OUT_UNROLL = 4;     // output pixels per lane and pass
+constexpr int SPLIT_UNROLL = 4;   // parent blocks per lane and pass of a stage split
+constexpr int SUMS_UNROLL = 2;    // 2x2 blocks per lane and pass of the pyramid's finest stage
+
 // ------------------------------------------------------- block-sum pyramid
 // Packed per-block RGB sums (21 bits per channel; B <= 64 keeps every
 // channel below 2^21) of one stage of block size B straight from the
@@ -310,6 +318,48 @@ __device__ __forceinline__ void sums_from_pixels(const Job &J, int s, int B, int
 {
     const int nbx = (J.W + B - 1) / B, nby = (J.H + B - 1) / B;
     const int64_t nb = (int64_t)nbx * nby;
+    if (B == 2) {
+        // 2x2 blocks (the finest stage of the usual schedules): SUMS_UNROLL
+        // blocks per lane and pass, the bytes of their (up to) four pixels
+        // loaded together; pixels past the image edge count as zero
+        for (int64_t i0 = tid; i0 < nb; i0 += SUMS_UNROLL * (int64_t)nt) {
+            uint32_t v[SUMS_UNROLL][12];
+#pragma unroll
+            for (int u = 0; u < SUMS_UNROLL; u++) {
+                const int64_t i = i0 + (int64_t)u * nt;
+                const int bx = (int)((uint32_t)i % (uint32_t)nbx), by = (int)((uint32_t)i / (uint32_t)nbx);
+                const bool in = i < nb, tx = in && 2 * bx + 1 < J.W, ty = in && 2 * by + 1 < J.H;
+                const uint8_t *r0 = J.rgb + (int64_t)(2 * by) * J.rgb_stride + 6 * (int64_t)bx;
+                const uint8_t *r1 = r0 + J.rgb_stride;
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    v[u][c] = in ? r0[c] : 0u;
+                    v[u][3 + c] = tx ? r0[3 + c] : 0u;
+                    v[u][6 + c] = ty ? r1[c] : 0u;
+                    v[u][9 + c] = tx && ty ? r1[3 + c] : 0u;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SUMS_UNROLL; u++) {
+                const int64_t i = i0 + (int64_t)u * nt;
+                if (i >= nb) continue;
+                uint32_t c3[3], q3[3];
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    c3[c] = v[u][c] + v[u][3 + c] + v[u][6 + c] + v[u][9 + c];
+                    q3[c] = v[u][c] * v[u][c] + v[u][3 + c] * v[u][3 + c] + v[u][6 + c] * v[u][6 + c] +
+                            v[u][9 + c] * v[u][9 + c];
+                }
+                if (SUMS) J.sums[s][i] = (uint64_t)c3[0] | ((uint64_t)c3[1] << 21) | ((uint64_t)c3[2] << 42);
+                if (MOMS) {
+                    J.moms[3 * i] = q3[0];
+                    J.moms[3 * i + 1] = q3[1];
+                    J.moms[3 * i + 2] = q3[2];
+                }
+            }
+        }
+        return;
+    }
     for (int64_t i = tid; i < nb; i += nt) {
         const int bx = (int)(i % nbx), by = (int)(i / nbx);
         const int x0 = bx * B, y0 = by * B;
@@ -371,13 +421,38 @@ __device__ __forceinline__ bool build_pyramid(const Job &J, const Sched &sc, int
             const int nbx = (J.W + B - 1) / B, nby = (J.H + B - 1) / B;
             const int nbxc = (J.W + Bc - 1) / Bc, nbyc = (J.H + Bc - 1) / Bc;
             const uint64_t *child = J.sums[s + 1];
-            for (int64_t i = tid; i < (int64_t)nbx * nby; i += nt) {
-                const int bx = (int)(i % nbx), by = (int)(i / nbx);
-                const int cx1 = min((bx + 1) * r, nbxc), cy1 = min((by + 1) * r, nbyc);
-                uint64_t acc = 0;
-                for (int cy = by * r; cy < cy1; cy++)
-                    for (int cx = bx * r; cx < cx1; cx++) acc += child[(int64_t)cy * nbxc + cx];
-                J.sums[s][i] = acc;
+            const int64_t nbs = (int64_t)nbx * nby;
+            if (r == 2) {
+                // SUMS_UNROLL parents per lane and pass, their four children
+                // loaded together (a child past the edge counts as zero)
+                for (int64_t i0 = tid; i0 < nbs; i0 += SUMS_UNROLL * (int64_t)nt) {
+                    uint64_t c4[SUMS_UNROLL][4];
+#pragma unroll
+                    for (int u = 0; u < SUMS_UNROLL; u++) {
+                        const int64_t i = i0 + (int64_t)u * nt;
+                        const int bx = (int)((uint32_t)i % (uint32_t)nbx), by = (int)((uint32_t)i / (uint32_t)nbx);
+                        const bool in = i < nbs, tx = in && 2 * bx + 1 < nbxc, ty = in && 2 * by + 1 < nbyc;
+                        const uint64_t *c0 = child + (int64_t)(2 * by) * nbxc + 2 * bx;
+                        c4[u][0] = in ? c0[0] : 0ull;
+                        c4[u][1] = tx ? c0[1] : 0ull;
+                        c4[u][2] = ty ? c0[nbxc] : 0ull;
+                        c4[u][3] = tx && ty ? c0[nbxc + 1] : 0ull;
+                    }
+#pragma unroll
+                    for (int u = 0; u < SUMS_UNROLL; u++) {
+                        const int64_t i = i0 + (int64_t)u * nt;
+                        if (i < nbs) J.sums[s][i] = c4[u][0] + c4[u][1] + c4[u][2] + c4[u][3];
+                    }
+                }
+            } else {
+                for (int64_t i = tid; i < nbs; i += nt) {
+                    const int bx = (int)(i % nbx), by = (int)(i / nbx);
+                    const int cx1 = min((bx + 1) * r, nbxc), cy1 = min((by + 1) * r, nbyc);
+                    uint64_t acc = 0;
+                    for (int cy = by * r; cy < cy1; cy++)
+                        for (int cx = bx * r; cx < cx1; cx++) acc += child[(int64_t)cy * nbxc + cx];
+                    J.sums[s][i] = acc;
+                }
             }
         }
         if (J.moms && J.moms_stage >= 0 && J.moms_stage < sf)
@@ -734,11 +809,23 @@ __device__ __attribute__((noinline)) void gate_point(const Job &J, const int64_t
     if (staged) {
         for (int by0 = 0; by0 < nbyq; by0 += RB) {
             const int rows = min(RB, nbyq - by0);
-            // rows by0 - 1 .. by0 + rows of the label map, -1 outside it
-            for (int r = 0; r < rows + 2; r++) {
-                const int y = by0 - 1 + r;
-                for (int x = tid; x < nbxq; x += nt)
-                    band[r * nbxq + x] = (y >= 0 && y < nbyq) ? Lq[(int64_t)y * nbxq + x] : -1;
+            // rows by0 - 1 .. by0 + rows of the label map, -1 outside it:
+            // one contiguous range of the map, copied in one pass with
+            // OUT_UNROLL loads per lane in flight
+            const int64_t nband = (int64_t)(rows + 2) * nbxq, gbase = (int64_t)(by0 - 1) * nbxq;
+            const int64_t nbq = (int64_t)nbxq * nbyq;
+            for (int64_t e0 = tid; e0 < nband; e0 += OUT_UNROLL * (int64_t)nt) {
+                int32_t v[OUT_UNROLL];
+#pragma unroll
+                for (int u = 0; u < OUT_UNROLL; u++) {
+                    const int64_t e = e0 + (int64_t)u * nt, gi = gbase + e;
+                    v[u] = (e < nband && gi >= 0 && gi < nbq) ? Lq[gi] : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < OUT_UNROLL; u++) {
+                    const int64_t e = e0 + (int64_t)u * nt;
+                    if (e < nband) band[e] = v[u];
+                }
             }
             // grid rows of the band's first pixel row, minus one
             const int ky0 = (int)(((int64_t)by0 * Bq * J.gy) / J.H) - 1;
@@ -1163,34 +1250,40 @@ __device__ __forceinline__ void refine_job(const Job &J, const Sched &sc, const 
             const int64_t nbp = (int64_t)nbxp * nbyp;
             const int32_t *Lp = J.lab[(s - 1) & 1];
             const int r = Bp / B;
-            for (int64_t p0 = 0; p0 < nbp; p0 += nt) {
-                int64_t p = p0 + tid;
-                int32_t a = 0;
-                bool sw = false, se = false, sn = false, ss = false;
-                int pxb = 0, pyb = 0;
-                if (p < nbp) {
-                    pxb = (int)(p % nbxp);
-                    pyb = (int)(p / nbxp);
-                    a = Lp[p];
-                    int32_t k;
-                    k = lab_at(Lp, pxb - 1, pyb, nbxp, nbyp);
-                    sw = k >= 0 && k != a && pair_on(gv, a, k);
-                    k = lab_at(Lp, pxb + 1, pyb, nbxp, nbyp);
-                    se = k >= 0 && k != a && pair_on(gv, a, k);
-                    k = lab_at(Lp, pxb, pyb - 1, nbxp, nbyp);
-                    sn = k >= 0 && k != a && pair_on(gv, a, k);
-                    k = lab_at(Lp, pxb, pyb + 1, nbxp, nbyp);
-                    ss = k >= 0 && k != a && pair_on(gv, a, k);
+            // SPLIT_UNROLL parents per lane and pass: the five labels of
+            // each (itself and its 4-neighbours) are loaded together
+            for (int64_t p0 = 0; p0 < nbp; p0 += SPLIT_UNROLL * (int64_t)nt) {
+                int32_t a[SPLIT_UNROLL], nw[SPLIT_UNROLL], ne[SPLIT_UNROLL], nn[SPLIT_UNROLL], ns[SPLIT_UNROLL];
+                int pxb[SPLIT_UNROLL], pyb[SPLIT_UNROLL];
+#pragma unroll
+                for (int u = 0; u < SPLIT_UNROLL; u++) {
+                    const int64_t p = p0 + (int64_t)u * nt + tid;
+                    pxb[u] = (int)((uint32_t)p % (uint32_t)nbxp);
+                    pyb[u] = (int)((uint32_t)p / (uint32_t)nbxp);
+                    const bool in = p < nbp;
+                    a[u] = in ? Lp[p] : 0;
+                    nw[u] = in ? lab_at(Lp, pxb[u] - 1, pyb[u], nbxp, nbyp) : -1;
+                    ne[u] = in ? lab_at(Lp, pxb[u] + 1, pyb[u], nbxp, nbyp) : -1;
+                    nn[u] = in ? lab_at(Lp, pxb[u], pyb[u] - 1, nbxp, nbyp) : -1;
+                    ns[u] = in ? lab_at(Lp, pxb[u], pyb[u] + 1, nbxp, nbyp) : -1;
                 }
+#pragma unroll
+                for (int u = 0; u < SPLIT_UNROLL; u++) {
+                    const bool in = p0 + (int64_t)u * nt + tid < nbp;
+                    const bool sw = nw[u] >= 0 && nw[u] != a[u] && pair_on(gv, a[u], nw[u]);
+                    const bool se = ne[u] >= 0 && ne[u] != a[u] && pair_on(gv, a[u], ne[u]);
+                    const bool sn = nn[u] >= 0 && nn[u] != a[u] && pair_on(gv, a[u], nn[u]);
+                    const bool ss = ns[u] >= 0 && ns[u] != a[u] && pair_on(gv, a[u], ns[u]);
 #pragma unroll 1
-                for (int ch = 0; ch < r * r; ch++) {
-                    int cx = pxb * r + ch % r, cy = pyb * r + ch / r;
-                    bool valid = p < nbp && cx < nbx && cy < nby;
-                    if (valid) L[(int64_t)cy * nbx + cx] = a;
-                    bool e = valid && ((sw && ch % r == 0) || (se && ch % r == r - 1) ||
-                                       (sn && ch / r == 0) || (ss && ch / r == r - 1));
-                    if (e) class_push(s_cnt, l_lists, capl, J.lists, capg, 3 * (cy % 3) + (cx % 3),
-                                      cy * nbx + cx);
+                    for (int ch = 0; ch < r * r; ch++) {
+                        int cx = pxb[u] * r + ch % r, cy = pyb[u] * r + ch / r;
+                        bool valid = in && cx < nbx && cy < nby;
+                        if (valid) L[(int64_t)cy * nbx + cx] = a[u];
+                        bool e = valid && ((sw && ch % r == 0) || (se && ch % r == r - 1) ||
+                                           (sn && ch / r == 0) || (ss && ch / r == r - 1));
+                        if (e) class_push(s_cnt, l_lists, capl, J.lists, capg, 3 * (cy % 3) + (cx % 3),
+                                          cy * nbx + cx);
+                    }
                 }
             }
         } else {
@@ -1557,21 +1650,45 @@ __device__ __forceinline__ void refine_job(const Job &J, const Sched &sc, const 
         const int B = sc.B[out_stage];
         const int nbx = (W + B - 1) / B;
         const int32_t *L = J.lab[out_stage & 1];
-        const int64_t ncore = (int64_t)J.core_w * J.core_h;
-        for (int64_t i = tid; i < ncore; i += nt) {
-            const int x = J.core_x0 + (int)(i % J.core_w), y = J.core_y0 + (int)(i / J.core_w);
-            const int32_t k = L[(y / B) * nbx + x / B];
-            J.out[(int64_t)y * J.out_stride + x] =
-                (int32_t)((J.gid_y0 + k / J.gx) * J.gid_w + J.gid_x0 + k % J.gx);
+        const uint32_t cw = (uint32_t)J.core_w, ncore = cw * (uint32_t)J.core_h;
+        const int32_t gx = J.gx;
+        // OUT_UNROLL pixels per lane and pass, every label load issued
+        // before the first store (W, H <= 8192: 32-bit pixel indices)
+        for (uint32_t i0 = (uint32_t)tid; i0 < ncore; i0 += OUT_UNROLL * (uint32_t)nt) {
+            int32_t k[OUT_UNROLL];
+            int x[OUT_UNROLL], y[OUT_UNROLL];
+#pragma unroll
+            for (int u = 0; u < OUT_UNROLL; u++) {
+                const uint32_t i = i0 + (uint32_t)u * (uint32_t)nt;
+                x[u] = J.core_x0 + (int)(i % cw);
+                y[u] = J.core_y0 + (int)(i / cw);
+                k[u] = i < ncore ? L[(y[u] / B) * nbx + x[u] / B] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < OUT_UNROLL; u++)
+                if (k[u] >= 0)
+                    J.out[(int64_t)y[u] * J.out_stride + x[u]] =
+                        (int32_t)((J.gid_y0 + k[u] / gx) * J.gid_w + J.gid_x0 + k[u] % gx);
         }
     } else if ((flags & FLAG_OUT) && s_end > 0) {
         const int B = sc.B[out_stage];
         const int nbx = (W + B - 1) / B;
         const int32_t *L = J.lab[out_stage & 1];
         if (!(B == 1 && L == J.out)) {
-            for (int64_t i = tid; i < (int64_t)W * H; i += nt) {
-                int x = (int)(i % W), y = (int)(i / W);
-                J.out[(int64_t)y * J.out_stride + x] = L[(int64_t)(y / B) * nbx + x / B];
+            const uint32_t npx = (uint32_t)W * (uint32_t)H;
+            for (uint32_t i0 = (uint32_t)tid; i0 < npx; i0 += OUT_UNROLL * (uint32_t)nt) {
+                int32_t k[OUT_UNROLL];
+                int x[OUT_UNROLL], y[OUT_UNROLL];
+#pragma unroll
+                for (int u = 0; u < OUT_UNROLL; u++) {
+                    const uint32_t i = i0 + (uint32_t)u * (uint32_t)nt;
+                    x[u] = (int)(i % (uint32_t)W);
+                    y[u] = (int)(i / (uint32_t)W);
+                    k[u] = i < npx ? L[(y[u] / B) * nbx + x[u] / B] : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < OUT_UNROLL; u++)
+                    if (k[u] >= 0) J.out[(int64_t)y[u] * J.out_stride + x[u]] = k[u];
             }
         }
     }
