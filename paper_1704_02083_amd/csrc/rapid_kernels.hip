@@ -269,13 +269,14 @@ __device__ __forceinline__ bool pair_on(const GateView &gv, int a, int k)
 __device__ __forceinline__ bool eligible(const int32_t *L, int bx, int by, int nbx, int nby,
                                          const GateView &gv)
 {
-    int32_t a = L[by * nbx + bx];
-    int32_t k;
-    if ((k = lab_at(L, bx - 1, by, nbx, nby)) >= 0 && k != a && pair_on(gv, a, k)) return true;
-    if ((k = lab_at(L, bx + 1, by, nbx, nby)) >= 0 && k != a && pair_on(gv, a, k)) return true;
-    if ((k = lab_at(L, bx, by - 1, nbx, nby)) >= 0 && k != a && pair_on(gv, a, k)) return true;
-    if ((k = lab_at(L, bx, by + 1, nbx, nby)) >= 0 && k != a && pair_on(gv, a, k)) return true;
-    return false;
+    // the five labels are loaded together (one memory round trip, not one
+    // per neighbour), then tested without short-circuiting
+    const int32_t a = L[by * nbx + bx];
+    const int32_t k0 = lab_at(L, bx - 1, by, nbx, nby), k1 = lab_at(L, bx + 1, by, nbx, nby);
+    const int32_t k2 = lab_at(L, bx, by - 1, nbx, nby), k3 = lab_at(L, bx, by + 1, nbx, nby);
+    const int e = (int)(k0 >= 0 && k0 != a && pair_on(gv, a, k0)) | (int)(k1 >= 0 && k1 != a && pair_on(gv, a, k1)) |
+                  (int)(k2 >= 0 && k2 != a && pair_on(gv, a, k2)) | (int)(k3 >= 0 && k3 != a && pair_on(gv, a, k3));
+    return e != 0;
 }
 
 // Inserts block index ni into the LDS hash set tab (mask + 1 words, keys
@@ -307,6 +308,7 @@ __device__ __forceinline__ void wg_sync()
 constexpr int OUT_UNROLL = 4;     // output pixels per lane and pass
 constexpr int SPLIT_UNROLL = 4;   // parent blocks per lane and pass of a stage split
 constexpr int SUMS_UNROLL = 2;    // 2x2 blocks per lane and pass of the pyramid's finest stage
+constexpr int FRONT_UNROLL = 2;   // neighbourhood blocks per lane and pass of a frontier rebuild
 
 // ------------------------------------------------------- block-sum pyramid
 // Packed per-block RGB sums (21 bits per channel; B <= 64 keeps every
@@ -1582,23 +1584,42 @@ __device__ __forceinline__ void refine_job(const Job &J, const Sched &sc, const 
             // visits fit it at half load, else with the global stamps.
             const int32_t stamp = s * (sc.max_sweeps + 1) + t + 1;
             const bool use_hash = !use_bm && 9 * nchg <= ht_cap / 2;
-            for (int q = tid; q < 9 * nchg; q += nt) {
-                int32_t bi = list_get(l_chg, capx, J.changed, 0, q / 9);
-                int d = q % 9;
-                int bx = bi % nbx + (d % 3) - 1, by = bi / nbx + (d / 3) - 1;
-                if (bx < 0 || by < 0 || bx >= nbx || by >= nby) continue;
-                int32_t ni = by * nbx + bx;
-                bool first;
-                if (use_bm) {
-                    uint32_t bit = 1u << (ni & 31);
-                    first = (atomicOr(&l_bm[ni >> 5], bit) & bit) == 0;
-                } else if (use_hash) {
-                    first = hash_insert(l_bm, ht_cap - 1, ni);
-                } else {
-                    first = atomicExch(&J.stamp[ni], stamp) != stamp;
+            // FRONT_UNROLL neighbourhood blocks per lane and pass: their
+            // first-visit tests (global stamps: atomics that return) and
+            // then their eligibility loads are issued together
+            for (int q0 = tid; q0 < 9 * nchg; q0 += FRONT_UNROLL * nt) {
+                int32_t ni[FRONT_UNROLL];
+                int bxs[FRONT_UNROLL], bys[FRONT_UNROLL];
+                bool ok[FRONT_UNROLL];
+#pragma unroll
+                for (int u = 0; u < FRONT_UNROLL; u++) {
+                    const int q = q0 + u * nt;
+                    ok[u] = q < 9 * nchg;
+                    const int32_t bi = ok[u] ? list_get(l_chg, capx, J.changed, 0, q / 9) : 0;
+                    const int d = q % 9;
+                    bxs[u] = bi % nbx + (d % 3) - 1;
+                    bys[u] = bi / nbx + (d / 3) - 1;
+                    ok[u] = ok[u] && bxs[u] >= 0 && bys[u] >= 0 && bxs[u] < nbx && bys[u] < nby;
+                    ni[u] = bys[u] * nbx + bxs[u];
                 }
-                if (first && eligible(L, bx, by, nbx, nby, gv))
-                    class_push(s_cnt, l_lists, capl, J.lists, capg, 3 * (by % 3) + (bx % 3), ni);
+#pragma unroll
+                for (int u = 0; u < FRONT_UNROLL; u++) {
+                    if (!ok[u]) continue;
+                    if (use_bm) {
+                        const uint32_t bit = 1u << (ni[u] & 31);
+                        ok[u] = (atomicOr(&l_bm[ni[u] >> 5], bit) & bit) == 0;
+                    } else if (use_hash) {
+                        ok[u] = hash_insert(l_bm, ht_cap - 1, ni[u]);
+                    } else {
+                        ok[u] = atomicExch(&J.stamp[ni[u]], stamp) != stamp;
+                    }
+                }
+                bool el[FRONT_UNROLL];
+#pragma unroll
+                for (int u = 0; u < FRONT_UNROLL; u++) el[u] = ok[u] && eligible(L, bxs[u], bys[u], nbx, nby, gv);
+#pragma unroll
+                for (int u = 0; u < FRONT_UNROLL; u++)
+                    if (el[u]) class_push(s_cnt, l_lists, capl, J.lists, capg, 3 * (bys[u] % 3) + (bxs[u] % 3), ni[u]);
             }
             wg_sync();
             if (use_bm)
