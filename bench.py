@@ -512,6 +512,7 @@ def bench_gated(args, ctx, rgb, labels, plain, W, H, dt_plain):
     network decision: nothing refined past the gate point (the schedule
     stopped before the gated stage) and everything refined (the gate's
     overhead)."""
+    import numpy as np
     import torch
     from paper_1704_02083_amd import gate, metrics, params, rapid, synth_gpu
     w, info = train_gate(ctx, args.gate_rule, args.train_tiles, gate_level=args.gate_level, save=args.save_gate)
@@ -577,7 +578,8 @@ def bench_gated(args, ctx, rgb, labels, plain, W, H, dt_plain):
     for target in (0.99, 0.995):
         cal = gate.calibrate(ctx, hold, params.gated(2048, 2048, 4096, rule=args.gate_rule,
                                                      gate_level=args.gate_level), w, target,
-                             candidates=[1e9, 4.0, 3.0, 2.0, 1.5, 1.0, 0.5, 0.0, -0.5, -1.0, -2.0, -1e9])
+                             candidates=[1e9, 4.0, 3.0, 2.0, 1.5, 1.25, 1.0, 0.75, 0.5, 0.4, 0.3, 0.2, 0.1, 0.0,
+                                         -0.25, -0.5, -1.0, -2.0, -1e9])
         if cal is None:
             res["points"].append({"target_br": target, "calibrated": None})
             continue
@@ -590,6 +592,40 @@ def bench_gated(args, ctx, rgb, labels, plain, W, H, dt_plain):
                             "gated stage" if c["held_out"]["marked"] == 0.0 else
                             "network: the marked superpixels refine in the gated stage")
         res["points"].append(c)
+    # what the network adds over a gate without it: on the held-out tiles, a
+    # random choice of the same share of superpixels, and the share a random
+    # choice needs to meet the target
+    pg_h = params.gated(2048, 2048, 4096, rule=args.gate_rule, gate_level=args.gate_level)
+    gx_h, gy_h = rapid.grid(2048, 2048, pg_h["K"])
+    plain_h = [ctx.segment(r, pg_h, report=False)[0] for r in hold]
+
+    def random_br(share):
+        brs = []
+        for i, (r, ph) in enumerate(zip(hold, plain_h)):
+            K = gx_h * gy_h
+            for sd in (0, 1):
+                bits = np.zeros(K, np.uint8)
+                bits[np.random.default_rng(1000 * sd + i).choice(K, int(round(share * K)), replace=False)] = 1
+                lab_r, _ = ctx.segment(r, pg_h, gate=torch.from_numpy(bits).cuda(), report=False)
+                brs.append(gate.boundary_recall(ctx, ph, lab_r))
+        return float(np.mean(brs))
+
+    for c in res["points"]:
+        if c.get("calibrated", True) is None or c["held_out"]["marked"] == 0.0:
+            continue
+        m = c["held_out"]["marked"]
+        need = None
+        for share in [m] + [x for x in (0.6, 0.7, 0.8, 0.9, 1.0) if x > m]:
+            br = random_br(share)
+            if share == m:
+                c["random_same_share"] = {"marked": round(m, 6), "br": round(br, 6)}
+            if br >= c["target_br"]:
+                need = share
+                break
+        c["random_share_for_target"] = need
+        c["random_note"] = ("held-out tiles, two random gates per tile: boundary recall of a random choice of the "
+                            "network's share, and the smallest share of (that share, 0.6 .. 1.0) whose random "
+                            "choice meets the target")
     for name, th in (("nothing refined past the gate", 1e9), ("everything refined (gate overhead)", -1e9)):
         r = point(th)
         r["name"] = name
