@@ -172,7 +172,7 @@ def _oracle_worker(idx, p, barrier, results):
 
 def cpu_baseline_multicore(p, n_images: int = 200):
     """The oracle in independent processes over the 200 batched images, one
-    process per core the box grants (at most 16): a multi-core host
+    process per core the host grants (at most 16): a multi-core host
     throughput beside the single-threaded one.  The processes are fresh
     interpreters, so they hold no GPU state."""
     import multiprocessing as mp
@@ -231,7 +231,7 @@ def cpu_baseline_tiles(rgb, W, H, p, lay, n_single: int = 8):
     tiles spread over the slide (the first and last tile, the rest evenly
     between them), as a slide rate of core pixels per second (the slide
     takes 768 / n_single times their time); and one distinct tile per core
-    the box grants (at most 16) in independent processes, as a multi-core
+    the host grants (at most 16) in independent processes, as a multi-core
     host rate.  Generation and copies are outside the timed regions."""
     import multiprocessing as mp
     import numpy as np
@@ -313,6 +313,9 @@ def main():
     ap.add_argument("--gate-level", type=int, default=3, choices=[1, 2, 3],
                     help="level of the schedule 16 | 8,4 | 2 | 1 from which the gate applies")
     ap.add_argument("--train-tiles", type=int, default=64, help="4096x4096 training tiles of the gate")
+    ap.add_argument("--min-miss", type=int, default=1,
+                    help="gate target: a superpixel is positive from this many boundary pixels that "
+                         "freezing it at the gate point would miss")
     ap.add_argument("--grain", type=int, default=1,
                     help="H&E workloads: stop the schedule at this effective block size (the paper's "
                          "'grain'; 4 = its 4x4 setting)")
@@ -337,7 +340,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the refinement path runs on a single MI355X "
-              "(multi-GPU sharding is not part of this build)", file=sys.stderr)
+              "(the library shards no work across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -467,9 +470,11 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def train_gate(ctx, rule: str, n_tiles: int, seed: int = 0, gate_level: int = 3, save: str | None = None):
+def train_gate(ctx, rule: str, n_tiles: int, seed: int = 0, gate_level: int = 3, save: str | None = None,
+               min_miss: int = 1):
     """Gate network trained on n_tiles synthetic 4096x4096 H&E tiles (seeds
-    5000...) with 32-px cells: features and targets from plain runs, the
+    5000...) with 32-px cells: features and targets (a superpixel is
+    positive from min_miss missed boundary pixels) from plain runs, the
     training itself, all on the GPU through the C-ABI."""
     import torch
     from paper_1704_02083_amd import gate, params, synth_gpu
@@ -477,7 +482,7 @@ def train_gate(ctx, rule: str, n_tiles: int, seed: int = 0, gate_level: int = 3,
     Xs, ts = [], []
     for i in range(n_tiles):
         rgb = synth_gpu.he_slide(4096, 4096, seed=5000 + i, background=0.4, device="cuda")
-        X, t, _ = gate.tile_samples(ctx, rgb, p)
+        X, t, _ = gate.tile_samples(ctx, rgb, p, min_miss=min_miss)
         Xs.append(X)
         ts.append(t)
         del rgb
@@ -487,7 +492,8 @@ def train_gate(ctx, rule: str, n_tiles: int, seed: int = 0, gate_level: int = 3,
     torch.cuda.synchronize()
     if save:
         gate.save_model(save, master, w, 0.0, gate_level, rule)
-    return w, {"tiles": n_tiles, "samples": int(X.shape[0]), "positive_rate": round(float(t.float().mean().item()), 4),
+    return w, {"tiles": n_tiles, "samples": int(X.shape[0]), "min_miss": min_miss,
+               "positive_rate": round(float(t.float().mean().item()), 4),
                "train_s": round(time.perf_counter() - t0, 3)}
 
 
@@ -515,7 +521,8 @@ def bench_gated(args, ctx, rgb, labels, plain, W, H, dt_plain):
     import numpy as np
     import torch
     from paper_1704_02083_amd import gate, metrics, params, rapid, synth_gpu
-    w, info = train_gate(ctx, args.gate_rule, args.train_tiles, gate_level=args.gate_level, save=args.save_gate)
+    w, info = train_gate(ctx, args.gate_rule, args.train_tiles, gate_level=args.gate_level, save=args.save_gate,
+                         min_miss=args.min_miss)
     print("bench: gate trained (%s)" % info, file=sys.stderr, flush=True)
     slide = args.workload in ("slide", "slide65k")
     if slide:
