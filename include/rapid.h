@@ -264,7 +264,10 @@ rapid_status rapid_segment_batch(rapid_ctx *ctx, const rapid_image *imgs, int32_
  * overlap on one GPU (other streams, contexts or threads) race and give
  * undefined results; calls ordered on one stream do not.  The array keeps
  * the last call's contents; each call initialises what it reads.  When a
- * report is requested the call synchronises the stream. */
+ * report is requested the call synchronises the stream; without one (and
+ * without RAPID_CFG_TIMING) it only queues kernels on the context's stream
+ * (no memset, copy or synchronisation), so a caller may capture it in a HIP
+ * graph and replay that graph on new contents of the same buffers. */
 #define RAPID_NOALLOC_SCRATCH_BYTES 67108864   /* 64 MiB */
 rapid_status rapid_segment_noalloc(rapid_ctx *ctx, const rapid_image *img, const rapid_params *params,
                                    const uint8_t *gate_dev, rapid_report *report);
