@@ -111,13 +111,17 @@ def stage_bytes_window(W, H, rep, pyramid: bool) -> int:
     return total
 
 
-def refine_alg_bytes(imgs, reports, model=stage_bytes) -> float:
+def refine_alg_bytes(imgs, reports, model=stage_bytes, pyramid: bool | None = None) -> float:
     """Algorithmic bytes of one refinement launch over whole images: the
-    stages' bytes plus the final pixel labels written once (4 B per pixel)."""
+    stages' bytes plus the final pixel labels written once (4 B per pixel).
+    pyramid: whether the launch builds the block-sum pyramid itself (its
+    reported launch shape); None: as a batch launch decides it."""
+    if pyramid is None:
+        pyramid = len(imgs) >= PYRAMID_MIN_JOBS
     total = 0
     for img, rep in zip(imgs, reports):
         H, W = img.shape[:2]
-        total += 4 * W * H + model(W, H, rep, len(imgs) >= PYRAMID_MIN_JOBS)
+        total += 4 * W * H + model(W, H, rep, pyramid)
     return float(total)
 
 
@@ -405,8 +409,8 @@ def main():
         _, reps = ctx.segment_batch(rgbs, p, labels=labels, report=True)
     ms_step = dt * 1e3 / args.steps
     avg_refine = sum(refine_ms) / len(refine_ms)
-    alg = refine_alg_bytes(imgs, reps)
-    alg_w = refine_alg_bytes(imgs, reps, stage_bytes_window)
+    alg = refine_alg_bytes(imgs, reps, pyramid=bool(tm["pyramid"]))
+    alg_w = refine_alg_bytes(imgs, reps, stage_bytes_window, pyramid=bool(tm["pyramid"]))
     achieved = alg / (avg_refine * 1e-3) / 1e9
     src_hash = kernel_source_hash()
     traffic = profile_traffic(kname, args.workload + ("_merge" if args.merge else ""), src_hash)
@@ -544,7 +548,9 @@ def bench_gated(args, ctx, rgb, labels, plain, W, H, dt_plain):
 
         def report_run(th):
             _, reps, _, g = ctx.segment_gated([rgb], pg, w, th, labels=[labels], report=True)
-            return refine_alg_bytes([rgb], reps), refine_alg_bytes([rgb], reps, stage_bytes_window), g
+            py = bool(ctx.last_timings()["pyramid"])
+            return (refine_alg_bytes([rgb], reps, pyramid=py), refine_alg_bytes([rgb], reps, stage_bytes_window,
+                                                                                 pyramid=py), g)
     hold = [synth_gpu.he_slide(2048, 2048, seed=7100 + i, background=0.4, device="cuda") for i in range(4)]
     crops = [(0, 0)] if not slide else [(1000, 3000), (9000, 17000), (20000, 7000), (28000, 28000)]
     measured = {}
@@ -819,7 +825,9 @@ def bench_he(args):
         alg, alg_w = tiles_alg_bytes(W, H, lay, reps), tiles_alg_bytes(W, H, lay, reps, stage_bytes_window)
     else:
         _, r = ctx.segment(rgb, p, labels=labels, report=True)
-        alg, alg_w = refine_alg_bytes([rgb], [r]), refine_alg_bytes([rgb], [r], stage_bytes_window)
+        py = bool(tm["pyramid"])
+        alg = refine_alg_bytes([rgb], [r], pyramid=py)
+        alg_w = refine_alg_bytes([rgb], [r], stage_bytes_window, pyramid=py)
     traffic = profile_traffic(kname, args.workload + ("_grain%d" % args.grain if args.grain > 1 else ""),
                               kernel_source_hash())
     out = {
