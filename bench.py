@@ -146,6 +146,18 @@ def host_cpu() -> str:
     return "unknown"
 
 
+def device_facts() -> dict:
+    """The GPU the line was measured on, as the runtime reports it."""
+    import torch
+    pr = torch.cuda.get_device_properties(0)
+    out = {"name": pr.name, "arch": getattr(pr, "gcnArchName", ""), "compute_units": pr.multi_processor_count,
+           "memory_gib": round(pr.total_memory / 2 ** 30, 1)}
+    l2 = getattr(pr, "L2_cache_size", None)
+    if l2:
+        out["l2_mib"] = round(l2 / 2 ** 20, 1)
+    return out
+
+
 def profile_traffic(kernel: str, wl: str, src_hash: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary,
     or None when absent or taken on other kernel sources."""
@@ -471,6 +483,7 @@ def main():
             print("bench: timing the CPU oracle on all host cores", file=sys.stderr, flush=True)
             out["cpu_baseline"]["multicore"] = cpu_baseline_multicore(p)
     ctx.close()
+    out["device"] = device_facts()
     print(json.dumps(out), flush=True)
 
 
@@ -770,6 +783,7 @@ def bench_roi(args):
                         "held-out tiles; the paper reports precision 0.816 and F1 0.898 on NLST (context only)"},
     }
     ctx.close()
+    out["device"] = device_facts()
     print(json.dumps(out), flush=True)
 
 
@@ -852,6 +866,7 @@ def bench_he(args):
         else:
             out["cpu_baseline"] = cpu_baseline([rgb.cpu().numpy()], p, 1)
     ctx.close()
+    out["device"] = device_facts()
     print(json.dumps(out), flush=True)
 
 
