@@ -33,10 +33,18 @@ METRIC = "MPixel/s segmented (all levels) at 1 MI355X, gated vs plain, % HBM pea
 
 
 def kernel_source_hash() -> str:
+    """Hash of the device code the profiles were taken on: the kernel
+    sources with comments, trailing blanks and empty lines removed, so that
+    a change of wording leaves the figures valid and a change of code does
+    not."""
     h = hashlib.sha256()
     for f in ("rapid_kernels.hip", "rapid_internal.h", "rapid_gate_dev.h"):
-        with open(os.path.join(ROOT, "paper_1704_02083_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1704_02083_amd", "csrc", f), encoding="utf-8") as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        lines = [l.rstrip() for l in src.split("\n")]
+        h.update("\n".join(l for l in lines if l).encode())
     return h.hexdigest()[:16]
 
 

@@ -301,11 +301,12 @@ __device__ __forceinline__ void wg_sync()
     __syncthreads();
 }
 
-// Whole-map passes of one workgroup (pyramid, stage split, output) take
-// several elements per lane and pass and issue all their loads before using
-// any: one element per lane and pass would wait for one memory round trip
-// per element.
-constexpr int OUT_UNROLL = 4;     // output pixels per lane and pass
+// Passes of one workgroup over many elements (the pyramid, a stage split,
+// the output, the gate point's band copy, a frontier rebuild) take several
+// elements per lane and pass and issue all their loads before using any:
+// one element per lane and pass would wait for one memory round trip per
+// element.
+constexpr int OUT_UNROLL = 4;     // output pixels (or band words) per lane and pass
 constexpr int SPLIT_UNROLL = 4;   // parent blocks per lane and pass of a stage split
 constexpr int SUMS_UNROLL = 2;    // 2x2 blocks per lane and pass of the pyramid's finest stage
 constexpr int FRONT_UNROLL = 2;   // neighbourhood blocks per lane and pass of a frontier rebuild
