@@ -118,3 +118,60 @@ def test_random_configuration_cooperative(gpu_lib, seed, large):
             os.environ.pop("RAPID_SHAPE", None)
         else:
             os.environ["RAPID_SHAPE"] = old
+
+
+def _fused_case(seed):
+    """A random H&E crop, grid, schedule, gate level and rule for the fused
+    gate (the network decides the bits inside the refinement launch)."""
+    rng = np.random.default_rng(777 + seed)
+    for _ in range(50):
+        W, H = int(rng.integers(200, 1100)), int(rng.integers(200, 900))
+        K = int(rng.integers(48, 3500))
+        levels = [params.THREE_LEVEL, params.GATED_LEVELS][int(rng.integers(2))]
+        p = params.default_params(W, H, K, levels=levels, gate_level=int(rng.integers(1, len(levels))))
+        p["gate_rule"] = ["either", "both", "differ"][int(rng.integers(3))]
+        img = synth.he_tile(W, H, seed=900 + seed)
+        try:
+            oracle.segment(img, dict(p, gate_level=-1))   # refuses infeasible grids and parameters
+        except (RuntimeError, ValueError):
+            continue
+        return rng, W, H, p, img
+    pytest.skip("no feasible case drawn")
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_fused_gate(gpu_lib, seed):
+    """The fused gate on random H&E crops: a random network (He init, bf16),
+    its threshold at a random quantile of its logits, a random launch shape
+    (workgroup size, residency, pyramid placement); labels and stage reports
+    against the oracle run under the GPU's own gate bits."""
+    import torch
+    from oracle import mlp
+    rng, W, H, p, img = _fused_case(seed)
+    theta = mlp.he_init(int(rng.integers(1000))).astype(np.float32)
+    wb = torch.from_numpy(mlp.to_bf16_bits(theta).view(np.int16)).cuda()
+    shape = "%d,%d,%d" % (int(rng.choice([256, 512, 1024])), int(rng.integers(0, 4)), int(rng.integers(0, 2)))
+    old = os.environ.get("RAPID_SHAPE")
+    os.environ["RAPID_SHAPE"] = shape
+    try:
+        c = gpu_lib.Context(0)
+    finally:
+        if old is None:
+            os.environ.pop("RAPID_SHAPE", None)
+        else:
+            os.environ["RAPID_SHAPE"] = old
+    try:
+        rgb = torch.from_numpy(img).cuda()
+        _, _, X, _ = c.segment_gated([rgb], p, wb, 1e9, features=True, report=False)
+        z, _ = mlp.forward(theta.astype(np.float64), X.cpu().numpy().astype(np.float64), bf16=True)
+        thresh = float(np.quantile(z, rng.uniform(0.2, 0.8)))
+        print("case: fused seed %d %dx%d levels %d gate level %d rule %s shape %s" % (
+            seed, W, H, len(p["levels"]), p["gate_level"], p["gate_rule"], shape), flush=True)
+        labs, reps, _, g = c.segment_gated([rgb], p, wb, thresh)
+        torch.cuda.synchronize()
+        gb = g.cpu().numpy()
+        ref, _, ref_rep = oracle.segment(img, p, gate=gb)
+        assert (labs[0].cpu().numpy() == ref).all()
+        assert reps[0] == ref_rep
+    finally:
+        c.close()
